@@ -1,0 +1,229 @@
+"""Throughput of the MOND particle-mesh step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload isothermal]
+                    [--no-cpu-baseline]
+
+Runs W untimed and K timed PM steps (deposit, AQUAL solve with 4 iterations,
+gather, kick and drift) through the C ABI on the default workload: the
+self-consistent isothermal sphere of 2^20 equal masses on a 256^3 grid in a
+512^3 periodic FFT box (standard interpolation, sigma = 1 cell).  Inputs are
+resident in HBM before the timed region.  Prints one JSON line.
+
+The line carries a roofline record for the kernel with the largest share of
+the step (its launch durations come from HIP events recorded around every
+launch on the library's stream during the timed steps) and a CPU baseline:
+the FP64 oracle timed on a bounded sample of the same workload on the host
+cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "PM steps/s at 256³ grid, 2^20 particles; learned vs plain solve time at 1e-5 res"
+HBM_PEAK_GBS = 8000.0
+
+
+def make_workload(name):
+    import workloads as W
+    if name == "isothermal":
+        return W.isothermal_sphere(seed=0)
+    if name == "ring":
+        return W.ring(seed=0)
+    if name == "two_body":
+        return W.two_body()
+    if name == "plummer512":
+        return W.plummer_mixture(seed=0)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def pass_bytes(N, K):
+    """Algorithmic HBM bytes per step of each timed kernel kind, and launches per step.
+
+    One complex spectrum component holds N * N * (N/2 + 1) valid entries of 8
+    bytes (C1); a real grid holds N^3 floats (R1).  Each pass reads its input
+    once and writes its output once.  The launch sequence is the one of one
+    fixed-K solve: Newton (x, y, z, y), then per iteration x(nu), y, z(curl),
+    y, x(mu), y, z(div), y, and in the last iteration x(nu), y, z(final).
+    """
+    C1 = N * N * (N // 2 + 1) * 8
+    R1 = N ** 3 * 4
+    b = {}
+    b["x_fwd_real"] = (R1 + C1, 1)
+    b["x_inv_real"] = (C1 + R1, 1)
+    b["x_nu"] = (K * 6 * C1, K)
+    b["x_mu"] = ((K - 1) * 6 * C1, K - 1)
+    b["y_fwd"] = (2 * C1 + (2 * (K - 1) + 1) * 6 * C1, 2 * (K - 1) + 2)
+    b["y_inv"] = (6 * C1 + 2 * (K - 1) * 6 * C1 + 2 * C1, 2 * (K - 1) + 2)
+    b["z_newton"] = (C1 + C1 + 3 * C1, 1)
+    b["z_curl"] = ((K - 1) * 6 * C1, K - 1)
+    b["z_div"] = ((K - 1) * 7 * C1, K - 1)
+    b["z_curl_final"] = (3 * C1 + C1, 1)
+    b["fill"] = (R1, 1)
+    return b
+
+
+def cpu_baseline(w, n_sample=4096):
+    """FP64 oracle on a bounded sample of the workload, scaled to one step.
+
+    Sample: the oracle's deposit and its gather + push on n_sample and on
+    2 n_sample of the particles (a fixed part and a per-particle slope are
+    fitted from the two and evaluated at N), its Newton solve on the full
+    FFT box, and one full AQUAL iteration on the full box (nu, 3 FFTs,
+    curl-free projection, 3 inverse FFTs, mu, 3 FFTs, divergence-free
+    projection, 3 inverse FFTs).  A K-iteration step is the deposit, the
+    Newton solve, K - 1 full iterations, a last one of nu, 3 FFTs, the
+    projection and the inverse FFT of phi (timed as well), and the gather.
+    """
+    import numpy as np
+    from oracle import pm as orc
+    p = orc.Params.from_dict(w["params"])
+    N = len(w["mass"])
+    pos = w["pos"].astype(np.float64)
+    mass = w["mass"].astype(np.float64)
+    vel = w["vel"].astype(np.float64)
+    idx = np.random.default_rng(0).choice(N, 2 * n_sample, replace=False)
+
+    def timed(f):
+        t0 = time.perf_counter()
+        r = f()
+        return time.perf_counter() - t0, r
+
+    def fit(t1, t2):
+        slope = max(t2 - t1, 0.0) / n_sample
+        return max(t1 - slope * n_sample, 0.0) + slope * N
+
+    d1, _ = timed(lambda: orc.deposit(p, pos[idx[:n_sample]], mass[idx[:n_sample]]))
+    d2, rho = timed(lambda: orc.deposit(p, pos[idx], mass[idx] * (N / (2 * n_sample))))
+    t_dep = fit(d1, d2)
+    t_newton, (_, gN) = timed(lambda: orc.newton_potential(p, rho))
+    del rho
+    t0 = time.perf_counter()
+    gM = orc.apply_nu(p, gN)
+    gh, phih = orc.project_curl_free(p, np.stack([orc.fft3(gM[c]) for c in range(3)]))
+    t_last_a = time.perf_counter() - t0
+    t_last_b, phi = timed(lambda: orc.ifft3_real(phih))
+    t0 = time.perf_counter()
+    gM = np.stack([orc.ifft3_real(gh[c]) for c in range(3)])
+    del gh
+    Fp = orc.apply_mu(p, gM)
+    del gM
+    Hh = orc.project_div_free(p, np.stack([orc.fft3((Fp - gN)[c]) for c in range(3)]))
+    del Fp
+    H = np.stack([orc.ifft3_real(Hh[c]) for c in range(3)])
+    del Hh
+    F = gN + H
+    t_rest = time.perf_counter() - t0
+    del H, F, gN
+    g1, _ = timed(lambda: orc.interp_push(p, phi, pos[idx[:n_sample]], vel[idx[:n_sample]], 0.1, 0.1))
+    g2, _ = timed(lambda: orc.interp_push(p, phi, pos[idx], vel[idx], 0.1, 0.1))
+    t_gat = fit(g1, g2)
+    K = p.iters
+    t_iter = t_last_a + t_rest
+    t_step = t_dep + t_gat + t_newton + (K - 1) * t_iter + t_last_a + t_last_b
+    cores = orc.WORKERS
+    return {"value": 1.0 / t_step, "unit": "PM steps/s", "cores": cores, "kind": "oracle",
+            "sample": (f"FP64 oracle (scipy.fft, {cores} workers): deposit and gather+push of "
+                       f"{n_sample} and {2 * n_sample} of {N} particles (fixed + per-particle cost "
+                       f"fitted, evaluated at N), Newton solve and one full AQUAL iteration on the "
+                       f"full {p.n_pad}^3 box; step = deposit + Newton + {K - 1} iterations + last "
+                       f"iteration + gather; measured s: deposit {t_dep:.1f}, gather {t_gat:.1f}, "
+                       f"newton {t_newton:.1f}, iteration {t_iter:.1f}, step {t_step:.1f}")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="isothermal")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--timing", action="store_true", help="print per-kernel timing table to stderr")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the path has no multi-GPU "
+              "code, see the sharding note in the design document", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2312_02968_amd import mondpm as M
+
+    w = make_workload(a.workload)
+    p = w["params"]
+    N_part = len(w["mass"])
+    dt = float(w["dt"])
+    torch.cuda.init()
+    ctx = M.pm_create(p, N_part)
+    pos = torch.from_numpy(w["pos"]).cuda()
+    vel = torch.from_numpy(w["vel"]).cuda()
+    mass = torch.from_numpy(w["mass"]).cuda()
+    for _ in range(a.warmup):
+        M.pm_step(ctx, pos, vel, mass, dt)
+    torch.cuda.synchronize()
+    M.pm_read_timing(ctx)
+    M.pm_set_timing(ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        M.pm_step(ctx, pos, vel, mass, dt)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    timing = M.pm_read_timing(ctx)
+    M.pm_set_timing(ctx, False)
+    ms_step = (t1 - t0) * 1e3 / a.steps
+
+    Npad = p["n_pad"]
+    K = p["iters"]
+    pb = pass_bytes(Npad, K)
+    dom = max((k for k in timing if k in pb), key=lambda k: timing[k][0])
+    tot_ms, launches = timing[dom]
+    bytes_step, launches_step = pb[dom]
+    avg_ms = tot_ms / launches
+    bytes_launch = bytes_step / launches_step
+    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+    if a.timing:
+        for k, (t, c) in sorted(timing.items(), key=lambda kv: -kv[1][0]):
+            extra = ""
+            if k in pb:
+                bb = pb[k][0] / pb[k][1]
+                extra = f"  {bb / 1e9:.3f} GB/launch  {bb / (t / c * 1e-3) / 1e9:.0f} GB/s"
+            print(f"{k:14s} {t / a.steps:8.3f} ms/step  {c // a.steps:3d} launches/step  "
+                  f"{t / c:8.4f} ms/launch{extra}", file=sys.stderr)
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+            "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": int(bytes_launch)}
+    out = {
+        "metric": METRIC,
+        "value": round(1e3 / ms_step, 3),
+        "unit": "PM steps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w["workload"], "grid": p["n"], "fft_box": Npad, "particles": N_part,
+                   "iterations": K, "sigma_cells": p["sigma"], "mu": "standard" if p["mu"] == 0 else
+                   ("deep" if p["mu"] == 1 else "newton"), "dt": dt},
+        "particle_updates_per_s": round(N_part * 1e3 / ms_step, 1),
+        "roofline": roof,
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,185 @@
+/*
+ * mondpm.h -- C ABI of the MI355X particle-mesh step for AQUAL MOND.
+ *
+ * One PM step of Visser, Eijt & de Nijs, "Fast particle-mesh code for
+ * Milgromian dynamics" (A&A 2023): Gaussian mass deposition (Eq. smooth),
+ * the FFT-based fixed-point solve of the AQUAL equation (Sect. 2.1 and the
+ * appendix "Flow scheme of the PM code"), kernel-smoothed forces (Eq. gi)
+ * and leapfrog (Eq. motion).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Device pointers are HIP device memory owned by the caller; the library
+ *    never frees them.  Host pointers are marked "host".
+ *  - Every call is enqueued on the stream given to pm_create and returns
+ *    without waiting, except where "synchronises" is stated.  A context is
+ *    not thread safe; use one context per stream.
+ *  - Lengths are in the caller's units; the pixel width is s = box / n.
+ *    Positions are measured from the centre of the FFT box (appendix
+ *    "Fourier transforms"): grid index j on an axis is the point
+ *    (j - n_pad/2) s.  Grids are [z][y][x] with x fastest.
+ *  - Particle arrays: pos and vel are float [N][3] (x, y, z), mass is
+ *    float [N].  N may be 0 (the call then does nothing but clears outputs).
+ *  - Errors: argument errors return PM_E_INVAL at once and enqueue nothing;
+ *    HIP runtime failures return PM_E_DEVICE.  Conditions found on the
+ *    device (a kernel ball leaving the physical region, a non-finite
+ *    residual, no convergence) are reported in the info structures filled
+ *    by the calls that take one; those calls synchronise the stream.
+ *    Nothing aborts and nothing throws across this interface.
+ */
+#ifndef MONDPM_H
+#define MONDPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Interpolation function mu (Eq. PDE).  STANDARD: mu(x) = x / sqrt(1+x^2)
+ * (Eq. mu) with its inverse nu printed in Sect. 2.1.  DEEP: mu(x) = x,
+ * nu(y) = 1/sqrt(y) (Sect. 4).  NEWTON: mu = nu = 1, the high-acceleration
+ * limit, in which the solve reduces to a Poisson solve. */
+typedef enum { PM_MU_STANDARD = 0, PM_MU_DEEP = 1, PM_MU_NEWTON = 2 } pm_mu;
+
+typedef enum {
+  PM_OK = 0,
+  PM_E_INVAL = -1,      /* bad argument; nothing was enqueued               */
+  PM_E_DEVICE = -2,     /* a HIP runtime call failed                         */
+  PM_E_NOMEM = -3,      /* device allocation failed in pm_create             */
+  PM_E_BOUNDS = -4,     /* warning: a particle's ball left the physical n^3
+                           region; it was computed with indices wrapped
+                           modulo n_pad                                      */
+  PM_E_NOTCONV = -5,    /* warning: tol > 0 and the residual did not reach it
+                           within iters iterations                           */
+  PM_E_NONFINITE = -6   /* a residual was NaN or Inf                         */
+} pm_status;
+
+/* Flags (pm_params.flags). */
+#define PM_F_ANALYTIC_NORM 0x1u /* literal Gaussian prefactor 1/((2pi)^1.5 sigma^3)
+                                   of Eq. smooth instead of dividing by the
+                                   FP64 sum of the weights over the ball      */
+#define PM_F_RESIDUAL      0x2u /* compute r_k every iteration in fixed-K mode
+                                   (always on when tol > 0)                   */
+
+/* Statement of the problem (Sect. 2, Sect. 3 and the table of symbols). */
+typedef struct {
+  int32_t  n;        /* physical cells per axis, power of two, 8..512          */
+  int32_t  n_pad;    /* FFT box cells per axis, power of two, n..1024;
+                        2n leaves the empty margin Sect. 3 asks for           */
+  double   box;      /* side of the physical grid; s = box / n               */
+  double   G;        /* Newton's constant                                    */
+  double   a0;       /* Milgrom's acceleration scale (> 0)                    */
+  int32_t  mu;       /* pm_mu                                                */
+  double   sigma;    /* Gaussian kernel std in cells (paper: 1), 0.5..2.5    */
+  double   cutoff;   /* ball radius in units of sigma, strict |d| < cutoff*sigma
+                        (paper: 4, giving 251 cells at sigma = 1)            */
+  int32_t  iters;    /* K: evaluations of nu per solve (paper: 4), 1..64     */
+  double   tol;      /* 0: exactly K iterations.  > 0: stop at iteration k
+                        once r_{k-1} <= tol (K is the maximum)               */
+  uint32_t flags;    /* PM_F_*                                               */
+} pm_params;
+
+/* Residual history of one solve.  r_k = ||H_k - H_{k-1}||_2 / ||g_N||_2 over
+ * the whole n_pad^3 box, accumulated in FP64 (the paper estimates the error
+ * from the change of H, Sect. 2.1). */
+typedef struct {
+  int32_t iterations;      /* evaluations of nu performed                     */
+  int32_t status;          /* PM_OK, PM_E_NOTCONV or PM_E_NONFINITE           */
+  int32_t n_residuals;     /* entries of residual[] that are valid            */
+  int32_t bounds_flag;     /* 1 if a deposited ball left the physical region  */
+  double  residual[64];    /* r_1 .. r_{n_residuals}                          */
+  double  gN_norm;         /* ||g_N||_2 over the box                          */
+} pm_solve_info;
+
+typedef struct pm_ctx pm_ctx;
+
+/* Bytes of device memory pm_create allocates for these parameters (the
+ * spectra, the Newton potential's spectrum, two real grids, sort buffers
+ * for max_particles particles and, with PM_F_RESIDUAL or tol > 0, the
+ * previous iterate of F). */
+size_t pm_workspace_bytes(const pm_params* p, int64_t max_particles);
+
+/* Validates p (host), allocates the workspace on the current HIP device and
+ * builds the tables (twiddles, wavevectors, ball offsets).  stream is a
+ * hipStream_t (NULL = the default stream).  Synchronises.  On success *out
+ * owns the device memory until pm_destroy. */
+pm_status pm_create(const pm_params* p, int64_t max_particles, void* stream, pm_ctx** out);
+pm_status pm_destroy(pm_ctx* ctx);
+
+/* Mass density of Eq. smooth on the FFT box.  rho: device float [n_pad^3],
+ * overwritten.  Each particle adds m_i w_id / s^3 to the cells c_i + d of its
+ * ball (central pixel c_i = floor(x_i/s + 1/2) per axis), with w the Gaussian
+ * weights normalised by their FP64 sum over the ball (or the literal prefactor
+ * with PM_F_ANALYTIC_NORM).  Cell sums use atomic adds, so the rounding
+ * order (and the last bits) vary from run to run.  N <= max_particles. */
+pm_status pm_deposit(pm_ctx* ctx, const float* pos, const float* mass, int64_t N, float* rho);
+
+/* MOND potential phi from rho by the fixed-point iteration of Sect. 2.1:
+ * Newton field g_N from rho (-4 pi G A rho_hat, finite-difference gradient),
+ * H = H0 (or 0), then K times: F = g_N + H, g_M = nu(|F|/a0) F, curl-free
+ * projection in Fourier space, and (except after the K-th) F' = mu(|g_M|/a0)
+ * g_M, H = divergence-free part of F' - g_N.  phi comes from the last
+ * projection.  rho: device float [n_pad^3] (read); H0: device float
+ * [3][n_pad^3] or NULL; phi: device float [n_pad^3] (written).  rho and phi
+ * may be the same buffer.  info (host) may be NULL; when given, or when
+ * tol > 0, the call synchronises and fills it. */
+pm_status aqual_solve(pm_ctx* ctx, const float* rho, const float* H0, float* phi,
+                      pm_solve_info* info);
+
+/* Kernel-smoothed acceleration of Eq. gi: g_i = -sum_d w_id (D phi)(c_i + d)
+ * with D the central-difference gradient and the same weights as pm_deposit.
+ * phi: device float [n_pad^3]; acc: device float [N][3] (written). */
+pm_status smooth_accel(pm_ctx* ctx, const float* phi, const float* pos, int64_t N, float* acc);
+
+/* Gather plus leapfrog (Eq. motion): v <- v + g_i dt_kick, then
+ * r <- r + v dt_drift, in place.  With v half a step behind r, the initial
+ * half step is interp_push(dt_kick = -dt/2, dt_drift = 0). */
+pm_status interp_push(pm_ctx* ctx, const float* phi, float* pos, float* vel, int64_t N,
+                      double dt_kick, double dt_drift);
+
+/* One PM step: deposit at r, solve, kick by dt, drift by dt (pos, vel in
+ * place; the flow scheme's alternation with one fixed phase).  info may be
+ * NULL (then nothing synchronises in fixed-K mode). */
+pm_status pm_step(pm_ctx* ctx, float* pos, float* vel, const float* mass, int64_t N,
+                  double dt, pm_solve_info* info);
+
+/* FP64 diagnostics (constants of motion of Sect. 4.1): out (host) receives
+ * 10 doubles: P (3), L (3), E_kin, total mass, and, if phi is not NULL,
+ * sum_i m_i phi_i with phi smoothed by the particle kernel (else 0), and the
+ * number of particles whose ball leaves the physical region.  Synchronises. */
+pm_status pm_diagnostics(pm_ctx* ctx, const float* pos, const float* vel, const float* mass,
+                         int64_t N, const float* phi, double* out);
+
+/* 3D real transforms of the FFT box used inside aqual_solve, exposed for
+ * testing.  Spectrum layout: complex (float2) [n_pad][n_pad][pitch] indexed
+ * [kz][ky][kx] with kx = 0..n_pad/2 valid and pitch = pm_spectrum_pitch(n_pad)
+ * complex entries per row.  Unnormalised in both directions: c2r(r2c(f)) =
+ * n_pad^3 f.  in and out must not overlap. */
+int32_t   pm_spectrum_pitch(int32_t n_pad);
+pm_status pm_fft_r2c(pm_ctx* ctx, const float* in, void* spectrum_out);
+pm_status pm_fft_c2r(pm_ctx* ctx, const void* spectrum_in, float* out);
+
+/* Per-kernel timing with HIP events on the context's stream.  Timer ids:
+ * one per pass kind of the 3D transforms and per particle kernel. */
+enum {
+  PM_T_X_FWD_REAL = 0, PM_T_X_FWD_REAL3, PM_T_X_INV_REAL, PM_T_X_NU, PM_T_X_MU,
+  PM_T_Y_FWD, PM_T_Y_INV, PM_T_Z_FWD, PM_T_Z_INV, PM_T_Z_NEWTON, PM_T_Z_CURL,
+  PM_T_Z_CURL_FINAL, PM_T_Z_DIV, PM_T_SORT, PM_T_DEPOSIT, PM_T_GATHER, PM_T_FILL,
+  PM_T_REDUCE, PM_NUM_TIMERS
+};
+/* enable != 0 records an event pair around every launch from now on (host). */
+pm_status pm_set_timing(pm_ctx* ctx, int enable);
+/* Synchronises; adds the elapsed milliseconds and launch counts recorded since
+ * the last read into total_ms[PM_NUM_TIMERS] and launches[PM_NUM_TIMERS]
+ * (host arrays the caller zeroes), then forgets them. */
+pm_status pm_read_timing(pm_ctx* ctx, double* total_ms, int64_t* launches);
+
+/* Last HIP error string seen by the library (host, static storage). */
+const char* pm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MONDPM_H */

@@ -1,0 +1,572 @@
+// C ABI of the PM step (declared in include/mondpm.h): context, tables, and
+// the host-side orchestration of the passes of one AQUAL solve.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <vector>
+
+#include "../../include/mondpm.h"
+#include "pm_internal.h"
+
+using namespace pm;
+
+static thread_local char g_err[512] = "";
+
+static pm_status dev_fail(hipError_t e, const char* where) {
+  snprintf(g_err, sizeof g_err, "%s: %s", where, hipGetErrorString(e));
+  return PM_E_DEVICE;
+}
+static pm_status inval(const char* msg) {
+  snprintf(g_err, sizeof g_err, "invalid argument: %s", msg);
+  return PM_E_INVAL;
+}
+
+#define HIPCHK(call)                                        \
+  do {                                                      \
+    hipError_t e_ = (call);                                 \
+    if (e_ != hipSuccess) return dev_fail(e_, #call);       \
+  } while (0)
+
+struct pm_ctx {
+  pm_params p;
+  int N = 0, n = 0, P = 0;
+  hipStream_t st = nullptr;
+  int64_t max_particles = 0;
+  float2* spec = nullptr;     // three spectra
+  float2* phiN = nullptr;     // Newton potential spectrum
+  float* rho = nullptr;       // internal real grids of pm_step
+  float* phi = nullptr;
+  float* fprev = nullptr;     // previous F for the residual (optional)
+  double* partials = nullptr;
+  double* dacc = nullptr;     // [0] |g_N|^2 sum, [1..64] residual sums, [80..89] diagnostics
+  double* hacc = nullptr;     // pinned host copy of dacc
+  float2* tw = nullptr;
+  float* kv = nullptr;
+  float* kt = nullptr;
+  float* kap = nullptr;
+  int* ball = nullptr;
+  int* ibuf = nullptr;        // sort buffers
+  std::vector<void*> allocs;
+  FftGeom fg{};
+  KernelGeom kg{};
+  SortBufs sb{};
+  int npartials = 0;
+  // event timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<int> ev_kind;   // timer id per recorded pair
+  size_t ev_used = 0;
+};
+
+// Records an event pair around one launch when timing is on.
+struct Timed {
+  pm_ctx* c;
+  int kind;
+  size_t slot;
+  bool on;
+  Timed(pm_ctx* c_, int kind_) : c(c_), kind(kind_), slot(0), on(c_->timing) {
+    if (!on) return;
+    if (c->ev_used + 2 > c->ev_pool.size()) {
+      for (int i = 0; i < 256; ++i) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) { on = false; return; }
+        c->ev_pool.push_back(e);
+      }
+      c->ev_kind.resize(c->ev_pool.size() / 2);
+    }
+    slot = c->ev_used;
+    c->ev_used += 2;
+    c->ev_kind[slot / 2] = kind;
+    (void)hipEventRecord(c->ev_pool[slot], c->st);
+  }
+  ~Timed() {
+    if (on) (void)hipEventRecord(c->ev_pool[slot + 1], c->st);
+  }
+};
+
+static int timer_of(PassKind k) {
+  switch (k) {
+    case PASS_X_FWD_REAL: return PM_T_X_FWD_REAL;
+    case PASS_X_FWD_REAL3: return PM_T_X_FWD_REAL3;
+    case PASS_X_INV_REAL: return PM_T_X_INV_REAL;
+    case PASS_X_NU: return PM_T_X_NU;
+    case PASS_X_MU: return PM_T_X_MU;
+    case PASS_Y_FWD: return PM_T_Y_FWD;
+    case PASS_Y_INV: return PM_T_Y_INV;
+    case PASS_Z_FWD: return PM_T_Z_FWD;
+    case PASS_Z_INV: return PM_T_Z_INV;
+    case PASS_Z_NEWTON: return PM_T_Z_NEWTON;
+    case PASS_Z_CURL: return PM_T_Z_CURL;
+    case PASS_Z_CURL_FINAL: return PM_T_Z_CURL_FINAL;
+    case PASS_Z_DIV: return PM_T_Z_DIV;
+  }
+  return PM_T_REDUCE;
+}
+
+static bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int32_t pm_spectrum_pitch(int32_t n_pad) {
+  const int need = n_pad / 2 + 1;
+  return (need + 15) & ~15;
+}
+
+static pm_status check_params(const pm_params* p) {
+  if (!p) return inval("params is NULL");
+  if (!pow2(p->n_pad) || p->n_pad < 16 || p->n_pad > 1024) return inval("n_pad must be a power of two in [16, 1024]");
+  if (!pow2(p->n) || p->n < 8 || p->n > p->n_pad) return inval("n must be a power of two in [8, n_pad]");
+  if (!(p->box > 0.0) || !isfinite(p->box)) return inval("box must be > 0");
+  if (!isfinite(p->G)) return inval("G must be finite");
+  if (p->mu != PM_MU_STANDARD && p->mu != PM_MU_DEEP && p->mu != PM_MU_NEWTON) return inval("unknown mu");
+  if (p->mu != PM_MU_NEWTON && !(p->a0 > 0.0)) return inval("a0 must be > 0");
+  if (!(p->sigma > 0.0) || !(p->cutoff > 0.0)) return inval("sigma and cutoff must be > 0");
+  const double R = p->cutoff * p->sigma;
+  if (R > 10.0) return inval("cutoff * sigma must be <= 10 cells");
+  if (p->iters < 1 || p->iters > 64) return inval("iters must be in [1, 64]");
+  if (!(p->tol >= 0.0)) return inval("tol must be >= 0");
+  return PM_OK;
+}
+
+static int ball_extent(double R) { return (int)ceil(R) - 1; }
+
+static std::vector<int> make_ball(double R) {
+  std::vector<int> out;
+  const int m = (int)floor(R);
+  for (int dz = -m; dz <= m; ++dz)
+    for (int dy = -m; dy <= m; ++dy)
+      for (int dx = -m; dx <= m; ++dx)
+        if ((double)(dx * dx + dy * dy + dz * dz) < R * R)
+          out.push_back((dx + 16) | ((dy + 16) << 8) | ((dz + 16) << 16));
+  return out;
+}
+
+static bool need_residual(const pm_params& p) { return (p.flags & PM_F_RESIDUAL) || p.tol > 0.0; }
+
+size_t pm_workspace_bytes(const pm_params* p, int64_t max_particles) {
+  if (check_params(p) != PM_OK || max_particles < 0) return 0;
+  const size_t N = p->n_pad, P = pm_spectrum_pitch(p->n_pad);
+  const size_t C = N * N * P * sizeof(float2), R = N * N * N * sizeof(float);
+  size_t b = 4 * C + 2 * R;
+  if (need_residual(*p)) b += 3 * R;
+  const size_t ntiles = (N / 8) * (N / 8) * (N / 8);
+  b += (size_t)max_particles * 4 * sizeof(int) + (2 * (ntiles + 1) + 4096 + 16) * sizeof(int);
+  return b;
+}
+
+const char* pm_last_error(void) { return g_err; }
+
+template <typename T>
+static pm_status dalloc(pm_ctx* c, T** ptr, size_t count) {
+  void* v = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc(&v, count * sizeof(T));
+  if (e != hipSuccess) {
+    snprintf(g_err, sizeof g_err, "hipMalloc(%zu bytes): %s", count * sizeof(T), hipGetErrorString(e));
+    return PM_E_NOMEM;
+  }
+  c->allocs.push_back(v);
+  *ptr = static_cast<T*>(v);
+  return PM_OK;
+}
+
+pm_status pm_destroy(pm_ctx* c) {
+  if (!c) return PM_OK;
+  (void)(c->st ? hipStreamSynchronize(c->st) : hipDeviceSynchronize());
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  for (void* v : c->allocs) (void)hipFree(v);
+  if (c->hacc) (void)hipHostFree(c->hacc);
+  delete c;
+  return PM_OK;
+}
+
+pm_status pm_create(const pm_params* p, int64_t max_particles, void* stream, pm_ctx** out) {
+  if (!out) return inval("out is NULL");
+  *out = nullptr;
+  pm_status s = check_params(p);
+  if (s != PM_OK) return s;
+  if (max_particles < 0 || max_particles > (int64_t)1 << 31) return inval("max_particles out of range");
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, dev));
+
+  pm_ctx* c = new pm_ctx();
+  c->p = *p;
+  c->N = p->n_pad;
+  c->n = p->n;
+  c->P = pm_spectrum_pitch(p->n_pad);
+  c->st = static_cast<hipStream_t>(stream);
+  c->max_particles = max_particles;
+  const int N = c->N;
+  const size_t C = (size_t)N * N * c->P, R = (size_t)N * N * N;
+  const double Rb = p->cutoff * p->sigma;
+  std::vector<int> ball = make_ball(Rb);
+  const int ext = ball_extent(Rb);
+  const size_t lds_need = sizeof(float) * (((ball.size() + 3) & ~(size_t)3) + (size_t)(8 + 2 * (ext + 1)) *
+                                                                                   (8 + 2 * (ext + 1)) * (8 + 2 * (ext + 1)));
+  if (lds_need > prop.sharedMemPerBlock) {
+    delete c;
+    return inval("kernel ball too large for the LDS of this device");
+  }
+  const int ntiles = (N / 8) * (N / 8) * (N / 8);
+  c->npartials = x_blocks(N) > z_blocks(N) ? x_blocks(N) : z_blocks(N);
+#define ALLOC(ptr, cnt)                       \
+  do {                                        \
+    pm_status s_ = dalloc(c, &(ptr), (cnt));  \
+    if (s_ != PM_OK) { pm_destroy(c); return s_; } \
+  } while (0)
+  ALLOC(c->spec, 3 * C);
+  ALLOC(c->phiN, C);
+  ALLOC(c->rho, R);
+  ALLOC(c->phi, R);
+  if (need_residual(*p)) ALLOC(c->fprev, 3 * R);
+  ALLOC(c->partials, (size_t)c->npartials);
+  ALLOC(c->dacc, 128);
+  ALLOC(c->tw, (size_t)N);
+  ALLOC(c->kv, (size_t)N);
+  ALLOC(c->kt, (size_t)N);
+  ALLOC(c->kap, (size_t)N);
+  ALLOC(c->ball, ball.size());
+  const size_t mp = (size_t)(max_particles > 0 ? max_particles : 1);
+  const size_t nb = ((size_t)ntiles + 1023) / 1024;
+  ALLOC(c->ibuf, 4 * mp + 2 * ((size_t)ntiles + 1) + nb + 16);
+#undef ALLOC
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->hacc), 128 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    pm_destroy(c);
+    return dev_fail(hipErrorOutOfMemory, "hipHostMalloc");
+  }
+
+  // tables (FP64 on the host, stored in FP32)
+  const double s_px = p->box / p->n;
+  std::vector<float2> tw(N);
+  std::vector<float> kv(N), kt(N), kap(N);
+  for (int t = 0; t < N; ++t) {
+    const double a = 2.0 * M_PI * t / N;
+    tw[t] = make_float2((float)cos(a), (float)-sin(a));
+    const int m = t < N / 2 ? t : t - N;
+    const double k = 2.0 * M_PI * m / (N * s_px);
+    kv[t] = (float)k;
+    kt[t] = (t == N / 2) ? 0.0f : (float)k;
+    kap[t] = (t == 0 || t == N / 2) ? 0.0f : (float)(sin(2.0 * M_PI * m / N) / s_px);
+  }
+  HIPCHK(hipMemcpy(c->tw, tw.data(), N * sizeof(float2), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(c->kv, kv.data(), N * sizeof(float), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(c->kt, kt.data(), N * sizeof(float), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(c->kap, kap.data(), N * sizeof(float), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(c->ball, ball.data(), ball.size() * sizeof(int), hipMemcpyHostToDevice));
+
+  c->fg.N = N;
+  c->fg.P = c->P;
+  c->fg.comp_stride = (long long)C;
+  c->fg.tw = c->tw;
+
+  c->kg.N = N;
+  c->kg.n = p->n;
+  c->kg.s = (float)s_px;
+  c->kg.inv_s = 1.0 / s_px;
+  c->kg.inv2sig2 = (float)(1.0 / (2.0 * p->sigma * p->sigma));
+  c->kg.ext = ext;
+  c->kg.nball = (int)ball.size();
+  c->kg.ball = c->ball;
+  c->kg.analytic = (p->flags & PM_F_ANALYTIC_NORM) ? 1 : 0;
+  c->kg.analytic_norm = pow(2.0 * M_PI, 1.5) * p->sigma * p->sigma * p->sigma;
+
+  int* ib = c->ibuf;
+  c->sb.keys = ib; ib += mp;
+  c->sb.rank = ib; ib += mp;
+  c->sb.perm = ib; ib += mp;
+  c->sb.skey = ib; ib += mp;
+  c->sb.counts = ib; ib += ntiles + 1;
+  c->sb.offsets = ib; ib += ntiles + 1;
+  c->sb.blocksums = ib; ib += nb;
+  c->sb.flags = ib;
+  c->sb.ntiles = ntiles;
+  HIPCHK(hipMemset(c->sb.flags, 0, 16 * sizeof(int)));
+  HIPCHK(hipDeviceSynchronize());
+  *out = c;
+  return PM_OK;
+}
+
+// ----------------------------------------------------------------------------
+// solve
+// ----------------------------------------------------------------------------
+static hipError_t pass(pm_ctx* c, PassDesc d) {
+  Timed t(c, timer_of(d.kind));
+  return fft_pass(c->fg, d, c->st);
+}
+
+static PassDesc pdesc(PassKind k, float2* spec, int ncomp = 1) {
+  PassDesc d;
+  d.kind = k;
+  d.spec = spec;
+  d.ncomp = ncomp;
+  return d;
+}
+
+static ZArgs zargs(pm_ctx* c) {
+  ZArgs z{};
+  z.spec = c->spec;
+  z.phiN = c->phiN;
+  z.kv = c->kv;
+  z.kt = c->kt;
+  z.kap = c->kap;
+  z.newton_coef = (float)(-4.0 * M_PI * c->p.G);
+  const double N = c->N;
+  z.scale = (float)(1.0 / (N * N * N));
+  z.partials = c->partials;
+  z.nc = 1;
+  return z;
+}
+
+static pm_status run_solve(pm_ctx* c, const float* rho, const float* H0, float* phi_out, pm_solve_info* info,
+                           bool want_info) {
+  const pm_params& p = c->p;
+  const int N = c->N;
+  const long long R = (long long)N * N * N;
+  const bool resid = need_residual(p);
+  const int K = p.iters;
+  const float inv_a0 = (p.mu == PM_MU_NEWTON) ? 0.0f : (float)(1.0 / p.a0);
+  const double N3 = (double)N * N * N;
+  pm_solve_info loc{};
+  loc.status = PM_OK;
+
+  // Newton: rho -> (x, y) spectrum in the phiN buffer
+  {
+    PassDesc d = pdesc(PASS_X_FWD_REAL, c->phiN);
+    d.real = const_cast<float*>(rho);
+    HIPCHK(pass(c, d));
+    HIPCHK(pass(c, pdesc(PASS_Y_FWD, c->phiN, 1)));
+  }
+  if (H0) {
+    PassDesc d = pdesc(PASS_X_FWD_REAL3, c->spec);
+    d.real = const_cast<float*>(H0);
+    d.real_cs = R;
+    HIPCHK(pass(c, d));
+    HIPCHK(pass(c, pdesc(PASS_Y_FWD, c->spec, 3)));
+  }
+  {
+    PassDesc d = pdesc(PASS_Z_NEWTON, c->spec);
+    d.z = zargs(c);
+    d.z.with_h0 = H0 ? 1 : 0;
+    HIPCHK(pass(c, d));
+    HIPCHK(reduce_partials(c->partials, z_blocks(N), c->dacc, c->st));
+    HIPCHK(pass(c, pdesc(PASS_Y_INV, c->spec, 3)));
+  }
+  int k_done = 0;
+  for (int k = 1; k <= K; ++k) {
+    {
+      PassDesc d = pdesc(PASS_X_NU, c->spec, 3);
+      d.mu_mode = p.mu;
+      d.inv_a0 = inv_a0;
+      d.fprev = resid ? c->fprev : nullptr;
+      d.partials = c->partials;
+      HIPCHK(pass(c, d));
+    }
+    bool final_it = (k == K);
+    if (resid && k >= 2) {
+      HIPCHK(reduce_partials(c->partials, x_blocks(N), c->dacc + (k - 1), c->st));
+      if (p.tol > 0.0) {
+        HIPCHK(hipMemcpyAsync(c->hacc, c->dacc, 128 * sizeof(double), hipMemcpyDeviceToHost, c->st));
+        HIPCHK(hipStreamSynchronize(c->st));
+        const double gn = sqrt(c->hacc[0] / N3);
+        const double r = gn > 0.0 ? sqrt(c->hacc[k - 1]) / gn : 0.0;
+        if (!isfinite(r)) {
+          loc.status = PM_E_NONFINITE;
+          final_it = true;
+        } else if (r <= p.tol) {
+          final_it = true;
+        }
+      }
+    }
+    k_done = k;
+    HIPCHK(pass(c, pdesc(PASS_Y_FWD, c->spec, 3)));
+    if (final_it) {
+      PassDesc d = pdesc(PASS_Z_CURL_FINAL, c->spec);
+      d.z = zargs(c);
+      HIPCHK(pass(c, d));
+      break;
+    }
+    {
+      PassDesc d = pdesc(PASS_Z_CURL, c->spec);
+      d.z = zargs(c);
+      HIPCHK(pass(c, d));
+    }
+    HIPCHK(pass(c, pdesc(PASS_Y_INV, c->spec, 3)));
+    {
+      PassDesc d = pdesc(PASS_X_MU, c->spec, 3);
+      d.mu_mode = p.mu;
+      d.inv_a0 = inv_a0;
+      HIPCHK(pass(c, d));
+    }
+    HIPCHK(pass(c, pdesc(PASS_Y_FWD, c->spec, 3)));
+    {
+      PassDesc d = pdesc(PASS_Z_DIV, c->spec);
+      d.z = zargs(c);
+      HIPCHK(pass(c, d));
+    }
+    HIPCHK(pass(c, pdesc(PASS_Y_INV, c->spec, 3)));
+  }
+  HIPCHK(pass(c, pdesc(PASS_Y_INV, c->spec, 1)));
+  {
+    PassDesc d = pdesc(PASS_X_INV_REAL, c->spec);
+    d.real = phi_out;
+    HIPCHK(pass(c, d));
+  }
+
+  if (want_info || p.tol > 0.0) {
+    HIPCHK(hipMemcpyAsync(c->hacc, c->dacc, 128 * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    loc.iterations = k_done;
+    loc.gN_norm = sqrt(c->hacc[0] / N3);
+    if (resid) {
+      loc.n_residuals = k_done - 1;
+      for (int k = 1; k < k_done && k <= 64; ++k) {
+        loc.residual[k - 1] = loc.gN_norm > 0.0 ? sqrt(c->hacc[k]) / loc.gN_norm : 0.0;
+        if (!isfinite(loc.residual[k - 1])) loc.status = PM_E_NONFINITE;
+      }
+      if (p.tol > 0.0 && loc.status == PM_OK &&
+          !(loc.n_residuals > 0 && loc.residual[loc.n_residuals - 1] <= p.tol))
+        loc.status = PM_E_NOTCONV;
+    }
+    if (info) *info = loc;
+  }
+  return PM_OK;
+}
+
+static pm_status check_ctx(pm_ctx* c, int64_t n) {
+  if (!c) return inval("ctx is NULL");
+  if (n < 0 || n > c->max_particles) return inval("particle count exceeds max_particles");
+  return PM_OK;
+}
+
+pm_status aqual_solve(pm_ctx* c, const float* rho, const float* H0, float* phi, pm_solve_info* info) {
+  if (!c) return inval("ctx is NULL");
+  if (!rho || !phi) return inval("rho and phi are required");
+  pm_status s = run_solve(c, rho, H0, phi, info, info != nullptr);
+  if (s == PM_OK && info) info->bounds_flag = 0;
+  return s;
+}
+
+pm_status pm_deposit(pm_ctx* c, const float* pos, const float* mass, int64_t n, float* rho) {
+  pm_status s = check_ctx(c, n);
+  if (s != PM_OK) return s;
+  if (!rho || (n > 0 && (!pos || !mass))) return inval("NULL buffer");
+  const long long R = (long long)c->N * c->N * c->N;
+  { Timed t(c, PM_T_FILL); HIPCHK(fill_zero(rho, R, c->st)); }
+  { Timed t(c, PM_T_SORT); HIPCHK(sort_particles(c->kg, c->sb, pos, n, c->st)); }
+  { Timed t(c, PM_T_DEPOSIT); HIPCHK(deposit_sorted(c->kg, c->sb, pos, mass, n, rho, c->st)); }
+  return PM_OK;
+}
+
+pm_status smooth_accel(pm_ctx* c, const float* phi, const float* pos, int64_t n, float* acc) {
+  pm_status s = check_ctx(c, n);
+  if (s != PM_OK) return s;
+  if (!phi || (n > 0 && (!pos || !acc))) return inval("NULL buffer");
+  { Timed t(c, PM_T_SORT); HIPCHK(sort_particles(c->kg, c->sb, pos, n, c->st)); }
+  { Timed t(c, PM_T_GATHER);
+    HIPCHK(gather_sorted(c->kg, c->sb, phi, const_cast<float*>(pos), nullptr, acc, n, 0.f, 0.f, 0, c->st)); }
+  return PM_OK;
+}
+
+pm_status interp_push(pm_ctx* c, const float* phi, float* pos, float* vel, int64_t n, double dt_kick,
+                      double dt_drift) {
+  pm_status s = check_ctx(c, n);
+  if (s != PM_OK) return s;
+  if (!phi || (n > 0 && (!pos || !vel))) return inval("NULL buffer");
+  { Timed t(c, PM_T_SORT); HIPCHK(sort_particles(c->kg, c->sb, pos, n, c->st)); }
+  { Timed t(c, PM_T_GATHER);
+    HIPCHK(gather_sorted(c->kg, c->sb, phi, pos, vel, nullptr, n, (float)dt_kick, (float)dt_drift, 1, c->st)); }
+  return PM_OK;
+}
+
+pm_status pm_step(pm_ctx* c, float* pos, float* vel, const float* mass, int64_t n, double dt,
+                  pm_solve_info* info) {
+  pm_status s = check_ctx(c, n);
+  if (s != PM_OK) return s;
+  if (n > 0 && (!pos || !vel || !mass)) return inval("NULL buffer");
+  const long long R = (long long)c->N * c->N * c->N;
+  if (info) HIPCHK(fill_zero(reinterpret_cast<float*>(c->sb.flags), 1, c->st));
+  { Timed t(c, PM_T_FILL); HIPCHK(fill_zero(c->rho, R, c->st)); }
+  { Timed t(c, PM_T_SORT); HIPCHK(sort_particles(c->kg, c->sb, pos, n, c->st)); }
+  { Timed t(c, PM_T_DEPOSIT); HIPCHK(deposit_sorted(c->kg, c->sb, pos, mass, n, c->rho, c->st)); }
+  s = run_solve(c, c->rho, nullptr, c->phi, info, info != nullptr);
+  if (s != PM_OK) return s;
+  { Timed t(c, PM_T_GATHER);
+    HIPCHK(gather_sorted(c->kg, c->sb, c->phi, pos, vel, nullptr, n, (float)dt, (float)dt, 1, c->st)); }
+  if (info) {
+    int flag = 0;
+    HIPCHK(hipMemcpyAsync(&flag, c->sb.flags, sizeof(int), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    info->bounds_flag = flag > 0 ? 1 : 0;
+  }
+  return PM_OK;
+}
+
+pm_status pm_diagnostics(pm_ctx* c, const float* pos, const float* vel, const float* mass, int64_t n,
+                         const float* phi, double* out) {
+  pm_status s = check_ctx(c, n);
+  if (s != PM_OK) return s;
+  if (!out || (n > 0 && (!pos || !vel || !mass))) return inval("NULL buffer");
+  HIPCHK(fill_zero(reinterpret_cast<float*>(c->dacc + 80), 2 * 10, c->st));
+  HIPCHK(fill_zero(reinterpret_cast<float*>(c->sb.flags), 1, c->st));
+  HIPCHK(diagnostics(c->kg, pos, vel, mass, phi, n, c->dacc + 80, c->st));
+  HIPCHK(sort_particles(c->kg, c->sb, pos, n, c->st));
+  int flag = 0;
+  HIPCHK(hipMemcpyAsync(c->hacc + 80, c->dacc + 80, 9 * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipMemcpyAsync(&flag, c->sb.flags, sizeof(int), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  for (int i = 0; i < 9; ++i) out[i] = c->hacc[80 + i];
+  if (!phi) out[8] = 0.0;
+  out[9] = (double)flag;
+  return PM_OK;
+}
+
+pm_status pm_fft_r2c(pm_ctx* c, const float* in, void* out) {
+  if (!c || !in || !out) return inval("NULL argument");
+  float2* sp = static_cast<float2*>(out);
+  PassDesc d = pdesc(PASS_X_FWD_REAL, sp);
+  d.real = const_cast<float*>(in);
+  HIPCHK(pass(c, d));
+  HIPCHK(pass(c, pdesc(PASS_Y_FWD, sp, 1)));
+  PassDesc z = pdesc(PASS_Z_FWD, sp);
+  z.z = zargs(c);
+  z.z.spec = sp;
+  z.z.nc = 1;
+  HIPCHK(pass(c, z));
+  return PM_OK;
+}
+
+pm_status pm_fft_c2r(pm_ctx* c, const void* in, float* out) {
+  if (!c || !in || !out) return inval("NULL argument");
+  const size_t C = (size_t)c->N * c->N * c->P;
+  HIPCHK(hipMemcpyAsync(c->spec, in, C * sizeof(float2), hipMemcpyDeviceToDevice, c->st));
+  PassDesc z = pdesc(PASS_Z_INV, c->spec);
+  z.z = zargs(c);
+  z.z.nc = 1;
+  HIPCHK(pass(c, z));
+  HIPCHK(pass(c, pdesc(PASS_Y_INV, c->spec, 1)));
+  PassDesc d = pdesc(PASS_X_INV_REAL, c->spec);
+  d.real = out;
+  HIPCHK(pass(c, d));
+  return PM_OK;
+}
+
+pm_status pm_set_timing(pm_ctx* c, int enable) {
+  if (!c) return inval("ctx is NULL");
+  c->timing = enable != 0;
+  return PM_OK;
+}
+
+pm_status pm_read_timing(pm_ctx* c, double* total_ms, int64_t* launches) {
+  if (!c || !total_ms || !launches) return inval("NULL argument");
+  HIPCHK(hipStreamSynchronize(c->st));
+  for (size_t i = 0; i + 1 < c->ev_used; i += 2) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev_pool[i], c->ev_pool[i + 1]));
+    const int k = c->ev_kind[i / 2];
+    total_ms[k] += ms;
+    launches[k] += 1;
+  }
+  c->ev_used = 0;
+  return PM_OK;
+}

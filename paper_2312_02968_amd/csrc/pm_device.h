@@ -1,0 +1,206 @@
+// Device building blocks shared by the HIP kernels of the PM step:
+// complex arithmetic, small DFTs in registers, one Stockham stage over a
+// block's sequences held in LDS, and the interpolation pair mu / nu.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pm {
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+// multiply by -i (forward) or +i (inverse)
+template <bool INV>
+__device__ __forceinline__ float2 mul_mi(float2 a) {
+  return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+
+// cos and sin of 2 pi q / 16, q = 0..7
+__device__ __constant__ static const float kC16[8] = {
+    1.0f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508977f,
+    0.0f, -0.38268343236508977f, -0.70710678118654752f, -0.92387953251128674f};
+__device__ __constant__ static const float kS16[8] = {
+    0.0f, 0.38268343236508977f, 0.70710678118654752f, 0.92387953251128674f,
+    1.0f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508977f};
+
+// exp(-+ 2 pi i q / R) for R in {2, 4, 8, 16}: forward uses the minus sign.
+template <int R, bool INV>
+__device__ __forceinline__ float2 unit_root(int q) {
+  const int t = q * (16 / R);
+  const float c = (t < 8) ? kC16[t] : -kC16[t - 8];
+  const float s = (t < 8) ? kS16[t] : -kS16[t - 8];
+  return make_float2(c, INV ? s : -s);
+}
+
+// In-register DFT of length R (power of two <= 16), radix-2 decimation in
+// time by recursion on even and odd samples.  X[q] = sum_r a[r] w^{rq} with
+// w = exp(-2 pi i / R) (forward) or exp(+2 pi i / R) (inverse); unnormalised.
+template <int R, bool INV>
+struct Dft {
+  __device__ __forceinline__ static void run(float2* a) {
+    float2 e[R / 2], o[R / 2];
+#pragma unroll
+    for (int r = 0; r < R / 2; ++r) { e[r] = a[2 * r]; o[r] = a[2 * r + 1]; }
+    Dft<R / 2, INV>::run(e);
+    Dft<R / 2, INV>::run(o);
+#pragma unroll
+    for (int q = 0; q < R / 2; ++q) {
+      float2 t = (q == 0) ? o[q] : cmul(o[q], unit_root<R, INV>(q));
+      a[q] = cadd(e[q], t);
+      a[q + R / 2] = csub(e[q], t);
+    }
+  }
+};
+template <bool INV>
+struct Dft<1, INV> {
+  __device__ __forceinline__ static void run(float2*) {}
+};
+template <bool INV>
+struct Dft<2, INV> {
+  __device__ __forceinline__ static void run(float2* a) {
+    float2 t = a[1];
+    a[1] = csub(a[0], t);
+    a[0] = cadd(a[0], t);
+  }
+};
+template <bool INV>
+struct Dft<4, INV> {
+  __device__ __forceinline__ static void run(float2* a) {
+    float2 s0 = cadd(a[0], a[2]), d0 = csub(a[0], a[2]);
+    float2 s1 = cadd(a[1], a[3]), d1 = mul_mi<INV>(csub(a[1], a[3]));
+    a[0] = cadd(s0, s1);
+    a[2] = csub(s0, s1);
+    a[1] = cadd(d0, d1);
+    a[3] = csub(d0, d1);
+  }
+};
+
+// Radix plan of a length-L transform: radix of stage st (0-based).
+template <int L>
+struct Plan;
+template <> struct Plan<2>    { static constexpr int S = 1; static constexpr int r[1] = {2}; };
+template <> struct Plan<4>    { static constexpr int S = 1; static constexpr int r[1] = {4}; };
+template <> struct Plan<8>    { static constexpr int S = 1; static constexpr int r[1] = {8}; };
+template <> struct Plan<16>   { static constexpr int S = 1; static constexpr int r[1] = {16}; };
+template <> struct Plan<32>   { static constexpr int S = 2; static constexpr int r[2] = {8, 4}; };
+template <> struct Plan<64>   { static constexpr int S = 2; static constexpr int r[2] = {8, 8}; };
+template <> struct Plan<128>  { static constexpr int S = 2; static constexpr int r[2] = {16, 8}; };
+template <> struct Plan<256>  { static constexpr int S = 2; static constexpr int r[2] = {16, 16}; };
+template <> struct Plan<512>  { static constexpr int S = 3; static constexpr int r[3] = {8, 8, 8}; };
+template <> struct Plan<1024> { static constexpr int S = 3; static constexpr int r[3] = {16, 8, 8}; };
+
+// Layout of a block's S sequences of length L in LDS: element i of sequence
+// q lives at buf[q * QS + i * IS].  SEQ_FAST selects the thread mapping:
+// consecutive threads take consecutive sequences (IS large, QS = 1) or
+// consecutive elements (QS large, IS = 1), so LDS accesses stay contiguous.
+//
+// One Stockham radix-R stage (Ns = product of the radices already applied):
+// butterfly j of a sequence reads x[j + r L/R], multiplies by the twiddle
+// w_{Ns R}^{r (j mod Ns)}, takes a length-R DFT and writes
+// y[(j div Ns) Ns R + (j mod Ns) + q' Ns].  The stage is done in place: all
+// inputs are read into registers before a barrier, outputs are written
+// after it.  tw holds exp(-2 pi i t / TWN) for t < TWN; TWN is a multiple of L.
+template <int L, int R, int S, int NT, bool SEQ_FAST, bool INV>
+__device__ __forceinline__ void stockham_stage(float2* buf, int QS, int IS, int Ns,
+                                               const float2* __restrict__ tw, int twmul) {
+  constexpr int NB = S * (L / R);
+  constexpr int BPT = (NB + NT - 1) / NT;
+  float2 v[BPT][R];
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < BPT; ++u) {
+    const int b = tid + u * NT;
+    if ((NB % NT) == 0 || b < NB) {
+      const int q = SEQ_FAST ? (b % S) : (b / (L / R));
+      const int j = SEQ_FAST ? (b / S) : (b % (L / R));
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[u][r] = buf[q * QS + (j + r * (L / R)) * IS];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < BPT; ++u) {
+    const int b = tid + u * NT;
+    if ((NB % NT) == 0 || b < NB) {
+      const int q = SEQ_FAST ? (b % S) : (b / (L / R));
+      const int j = SEQ_FAST ? (b / S) : (b % (L / R));
+      const int k = j % Ns;
+      if (Ns > 1) {
+        const int step = (L / (Ns * R)) * twmul;   // twiddle index unit
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          float2 w = tw[r * k * step];
+          if (INV) w.y = -w.y;
+          v[u][r] = cmul(v[u][r], w);
+        }
+      }
+      Dft<R, INV>::run(v[u]);
+      const int base = (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[q * QS + (base + r * Ns) * IS] = v[u][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <int L, int S, int NT, bool SEQ_FAST, bool INV, int ST>
+struct FftStages {
+  __device__ __forceinline__ static void run(float2* buf, int QS, int IS, int Ns,
+                                             const float2* __restrict__ tw, int twmul) {
+    constexpr int R = Plan<L>::r[Plan<L>::S - ST];
+    stockham_stage<L, R, S, NT, SEQ_FAST, INV>(buf, QS, IS, Ns, tw, twmul);
+    FftStages<L, S, NT, SEQ_FAST, INV, ST - 1>::run(buf, QS, IS, Ns * R, tw, twmul);
+  }
+};
+template <int L, int S, int NT, bool SEQ_FAST, bool INV>
+struct FftStages<L, S, NT, SEQ_FAST, INV, 0> {
+  __device__ __forceinline__ static void run(float2*, int, int, int, const float2* __restrict__, int) {}
+};
+
+// Unnormalised length-L complex FFT of the block's S sequences in LDS, in
+// place, natural order in and out.  Ends with a barrier.
+template <int L, int S, int NT, bool SEQ_FAST, bool INV>
+__device__ __forceinline__ void block_fft(float2* buf, int QS, int IS, const float2* __restrict__ tw,
+                                          int twmul) {
+  FftStages<L, S, NT, SEQ_FAST, INV, Plan<L>::S>::run(buf, QS, IS, 1, tw, twmul);
+}
+
+// ---------------------------------------------------------------------------
+// The algebraic equations of the AQUAL system (Eqs. inverse, interpolation).
+// mode: 0 standard mu(x) = x / sqrt(1 + x^2), 1 deep MOND mu(x) = x, 2 Newton.
+// ---------------------------------------------------------------------------
+
+// Ratio |g_M| / |F| = nu(y) with y = |F| / a0; zero vector -> 0 (caller
+// multiplies F by the ratio).  Standard: nu(y) = sqrt(1/2 + 1/2 sqrt(1 + 4/y^2))
+// for y >= 1 and the equal form sqrt((y + sqrt(y^2 + 4)) / (2 y)) below 1, so
+// that neither 4/y^2 nor y^2 overflows.
+__device__ __forceinline__ float nu_ratio(int mode, float Fm, float inv_a0) {
+  if (mode == 2) return 1.0f;
+  if (!(Fm > 0.0f)) return 0.0f;
+  const float y = Fm * inv_a0;
+  if (mode == 1) return rsqrtf(y);
+  if (y >= 1.0f) {
+    const float t = 1.0f / y;
+    return sqrtf(0.5f * (1.0f + sqrtf(fmaf(4.0f * t, t, 1.0f))));
+  }
+  return sqrtf((y + sqrtf(fmaf(y, y, 4.0f))) / (2.0f * y));
+}
+
+// Ratio |F| / |g_M| = mu(x) with x = |g_M| / a0.
+__device__ __forceinline__ float mu_ratio(int mode, float gm, float inv_a0) {
+  if (mode == 2) return 1.0f;
+  const float x = gm * inv_a0;
+  if (mode == 1) return x;
+  if (x >= 1.0f) {
+    const float t = 1.0f / x;
+    return rsqrtf(fmaf(t, t, 1.0f));
+  }
+  return x * rsqrtf(fmaf(x, x, 1.0f));
+}
+
+}  // namespace pm

@@ -1,0 +1,499 @@
+// 3D real FFT passes of the AQUAL solve, with the pointwise and spectral steps
+// of the fixed-point iteration fused into them.
+//
+// Data layout.  A real grid is float [N][N][N] ([z][y][x], x fastest).  A
+// spectrum is float2 [N][N][P] ([z or kz][y or ky][kx]) with kx = 0..N/2
+// valid (the half spectrum of a real transform along x) and P complex per
+// row.  Three-component fields are three such spectra, comp_stride apart.
+//
+// A 3D transform is three passes, one per axis.  The x pass works on whole
+// rows and does the real<->complex step as a half-length complex FFT plus the
+// usual even/odd split; the y and z passes work on tiles of T kx-columns.
+// Between the forward and the inverse z transform the whole 3D spectrum of a
+// pencil is in LDS, which is where the spectral operators of the paper's flow
+// scheme (inverse Laplacian, curl-free and divergence-free projections) are
+// applied.  Between the inverse and the next forward x transform a whole real
+// row is in LDS, which is where the algebraic equations (nu, mu) are applied.
+// Every pass reads its block's data completely before writing, and blocks
+// own disjoint data, so all passes run in place.
+#include "pm_device.h"
+#include "pm_internal.h"
+
+namespace pm {
+
+// ----------------------------------------------------------------------------
+// x pass
+// ----------------------------------------------------------------------------
+// XMODE
+enum { X_FWD_REAL = 0, X_INV_REAL = 1, X_FUSED_NU = 2, X_FUSED_MU = 3 };
+
+// r2c split: LDS holds Z = FFT_H(x[2m] + i x[2m+1]) for each sequence; turn
+// it into X[k], k = 0..H (X[H] goes to element H, one past the complex data).
+template <int H, int S, int NT>
+__device__ __forceinline__ void r2c_split(float2* buf, int IS, const float2* __restrict__ tw) {
+  constexpr int NP = S * (H / 2 + 1);
+  for (int b = threadIdx.x; b < NP; b += NT) {
+    const int q = b % S, k = b / S;
+    const int km = (H - k) & (H - 1);
+    const float2 zk = buf[k * IS + q], zm = buf[km * IS + q];
+    // X[k] = E + W^k O,  E = (Zk + conj Zm)/2,  O = -i (Zk - conj Zm)/2
+    float2 e = cscale(cadd(zk, cconj(zm)), 0.5f);
+    float2 o = cscale(mul_mi<false>(csub(zk, cconj(zm))), 0.5f);
+    const float2 xk = cadd(e, cmul(tw[k], o));
+    if (k == 0) {
+      buf[q] = make_float2(zk.x + zk.y, 0.0f);
+      buf[H * IS + q] = make_float2(zk.x - zk.y, 0.0f);
+    } else if (2 * k == H) {
+      buf[k * IS + q] = xk;
+    } else {
+      float2 e2 = cscale(cadd(zm, cconj(zk)), 0.5f);
+      float2 o2 = cscale(mul_mi<false>(csub(zm, cconj(zk))), 0.5f);
+      const float2 xm = cadd(e2, cmul(tw[H - k], o2));
+      buf[k * IS + q] = xk;
+      buf[km * IS + q] = xm;
+    }
+  }
+  __syncthreads();
+}
+
+// c2r merge: LDS holds X[k], k = 0..H; produce Z[k], k < H, such that the
+// unnormalised inverse FFT_H of Z gives x[2m] + i x[2m+1] with
+// x[n] = sum over the full spectrum of X_k exp(+2 pi i k n / N).
+template <int H, int S, int NT>
+__device__ __forceinline__ void c2r_merge(float2* buf, int IS, const float2* __restrict__ tw) {
+  constexpr int NP = S * (H / 2 + 1);
+  for (int b = threadIdx.x; b < NP; b += NT) {
+    const int q = b % S, k = b / S;
+    const float2 xk = buf[k * IS + q], xm = buf[(H - k) * IS + q];
+    // Z[k] = (Xk + conj Xm) + i (Xk - conj Xm) conj(W^k)
+    const float2 zk = cadd(cadd(xk, cconj(xm)), mul_mi<true>(cmul(csub(xk, cconj(xm)), cconj(tw[k]))));
+    if (k == 0 || 2 * k == H) {
+      buf[k * IS + q] = zk;
+    } else {
+      const float2 zm = cadd(cadd(xm, cconj(xk)),
+                             mul_mi<true>(cmul(csub(xm, cconj(xk)), cconj(tw[H - k]))));
+      buf[k * IS + q] = zk;
+      buf[(H - k) * IS + q] = zm;
+    }
+  }
+  __syncthreads();
+}
+
+// One block: ROWS rows of NC components.  Sequence q = c * ROWS + r.
+//   X_FWD_REAL : real rows (float, row pitch 2H) -> spectrum rows
+//   X_INV_REAL : spectrum rows -> real rows
+//   X_FUSED_*  : spectrum rows -> c2r -> nu or mu on the 3-vector -> r2c ->
+//                spectrum rows (in place).  With fprev != nullptr (X_FUSED_NU)
+//                the squared change of F against fprev is accumulated in FP64
+//                into partials[blockIdx.x] and F is stored to fprev.
+template <int H, int ROWS, int NC, int NT, int XMODE>
+__global__ __launch_bounds__(NT) void k_xpass(float2* spec, long long comp_stride, int P,
+                                              float* real, long long real_comp_stride,
+                                              const float2* __restrict__ tw, int mu_mode, float inv_a0,
+                                              float* fprev, double* partials) {
+  constexpr int S = NC * ROWS;
+  constexpr int IS = S + 1;
+  extern __shared__ float2 lds[];
+  const int row0 = blockIdx.x * ROWS;
+  const int N = 2 * H;
+
+  // ---- load
+  if (XMODE == X_FWD_REAL) {
+    for (int b = threadIdx.x; b < S * H; b += NT) {
+      const int q = b / H, m = b % H;
+      const int c = q / ROWS, r = q % ROWS;
+      const float2* src = reinterpret_cast<const float2*>(real + c * real_comp_stride + (long long)(row0 + r) * N);
+      lds[m * IS + q] = src[m];
+    }
+  } else {
+    for (int b = threadIdx.x; b < S * H; b += NT) {
+      const int q = b / H, k = b % H;
+      const int c = q / ROWS, r = q % ROWS;
+      lds[k * IS + q] = spec[c * comp_stride + (long long)(row0 + r) * P + k];
+    }
+    for (int q = threadIdx.x; q < S; q += NT) {
+      const int c = q / ROWS, r = q % ROWS;
+      lds[H * IS + q] = spec[c * comp_stride + (long long)(row0 + r) * P + H];
+    }
+  }
+  __syncthreads();
+
+  if (XMODE != X_FWD_REAL) {
+    c2r_merge<H, S, NT>(lds, IS, tw);
+    block_fft<H, S, NT, true, true>(lds, 1, IS, tw, 2);
+  }
+
+  if (XMODE == X_FUSED_NU || XMODE == X_FUSED_MU) {
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < ROWS * H; b += NT) {
+      const int r = b % ROWS, m = b / ROWS;
+      float2 v0 = lds[m * IS + r], v1 = lds[m * IS + ROWS + r], v2 = lds[m * IS + 2 * ROWS + r];
+      if (XMODE == X_FUSED_NU && fprev != nullptr) {
+        const long long e = (long long)(row0 + r) * N + 2 * m;
+        const long long cs = (long long)N * N * N;
+        float2* f0 = reinterpret_cast<float2*>(fprev + e);
+        float2* f1 = reinterpret_cast<float2*>(fprev + cs + e);
+        float2* f2 = reinterpret_cast<float2*>(fprev + 2 * cs + e);
+        const float2 p0 = *f0, p1 = *f1, p2 = *f2;
+        const double d0 = (double)v0.x - p0.x, d1 = (double)v1.x - p1.x, d2 = (double)v2.x - p2.x;
+        const double e0 = (double)v0.y - p0.y, e1 = (double)v1.y - p1.y, e2 = (double)v2.y - p2.y;
+        acc += d0 * d0 + d1 * d1 + d2 * d2 + e0 * e0 + e1 * e1 + e2 * e2;
+        *f0 = v0; *f1 = v1; *f2 = v2;
+      }
+      // two grid points per complex entry: .x is x = 2m, .y is x = 2m+1
+      {
+        const float m0 = sqrtf(v0.x * v0.x + v1.x * v1.x + v2.x * v2.x);
+        const float f = (XMODE == X_FUSED_NU) ? nu_ratio(mu_mode, m0, inv_a0) : mu_ratio(mu_mode, m0, inv_a0);
+        v0.x *= f; v1.x *= f; v2.x *= f;
+      }
+      {
+        const float m1 = sqrtf(v0.y * v0.y + v1.y * v1.y + v2.y * v2.y);
+        const float f = (XMODE == X_FUSED_NU) ? nu_ratio(mu_mode, m1, inv_a0) : mu_ratio(mu_mode, m1, inv_a0);
+        v0.y *= f; v1.y *= f; v2.y *= f;
+      }
+      lds[m * IS + r] = v0;
+      lds[m * IS + ROWS + r] = v1;
+      lds[m * IS + 2 * ROWS + r] = v2;
+    }
+    if (XMODE == X_FUSED_NU && fprev != nullptr) {
+      // block reduction of acc (FP64)
+      __shared__ double red[NT / 64];
+      for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+      if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < NT / 64; ++w) t += red[w];
+        partials[blockIdx.x] = t;
+      }
+    }
+    __syncthreads();
+  }
+
+  if (XMODE != X_INV_REAL) {
+    block_fft<H, S, NT, true, false>(lds, 1, IS, tw, 2);
+    r2c_split<H, S, NT>(lds, IS, tw);
+    for (int b = threadIdx.x; b < S * H; b += NT) {
+      const int q = b / H, k = b % H;
+      const int c = q / ROWS, r = q % ROWS;
+      spec[c * comp_stride + (long long)(row0 + r) * P + k] = lds[k * IS + q];
+    }
+    for (int q = threadIdx.x; q < S; q += NT) {
+      const int c = q / ROWS, r = q % ROWS;
+      spec[c * comp_stride + (long long)(row0 + r) * P + H] = lds[H * IS + q];
+    }
+  } else {
+    for (int b = threadIdx.x; b < S * H; b += NT) {
+      const int q = b / H, m = b % H;
+      const int c = q / ROWS, r = q % ROWS;
+      float2* dst = reinterpret_cast<float2*>(real + c * real_comp_stride + (long long)(row0 + r) * N);
+      dst[m] = lds[m * IS + q];
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// y pass: c2c along y for T kx-columns of one z plane of one component.
+// ----------------------------------------------------------------------------
+template <int L, int T, int NT, bool INV>
+__global__ __launch_bounds__(NT) void k_ypass(float2* spec, long long comp_stride, int P, int ncols,
+                                              const float2* __restrict__ tw) {
+  constexpr int IS = T + 1;
+  extern __shared__ float2 lds[];
+  const int x0 = blockIdx.x * T;
+  const int z = blockIdx.y;
+  const int nv = min(T, ncols - x0);
+  float2* base = spec + blockIdx.z * comp_stride + (long long)z * L * P + x0;
+  for (int b = threadIdx.x; b < T * L; b += NT) {
+    const int q = b % T, i = b / T;
+    lds[i * IS + q] = (q < nv) ? base[(long long)i * P + q] : make_float2(0.0f, 0.0f);
+  }
+  __syncthreads();
+  block_fft<L, T, NT, true, INV>(lds, 1, IS, tw, 1);
+  for (int b = threadIdx.x; b < T * L; b += NT) {
+    const int q = b % T, i = b / T;
+    if (q < nv) base[(long long)i * P + q] = lds[i * IS + q];
+  }
+}
+
+// ----------------------------------------------------------------------------
+// z pass: forward z transform, spectral operator, inverse z transform, for T
+// kx-columns of one ky row, all components at once.
+// ----------------------------------------------------------------------------
+enum { Z_FWD = 0, Z_INV = 1, Z_NEWTON = 2, Z_CURL = 3, Z_CURL_FINAL = 4, Z_DIV = 5 };
+
+
+template <int L, int T, int NT, int ZOP>
+__global__ __launch_bounds__(NT) void k_zpass(ZArgs a, const float2* __restrict__ tw) {
+  constexpr int NCMAX = 3;
+  constexpr int S = NCMAX * T;
+  constexpr int IS = S + 1;
+  extern __shared__ float2 lds[];
+  const int x0 = blockIdx.x * T;
+  const int y = blockIdx.y;
+  const int nv = min(T, a.ncols - x0);
+  const long long row = (long long)L * a.P;   // stride between z planes
+  const long long off = (long long)y * a.P + x0;
+
+  // inputs: how many components come from where
+  const int nin = (ZOP == Z_FWD || ZOP == Z_INV) ? a.nc
+                  : (ZOP == Z_NEWTON) ? (a.with_h0 ? 4 : 1) : 3;
+  // sequence layout: q = c * T + col for c < 3; for Z_NEWTON with H0 the
+  // density spectrum uses slot 0 and H0's three components are loaded later.
+  for (int b = threadIdx.x; b < NCMAX * T * L; b += NT) {
+    const int q = b % S, i = b / S;
+    const int c = q / T, col = q % T;
+    float2 v = make_float2(0.0f, 0.0f);
+    if (col < nv) {
+      if (ZOP == Z_NEWTON) {
+        if (c == 0) v = a.phiN[(long long)i * row + off + col];
+      } else if (c < nin) {
+        v = a.spec[c * a.comp_stride + (long long)i * row + off + col];
+      }
+    }
+    lds[i * IS + q] = v;
+  }
+  __syncthreads();
+  if (ZOP != Z_INV) block_fft<L, S, NT, true, false>(lds, 1, IS, tw, 1);
+
+  if (ZOP == Z_NEWTON) {
+    double acc = 0.0;
+    const float ky = a.kv[y];
+    const float kapy = a.kap[y];
+    for (int b = threadIdx.x; b < T * L; b += NT) {
+      const int col = b % T, i = b / T;
+      const int kxi = x0 + col;
+      float2 rh = lds[i * IS + col];
+      const float kx = a.kv[kxi < L ? kxi : 0], kz = a.kv[i];
+      const float k2 = kx * kx + ky * ky + kz * kz;
+      const float A = (k2 > 0.0f) ? 1.0f / k2 : 0.0f;
+      const float2 ph = cscale(rh, a.newton_coef * A);       // phi_N hat (raw DFT)
+      if (col < nv) a.phiN[(long long)i * row + off + col] = ph;
+      const float kpx = (kxi < L / 2) ? a.kap[kxi] : 0.0f;
+      const float kpz = a.kap[i];
+      // g_N hat = -i kappa phi_N hat, scaled for the unnormalised inverse
+      const float2 g = cscale(mul_mi<false>(ph), a.scale);
+      lds[i * IS + col] = cscale(g, kpx);
+      lds[i * IS + T + col] = cscale(g, kapy);
+      lds[i * IS + 2 * T + col] = cscale(g, kpz);
+      if (col < nv) {
+        const double w = (kxi == 0 || kxi == L / 2) ? 1.0 : 2.0;
+        const double m2 = (double)ph.x * ph.x + (double)ph.y * ph.y;
+        acc += w * m2 * ((double)kpx * kpx + (double)kapy * kapy + (double)kpz * kpz);
+      }
+    }
+    __shared__ double red[NT / 64];
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int w = 0; w < NT / 64; ++w) t += red[w];
+      a.partials[blockIdx.y * gridDim.x + blockIdx.x] = t;
+    }
+    if (a.with_h0) {
+      // H0's (kx, ky, z) spectra: forward z, add (scaled) to the g_N terms.
+      // Reuse the LDS: stash g_N terms in registers is not possible for all
+      // elements, so transform H0 in place after saving g_N to the output
+      // layout first.
+      __syncthreads();
+      for (int b = threadIdx.x; b < NCMAX * T * L; b += NT) {
+        const int q = b % S, i = b / S;
+        const int c = q / T, col = q % T;
+        if (col < nv) {
+          // swap: LDS gets H0, spec gets g_N term (temporarily)
+          const long long gi = c * a.comp_stride + (long long)i * row + off + col;
+          const float2 h = a.spec[gi];
+          a.spec[gi] = lds[i * IS + q];
+          lds[i * IS + q] = h;
+        } else {
+          lds[i * IS + q] = make_float2(0.0f, 0.0f);
+        }
+      }
+      __syncthreads();
+      block_fft<L, S, NT, true, false>(lds, 1, IS, tw, 1);
+      for (int b = threadIdx.x; b < NCMAX * T * L; b += NT) {
+        const int q = b % S, i = b / S;
+        const int c = q / T, col = q % T;
+        if (col < nv) {
+          const long long gi = c * a.comp_stride + (long long)i * row + off + col;
+          lds[i * IS + q] = cadd(a.spec[gi], cscale(lds[i * IS + q], a.scale));
+        }
+      }
+    }
+    __syncthreads();
+  } else if (ZOP == Z_CURL || ZOP == Z_CURL_FINAL || ZOP == Z_DIV) {
+    const float ty = a.kt[y];
+    for (int b = threadIdx.x; b < T * L; b += NT) {
+      const int col = b % T, i = b / T;
+      const int kxi = x0 + col;
+      const float tx = (kxi < L / 2) ? a.kt[kxi] : 0.0f;
+      const float tz = a.kt[i];
+      const float t2 = tx * tx + ty * ty + tz * tz;
+      const float At = (t2 > 0.0f) ? 1.0f / t2 : 0.0f;
+      float2 g0 = lds[i * IS + col], g1 = lds[i * IS + T + col], g2 = lds[i * IS + 2 * T + col];
+      if (ZOP == Z_DIV) {
+        // F = F' + kt At kt.(g_N - F'), g_N = -i kappa phi_N
+        float2 ph = make_float2(0.0f, 0.0f);
+        if (col < nv) ph = a.phiN[(long long)i * row + off + col];
+        const float kpx = (kxi < L / 2) ? a.kap[kxi] : 0.0f;
+        const float2 mph = mul_mi<false>(ph);
+        const float2 d0 = csub(cscale(mph, kpx), g0);
+        const float2 d1 = csub(cscale(mph, a.kap[y]), g1);
+        const float2 d2 = csub(cscale(mph, a.kap[i]), g2);
+        const float2 dd = cscale(cadd(cadd(cscale(d0, tx), cscale(d1, ty)), cscale(d2, tz)), At);
+        g0 = cscale(cadd(g0, cscale(dd, tx)), a.scale);
+        g1 = cscale(cadd(g1, cscale(dd, ty)), a.scale);
+        g2 = cscale(cadd(g2, cscale(dd, tz)), a.scale);
+      } else {
+        const float2 dot = cadd(cadd(cscale(g0, tx), cscale(g1, ty)), cscale(g2, tz));
+        if (ZOP == Z_CURL) {
+          const float2 s = cscale(dot, At * a.scale);
+          g0 = cscale(s, tx);
+          g1 = cscale(s, ty);
+          g2 = cscale(s, tz);
+        } else {
+          // phi_hat = i At kt.g_hat
+          g0 = cscale(mul_mi<true>(dot), At * a.scale);
+          g1 = make_float2(0.0f, 0.0f);
+          g2 = make_float2(0.0f, 0.0f);
+        }
+      }
+      lds[i * IS + col] = g0;
+      lds[i * IS + T + col] = g1;
+      lds[i * IS + 2 * T + col] = g2;
+    }
+    __syncthreads();
+  }
+
+  if (ZOP != Z_FWD) block_fft<L, S, NT, true, true>(lds, 1, IS, tw, 1);
+
+  const int nout = (ZOP == Z_FWD || ZOP == Z_INV) ? a.nc : (ZOP == Z_CURL_FINAL ? 1 : 3);
+  for (int b = threadIdx.x; b < NCMAX * T * L; b += NT) {
+    const int q = b % S, i = b / S;
+    const int c = q / T, col = q % T;
+    if (col < nv && c < nout) a.spec[c * a.comp_stride + (long long)i * row + off + col] = lds[i * IS + q];
+  }
+}
+
+// Sum of partials[0..n) into out[0] (FP64), one block.
+__global__ __launch_bounds__(1024) void k_reduce_partials(const double* __restrict__ partials, int n,
+                                                          double* out) {
+  __shared__ double red[16];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += 1024) acc += partials[i];
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < 16; ++w) t += red[w];
+    out[0] = t;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// host-side launchers
+// ----------------------------------------------------------------------------
+namespace {
+constexpr int kNT = 256;
+
+template <int N>
+struct Cfg {
+  static constexpr int H = N / 2;
+  static constexpr int ROWS = (1024 / H) < 1 ? 1 : ((1024 / H) > 64 ? 64 : (1024 / H));
+  static constexpr int TY = (8192 / N) > 16 ? 16 : (8192 / N);
+  static constexpr int TZ = (4096 / N) > 16 ? 16 : ((4096 / N) < 1 ? 1 : (4096 / N));
+};
+
+template <int N, int XMODE, int NC>
+hipError_t launch_x(const FftGeom& g, float2* spec, float* real, long long real_cs, int mu_mode,
+                    float inv_a0, float* fprev, double* partials, hipStream_t st) {
+  using C = Cfg<N>;
+  const int blocks = N * N / C::ROWS;
+  const size_t sh = sizeof(float2) * (size_t)(C::H + 1) * (NC * C::ROWS + 1);
+  hipLaunchKernelGGL((k_xpass<C::H, C::ROWS, NC, kNT, XMODE>), dim3(blocks), dim3(kNT), sh, st, spec,
+                     g.comp_stride, g.P, real, real_cs, g.tw, mu_mode, inv_a0, fprev, partials);
+  return hipGetLastError();
+}
+
+template <int N, bool INV>
+hipError_t launch_y(const FftGeom& g, float2* spec, int ncomp, hipStream_t st) {
+  using C = Cfg<N>;
+  const int tiles = (C::H + 1 + C::TY - 1) / C::TY;
+  const size_t sh = sizeof(float2) * (size_t)N * (C::TY + 1);
+  hipLaunchKernelGGL((k_ypass<N, C::TY, kNT, INV>), dim3(tiles, N, ncomp), dim3(kNT), sh, st, spec,
+                     g.comp_stride, g.P, C::H + 1, g.tw);
+  return hipGetLastError();
+}
+
+template <int N, int ZOP>
+hipError_t launch_z(const FftGeom& g, ZArgs a, hipStream_t st) {
+  using C = Cfg<N>;
+  const int tiles = (C::H + 1 + C::TZ - 1) / C::TZ;
+  const size_t sh = sizeof(float2) * (size_t)N * (3 * C::TZ + 1);
+  a.comp_stride = g.comp_stride;
+  a.P = g.P;
+  a.ncols = C::H + 1;
+  hipLaunchKernelGGL((k_zpass<N, C::TZ, kNT, ZOP>), dim3(tiles, N), dim3(kNT), sh, st, a, g.tw);
+  return hipGetLastError();
+}
+
+template <int N>
+hipError_t run_pass(const FftGeom& g, const PassDesc& d, hipStream_t st) {
+  switch (d.kind) {
+    case PASS_X_FWD_REAL:
+      return launch_x<N, X_FWD_REAL, 1>(g, d.spec, d.real, d.real_cs, 0, 0.f, nullptr, nullptr, st);
+    case PASS_X_FWD_REAL3:
+      return launch_x<N, X_FWD_REAL, 3>(g, d.spec, d.real, d.real_cs, 0, 0.f, nullptr, nullptr, st);
+    case PASS_X_INV_REAL:
+      return launch_x<N, X_INV_REAL, 1>(g, d.spec, d.real, d.real_cs, 0, 0.f, nullptr, nullptr, st);
+    case PASS_X_NU:
+      return launch_x<N, X_FUSED_NU, 3>(g, d.spec, nullptr, 0, d.mu_mode, d.inv_a0, d.fprev, d.partials, st);
+    case PASS_X_MU:
+      return launch_x<N, X_FUSED_MU, 3>(g, d.spec, nullptr, 0, d.mu_mode, d.inv_a0, nullptr, nullptr, st);
+    case PASS_Y_FWD: return launch_y<N, false>(g, d.spec, d.ncomp, st);
+    case PASS_Y_INV: return launch_y<N, true>(g, d.spec, d.ncomp, st);
+    case PASS_Z_FWD: return launch_z<N, Z_FWD>(g, d.z, st);
+    case PASS_Z_INV: return launch_z<N, Z_INV>(g, d.z, st);
+    case PASS_Z_NEWTON: return launch_z<N, Z_NEWTON>(g, d.z, st);
+    case PASS_Z_CURL: return launch_z<N, Z_CURL>(g, d.z, st);
+    case PASS_Z_CURL_FINAL: return launch_z<N, Z_CURL_FINAL>(g, d.z, st);
+    case PASS_Z_DIV: return launch_z<N, Z_DIV>(g, d.z, st);
+  }
+  return hipErrorInvalidValue;
+}
+}  // namespace
+
+int x_blocks(int N) {
+  const int H = N / 2;
+  int rows = 1024 / H;
+  rows = rows < 1 ? 1 : (rows > 64 ? 64 : rows);
+  return N * N / rows;
+}
+int z_blocks(int N) {
+  const int H = N / 2;
+  int tz = 4096 / N;
+  tz = tz > 16 ? 16 : (tz < 1 ? 1 : tz);
+  return ((H + 1 + tz - 1) / tz) * N;
+}
+
+hipError_t fft_pass(const FftGeom& g, const PassDesc& d, hipStream_t st) {
+  switch (g.N) {
+    case 16: return run_pass<16>(g, d, st);
+    case 32: return run_pass<32>(g, d, st);
+    case 64: return run_pass<64>(g, d, st);
+    case 128: return run_pass<128>(g, d, st);
+    case 256: return run_pass<256>(g, d, st);
+    case 512: return run_pass<512>(g, d, st);
+    case 1024: return run_pass<1024>(g, d, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t reduce_partials(const double* partials, int n, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(1024), 0, st, partials, n, out);
+  return hipGetLastError();
+}
+
+}  // namespace pm

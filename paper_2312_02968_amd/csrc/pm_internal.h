@@ -1,0 +1,95 @@
+// Internal interfaces between the C ABI (pm_api.hip) and the kernel files.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pm {
+
+// Geometry of the FFT box and its half spectrum.
+struct FftGeom {
+  int N;                  // n_pad
+  int P;                  // complex entries per spectrum row (>= N/2 + 1)
+  long long comp_stride;  // complex entries per spectrum component (N * N * P)
+  const float2* tw;       // exp(-2 pi i t / N), t < N
+};
+
+// Arguments of a z pass (see pm_fft.hip).
+struct ZArgs {
+  float2* spec;
+  long long comp_stride;
+  int P, ncols;
+  float2* phiN;
+  const float* kv;
+  const float* kt;
+  const float* kap;
+  float newton_coef;
+  float scale;
+  int with_h0;
+  double* partials;
+  int nc;
+};
+
+enum PassKind {
+  PASS_X_FWD_REAL, PASS_X_FWD_REAL3, PASS_X_INV_REAL, PASS_X_NU, PASS_X_MU,
+  PASS_Y_FWD, PASS_Y_INV,
+  PASS_Z_FWD, PASS_Z_INV, PASS_Z_NEWTON, PASS_Z_CURL, PASS_Z_CURL_FINAL, PASS_Z_DIV
+};
+
+struct PassDesc {
+  PassKind kind;
+  float2* spec = nullptr;
+  float* real = nullptr;
+  long long real_cs = 0;
+  int mu_mode = 0;
+  float inv_a0 = 0.f;
+  float* fprev = nullptr;
+  double* partials = nullptr;
+  int ncomp = 1;
+  ZArgs z{};
+};
+
+hipError_t fft_pass(const FftGeom& g, const PassDesc& d, hipStream_t st);
+hipError_t reduce_partials(const double* partials, int n, double* out, hipStream_t st);
+int x_blocks(int N);
+int z_blocks(int N);
+
+// ---------------------------------------------------------------------------
+// particles
+// ---------------------------------------------------------------------------
+struct KernelGeom {
+  int N;            // n_pad
+  int n;            // physical cells per axis
+  float s;          // pixel width
+  double inv_s;     // 1 / s
+  float inv2sig2;   // 1 / (2 sigma^2)
+  int ext;          // largest |d_axis| in the ball
+  int nball;        // ball cells
+  const int* ball;  // packed offsets (dx+16) | (dy+16) << 8 | (dz+16) << 16
+  int analytic;     // literal prefactor instead of the ball-sum normalisation
+  double analytic_norm;  // (2 pi)^1.5 sigma^3
+};
+
+struct SortBufs {
+  int* keys;        // [N] tile of each particle
+  int* rank;        // [N] rank within its tile
+  int* perm;        // [N] sorted order -> particle index
+  int* skey;        // [N] tile of perm[i]
+  int* counts;      // [ntiles + 1]
+  int* offsets;     // [ntiles + 1] exclusive scan of counts
+  int* blocksums;   // scan scratch
+  int ntiles;
+  int* flags;       // [0]: bounds violations
+};
+
+hipError_t sort_particles(const KernelGeom& kg, const SortBufs& sb, const float* pos, int64_t n,
+                          hipStream_t st);
+hipError_t deposit_sorted(const KernelGeom& kg, const SortBufs& sb, const float* pos, const float* mass,
+                          int64_t n, float* rho, hipStream_t st);
+// mode 0: acc = g; mode 1: v += g dt_kick, r += v dt_drift
+hipError_t gather_sorted(const KernelGeom& kg, const SortBufs& sb, const float* phi, float* pos, float* vel,
+                         float* acc, int64_t n, float dt_kick, float dt_drift, int mode, hipStream_t st);
+hipError_t fill_zero(float* p, long long count, hipStream_t st);
+hipError_t diagnostics(const KernelGeom& kg, const float* pos, const float* vel, const float* mass,
+                       const float* phi, int64_t n, double* out_dev, hipStream_t st);
+
+}  // namespace pm

@@ -1,0 +1,42 @@
+"""The C ABI library loads and exports every function include/mondpm.h declares
+(CPU only: no compute call is made)."""
+import ctypes
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mondpm.h")
+LIB = os.path.join(ROOT, "paper_2312_02968_amd", "libmondpm.so")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s+\**([a-z_][a-z0-9_]*)\s*\(",
+                       src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_lists_the_entry_points():
+    names = declared_functions()
+    for required in ("pm_deposit", "aqual_solve", "smooth_accel", "interp_push", "pm_step",
+                     "pm_create", "pm_destroy", "pm_workspace_bytes"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    assert os.path.exists(LIB), "build the library first (python -m paper_2312_02968_amd.build)"
+    lib = ctypes.CDLL(LIB)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_host_side_argument_checks_without_gpu():
+    from paper_2312_02968_amd import mondpm as M
+    import workloads as W
+    assert M.pm_spectrum_pitch(512) == 272 and M.pm_spectrum_pitch(16) == 16
+    good = W.params(256)
+    assert M.pm_workspace_bytes(good, 1 << 20) > 4 * 512 ** 3 * 4
+    assert M.pm_workspace_bytes(dict(good, n_pad=500), 0) == 0     # not a power of two
+    assert M.pm_workspace_bytes(dict(good, sigma=3.0), 0) == 0     # ball radius > 10 cells
+    assert M.pm_workspace_bytes(dict(good, iters=0), 0) == 0

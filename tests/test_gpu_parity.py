@@ -1,0 +1,309 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Inputs are the seeded FP32 arrays of ``workloads``; the oracle receives the
+same FP32 values promoted to FP64.  Tolerances (FP32 arithmetic against FP64):
+density 1e-6 of its maximum per cell (each cell is a sum of FP32-rounded
+terms), 3D transforms 3e-6 relative L2, potential and forces 1e-5 relative
+(the target of the method's FP32 path), positions and velocities after a push
+to FP32 rounding of the update.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import pm as orc  # noqa: E402
+import workloads as W  # noqa: E402
+from tests.gpu_util import dev, host, oparams, rel_l2, rel_max, grid  # noqa: E402
+
+
+def _log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def M():
+    from paper_2312_02968_amd import mondpm
+    mondpm.lib()
+    return mondpm
+
+
+# ---------------------------------------------------------------------------
+# 3D transforms
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("N", [16, 32, 64, 128, 256])
+def test_fft_r2c_c2r_against_dft(M, N):
+    _log("fft", N)
+    rng = np.random.default_rng(N)
+    x = rng.standard_normal((N, N, N)).astype(np.float32)
+    params = W.params(N // 2, n_pad=N)
+    ctx = M.pm_create(params, 0)
+    P = M.pm_spectrum_pitch(N)
+    spec = torch.zeros(N * N * P * 2, dtype=torch.float32, device="cuda")
+    M.pm_fft_r2c(ctx, dev(x), spec)
+    s = host(spec).reshape(N, N, P, 2)
+    got = s[:, :, : N // 2 + 1, 0] + 1j * s[:, :, : N // 2 + 1, 1]
+    ref = orc.fft3(x.astype(np.float64))[:, :, : N // 2 + 1]
+    assert rel_l2(got, ref) < 3e-6
+    out = grid(N)
+    M.pm_fft_c2r(ctx, spec, out)
+    back = host(out).reshape(N, N, N) / N ** 3
+    assert rel_l2(back, x) < 3e-6
+    ctx.close()
+
+
+def test_fft_single_mode_exact(M):
+    # cos(k.x) has exactly two non-zero DFT bins of value N^3 / 2.
+    N = 64
+    ax = np.arange(N)
+    z, y, x = np.meshgrid(ax, ax, ax, indexing="ij")
+    m = (3, 5, 7)
+    f = np.cos(2 * np.pi * (m[0] * x + m[1] * y + m[2] * z) / N)
+    ctx = M.pm_create(W.params(32, n_pad=N), 0)
+    P = M.pm_spectrum_pitch(N)
+    spec = torch.zeros(N * N * P * 2, dtype=torch.float32, device="cuda")
+    M.pm_fft_r2c(ctx, dev(f), spec)
+    s = host(spec).reshape(N, N, P, 2)
+    mag = np.hypot(s[:, :, : N // 2 + 1, 0], s[:, :, : N // 2 + 1, 1])
+    assert mag[m[2], m[1], m[0]] == pytest.approx(N ** 3 / 2, rel=1e-6)
+    mag[m[2], m[1], m[0]] = 0.0
+    assert mag.max() < 1e-6 * N ** 3
+    ctx.close()
+
+
+# ---------------------------------------------------------------------------
+# deposit
+# ---------------------------------------------------------------------------
+DEPOSIT_CASES = [
+    ("cloud16", lambda: W.random_cloud(1, 16, 37, radius_frac=0.3)),
+    ("cloud32_s1.5", lambda: W.random_cloud(2, 32, 1000, sigma=1.5, radius_frac=0.25)),
+    ("dense32", lambda: W.random_cloud(3, 32, 5000, radius_frac=0.08)),     # LDS tile path
+    ("two_body", lambda: W.two_body()),
+    ("ring_small", lambda: W.ring(seed=0, n_ring=300, radius=10.0, n=32, sigma=1.5)),
+]
+
+
+@pytest.mark.parametrize("name,make", DEPOSIT_CASES, ids=[c[0] for c in DEPOSIT_CASES])
+def test_deposit_parity(M, name, make):
+    _log("deposit", name)
+    w = make()
+    p = w["params"]
+    N = p["n_pad"]
+    ref = orc.deposit(oparams(p), w["pos"].astype(np.float64), w["mass"].astype(np.float64))
+    ctx = M.pm_create(p, len(w["mass"]))
+    rho = grid(N)
+    M.pm_deposit(ctx, dev(w["pos"]), dev(w["mass"]), rho)
+    got = host(rho).reshape(N, N, N)
+    assert rel_max(got, ref) < 1e-6
+    assert abs(got.sum() - ref.sum()) <= 1e-6 * ref.sum()
+    ctx.close()
+
+
+def test_deposit_analytic_norm_and_empty(M):
+    w = W.random_cloud(5, 16, 20)
+    p = dict(w["params"], flags=M.PM_F_ANALYTIC_NORM, box=24.0)
+    N = p["n_pad"]
+    ref = orc.deposit(oparams(p), w["pos"].astype(np.float64), w["mass"].astype(np.float64))
+    ctx = M.pm_create(p, 64)
+    rho = grid(N)
+    M.pm_deposit(ctx, dev(w["pos"]), dev(w["mass"]), rho)
+    assert rel_max(host(rho).reshape(N, N, N), ref) < 1e-6
+    # zero particles: the grid is cleared
+    M.pm_deposit(ctx, dev(np.zeros((0, 3))), dev(np.zeros(0)), rho)
+    assert float(host(rho).max()) == 0.0
+    ctx.close()
+
+
+def test_deposit_wraps_and_flags_out_of_region(M):
+    p = W.params(16, n_pad=32, sigma=1.0)
+    pos = np.array([[15.7, -15.9, 0.2], [0.1, 0.2, 0.3], [7.4, 0.0, 0.0]], dtype=np.float32)
+    mass = np.array([1.0, 2.0, 0.5], dtype=np.float32)
+    ref = orc.deposit(oparams(p), pos.astype(np.float64), mass.astype(np.float64))
+    ctx = M.pm_create(p, 3)
+    rho = grid(32)
+    M.pm_deposit(ctx, dev(pos), dev(mass), rho)
+    assert rel_max(host(rho).reshape(32, 32, 32), ref) < 1e-6
+    d = M.pm_diagnostics(ctx, dev(pos), dev(np.zeros_like(pos)), dev(mass))
+    assert d["out_of_region"] == int(orc.out_of_region(oparams(p), pos.astype(np.float64)).sum()) == 2
+    ctx.close()
+
+
+# ---------------------------------------------------------------------------
+# solve
+# ---------------------------------------------------------------------------
+SOLVE_CASES = [(mu, n, K) for mu in (0, 1, 2) for (n, K) in ((16, 1), (16, 4), (32, 4))]
+
+
+@pytest.mark.parametrize("mu,n,K", SOLVE_CASES)
+def test_solve_parity(M, mu, n, K):
+    _log("solve", mu, n, K)
+    w = W.random_cloud(10 + n, n, 3 * n, mu=mu, iters=K)
+    p = w["params"]
+    N = p["n_pad"]
+    rho32 = orc.deposit(oparams(p), w["pos"].astype(np.float64), w["mass"].astype(np.float64)).astype(np.float32)
+    phi_ref, info_ref = orc.aqual_solve(oparams(p), rho32.astype(np.float64))
+    ctx = M.pm_create(dict(p, flags=M.PM_F_RESIDUAL), 0)
+    phi = grid(N)
+    info = M.aqual_solve(ctx, dev(rho32), phi)
+    got = host(phi).reshape(N, N, N)
+    assert rel_l2(got, phi_ref) < 1e-5
+    assert rel_max(got, phi_ref) < 1e-5
+    assert info["iterations"] == K
+    assert len(info["residuals"]) == len(info_ref.residuals) == K - 1
+    for a, b in zip(info["residuals"], info_ref.residuals):
+        # FP32 fields: a residual that is exactly 0 in FP64 (Newton mode) sits
+        # at the FP32 rounding floor
+        assert a == pytest.approx(b, rel=1e-3, abs=2e-6)
+    ctx.close()
+
+
+def test_solve_in_place_and_h0(M):
+    w = W.random_cloud(21, 16, 40, mu=0, iters=3)
+    p = w["params"]
+    N = p["n_pad"]
+    rho32 = orc.deposit(oparams(p), w["pos"].astype(np.float64), w["mass"].astype(np.float64)).astype(np.float32)
+    rng = np.random.default_rng(0)
+    _, gN = orc.newton_potential(oparams(p), rho32.astype(np.float64))
+    H0 = (0.05 * np.abs(gN).max() * rng.standard_normal((3, N, N, N))).astype(np.float32)
+    phi_ref, _ = orc.aqual_solve(oparams(p), rho32.astype(np.float64), H0=H0.astype(np.float64))
+    ctx = M.pm_create(p, 0)
+    buf = dev(rho32)
+    M.aqual_solve(ctx, buf, buf, H0=dev(H0))        # rho and phi share a buffer
+    assert rel_l2(host(buf).reshape(N, N, N), phi_ref) < 1e-5
+    ctx.close()
+
+
+def test_tolerance_mode(M):
+    w = W.random_cloud(4, 16, 50, mu=0, iters=12)
+    p = w["params"]
+    N = p["n_pad"]
+    rho32 = orc.deposit(oparams(p), w["pos"].astype(np.float64), w["mass"].astype(np.float64)).astype(np.float32)
+    _, full = orc.aqual_solve(oparams(p), rho32.astype(np.float64))
+    tol = math.sqrt(full.residuals[2] * full.residuals[3])   # between r_3 and r_4
+    q = dict(p, tol=tol)
+    phi_ref, info_ref = orc.aqual_solve(oparams(q), rho32.astype(np.float64))
+    ctx = M.pm_create(q, 0)
+    phi = grid(N)
+    info = M.aqual_solve(ctx, dev(rho32), phi)
+    assert info["iterations"] == info_ref.iterations
+    assert info["status"] == 0
+    assert rel_l2(host(phi).reshape(N, N, N), phi_ref) < 1e-5
+    ctx.close()
+    q = dict(p, tol=1e-30, iters=3)
+    ctx = M.pm_create(q, 0)
+    info = M.aqual_solve(ctx, dev(rho32), phi)
+    assert info["iterations"] == 3 and info["status"] == M.PM_E_NOTCONV
+    ctx.close()
+
+
+# ---------------------------------------------------------------------------
+# gather and push
+# ---------------------------------------------------------------------------
+def _phi_case(seed, n, Npart, mu=0, sigma=1.0, radius_frac=0.3):
+    w = W.random_cloud(seed, n, Npart, mu=mu, sigma=sigma, radius_frac=radius_frac)
+    p = w["params"]
+    rho = orc.deposit(oparams(p), w["pos"].astype(np.float64), w["mass"].astype(np.float64))
+    phi, _ = orc.aqual_solve(oparams(p), rho)
+    return w, p, phi.astype(np.float32)
+
+
+@pytest.mark.parametrize("seed,n,Npart,sigma,rf", [(1, 16, 33, 1.0, 0.3), (2, 32, 3000, 1.0, 0.1),
+                                                  (3, 32, 700, 1.5, 0.25), (4, 32, 129, 2.0, 0.2)])
+def test_smooth_accel_parity(M, seed, n, Npart, sigma, rf):
+    _log("gather", seed, n, Npart, sigma)
+    w, p, phi32 = _phi_case(seed, n, Npart, sigma=sigma, radius_frac=rf)
+    N = p["n_pad"]
+    ref = orc.smooth_accel(oparams(p), phi32.astype(np.float64), w["pos"].astype(np.float64))
+    ctx = M.pm_create(p, Npart)
+    acc = torch.zeros(3 * Npart, dtype=torch.float32, device="cuda")
+    M.smooth_accel(ctx, dev(phi32), dev(w["pos"]), acc)
+    got = host(acc).reshape(-1, 3)
+    assert rel_l2(got, ref) < 1e-5
+    assert rel_max(got, ref) < 1e-5
+    ctx.close()
+
+
+def test_interp_push_parity(M):
+    w, p, phi32 = _phi_case(7, 16, 50)
+    ctx = M.pm_create(p, 50)
+    pos, vel = dev(w["pos"]), dev(w["vel"])
+    M.interp_push(ctx, dev(phi32), pos, vel, 0.3, 0.7)
+    pr, vr = orc.interp_push(oparams(p), phi32.astype(np.float64), w["pos"].astype(np.float64),
+                             w["vel"].astype(np.float64), 0.3, 0.7)
+    dv_ref = vr - w["vel"]
+    dv = host(vel).reshape(-1, 3) - w["vel"]
+    assert rel_l2(dv, dv_ref) < 1e-5
+    assert np.max(np.abs(host(pos).reshape(-1, 3) - pr)) < 1e-5 * max(1.0, np.abs(pr).max())
+    ctx.close()
+
+
+# ---------------------------------------------------------------------------
+# whole step
+# ---------------------------------------------------------------------------
+STEP_CASES = [
+    ("cloud_std", lambda: W.random_cloud(31, 32, 400, mu=0, radius_frac=0.2)),
+    ("cloud_deep", lambda: W.random_cloud(32, 32, 400, mu=1, radius_frac=0.2)),
+    ("two_body", lambda: W.two_body()),
+    ("iso_small", lambda: W.isothermal_sphere(seed=1, N=4096, n=32, b=3.0, r_max=11.0)),
+]
+
+
+@pytest.mark.parametrize("name,make", STEP_CASES, ids=[c[0] for c in STEP_CASES])
+def test_pm_step_parity(M, name, make):
+    _log("step", name)
+    w = make()
+    p = w["params"]
+    n_p = len(w["mass"])
+    dt = float(w["dt"])
+    ctx = M.pm_create(p, n_p)
+    pos, vel, mass = dev(w["pos"]), dev(w["vel"]), dev(w["mass"])
+    info = M.pm_step(ctx, pos, vel, mass, dt, want_info=True)
+    assert info["iterations"] == p["iters"] and info["bounds_flag"] == 0
+    pr, vr, _ = orc.pm_step(oparams(p), w["pos"].astype(np.float64), w["vel"].astype(np.float64),
+                            w["mass"].astype(np.float64), dt)
+    # force parity: the velocity change is g dt
+    g_ref = (vr - w["vel"]) / dt
+    g = (host(vel).reshape(-1, 3) - w["vel"]) / dt
+    assert rel_l2(g, g_ref) < 1e-5
+    assert rel_max(g, g_ref) < 1e-5
+    assert np.max(np.abs(host(pos).reshape(-1, 3) - pr)) < 2e-5 * max(1.0, np.abs(pr).max())
+    ctx.close()
+
+
+def test_pm_step_zero_particles(M):
+    p = W.params(16)
+    ctx = M.pm_create(p, 8)
+    e = torch.zeros(0, dtype=torch.float32, device="cuda")
+    M.pm_step(ctx, e, e, e, 0.1)
+    ctx.close()
+
+
+def test_newton_momentum_conserved_on_gpu(M):
+    # Newton mode: sum_i m_i g_i = 0 up to FP32 rounding of the forces.
+    w = W.random_cloud(40, 32, 2000, mu=2, radius_frac=0.2)
+    p = w["params"]
+    ctx = M.pm_create(p, 2000)
+    pos, vel, mass = dev(w["pos"]), dev(np.zeros_like(w["vel"])), dev(w["mass"])
+    M.pm_step(ctx, pos, vel, mass, 1.0)
+    g = host(vel).reshape(-1, 3)
+    m = w["mass"].astype(np.float64)
+    tot = (m[:, None] * g).sum(0)
+    assert np.max(np.abs(tot)) < 1e-5 * (m[:, None] * np.abs(g)).sum()
+    ctx.close()
+
+
+def test_invalid_arguments(M):
+    with pytest.raises(M.PmError):
+        M.pm_create(dict(W.params(16), n_pad=24), 0)
+    with pytest.raises(M.PmError):
+        M.pm_create(dict(W.params(16), a0=-1.0), 0)
+    ctx = M.pm_create(W.params(16), 4)
+    with pytest.raises(M.PmError):
+        M.pm_deposit(ctx, dev(np.zeros((5, 3))), dev(np.ones(5)), grid(32))   # N > max_particles
+    ctx.close()
