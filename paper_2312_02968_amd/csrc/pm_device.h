@@ -204,3 +204,150 @@ __device__ __forceinline__ float mu_ratio(int mode, float gm, float inv_a0) {
 }
 
 }  // namespace pm
+
+namespace pm {
+
+// ---------------------------------------------------------------------------
+// Column FFT engine with register staging.
+//
+// S sequences ("columns") of length L are spread over NT threads.  In stage
+// st (radix R, Ns = product of the earlier radices) butterfly b of a thread
+// is (q = b mod S, j = b div S); it consumes elements j + r L/R and produces
+// elements (j - j mod Ns) R + j mod Ns + r Ns.  The first stage's inputs come
+// from a loader (global memory) and the last stage's outputs go to the caller
+// in registers: the last stage has j < Ns, so it produces elements
+// j + r L/R -- exactly the inputs of the first stage of a transform run with
+// the reversed radix plan.  Only the hand-overs between stages go through LDS
+// (one buffer of S L complex, element i of column q at i * (S + 1) + q), one
+// component at a time.
+// ---------------------------------------------------------------------------
+template <int L, bool REV, int ST>
+struct PlanAt {
+  static constexpr int R = REV ? Plan<L>::r[Plan<L>::S - 1 - ST] : Plan<L>::r[ST];
+  static constexpr int Ns = PlanAt<L, REV, ST - 1>::Ns * PlanAt<L, REV, ST - 1>::R;
+};
+template <int L, bool REV>
+struct PlanAt<L, REV, 0> {
+  static constexpr int R = REV ? Plan<L>::r[Plan<L>::S - 1] : Plan<L>::r[0];
+  static constexpr int Ns = 1;
+};
+
+// Register elements per thread: the largest BPT * R over the stages of the
+// plan (when a stage has fewer butterflies than threads, a thread still holds
+// one whole butterfly).
+template <int L, int S, int NT>
+struct ColCfg {
+  static constexpr int bpr(int R) { return ((S * (L / R) + NT - 1) / NT) * R; }
+  static constexpr int emax() {
+    int e = 0;
+    for (int st = 0; st < Plan<L>::S; ++st) e = bpr(Plan<L>::r[st]) > e ? bpr(Plan<L>::r[st]) : e;
+    return e;
+  }
+  static constexpr int E = emax();
+  static constexpr int IS = S + 1;
+};
+
+// Number of butterflies per thread and validity for stage parameters.
+template <int L, int S, int NT, int R>
+struct Bfly {
+  static constexpr int NB = S * (L / R);
+  static constexpr int BPT = (NB + NT - 1) / NT;
+  __device__ __forceinline__ static bool valid(int b) { return (NB % NT) == 0 || b < NB; }
+};
+
+// Twiddle and DFT of the butterflies held in v (stage with radix R at Ns).
+template <int L, int S, int NT, int R, int Ns, bool INV>
+__device__ __forceinline__ void reg_butterflies(float2* v, const float2* tw_lds, int twmul) {
+  using B = Bfly<L, S, NT, R>;
+#pragma unroll
+  for (int u = 0; u < B::BPT; ++u) {
+    const int b = threadIdx.x + u * NT;
+    if (!B::valid(b)) continue;
+    float2* a = v + u * R;
+    if (Ns > 1) {
+      const int j = b / S;
+      const int k = j % Ns;
+      const int step = (L / (Ns * R)) * twmul;
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        float2 w = tw_lds[r * k * step];
+        if (INV) w.y = -w.y;
+        a[r] = cmul(a[r], w);
+      }
+    }
+    Dft<R, INV>::run(a);
+  }
+}
+
+// Write the outputs of stage (R, Ns) held in v to LDS.
+template <int L, int S, int NT, int R, int Ns>
+__device__ __forceinline__ void reg_to_lds(const float2* v, float2* buf) {
+  using B = Bfly<L, S, NT, R>;
+  constexpr int IS = S + 1;
+#pragma unroll
+  for (int u = 0; u < B::BPT; ++u) {
+    const int b = threadIdx.x + u * NT;
+    if (!B::valid(b)) continue;
+    const int q = b % S, j = b / S, k = j % Ns;
+    const int base = (j - k) * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) buf[(base + r * Ns) * IS + q] = v[u * R + r];
+  }
+}
+
+// Read the inputs of a stage with radix R from LDS into v.
+template <int L, int S, int NT, int R>
+__device__ __forceinline__ void lds_to_reg(float2* v, const float2* buf) {
+  using B = Bfly<L, S, NT, R>;
+  constexpr int IS = S + 1;
+#pragma unroll
+  for (int u = 0; u < B::BPT; ++u) {
+    const int b = threadIdx.x + u * NT;
+    if (!B::valid(b)) continue;
+    const int q = b % S, j = b / S;
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[u * R + r] = buf[(j + r * (L / R)) * IS + q];
+  }
+}
+
+// Remaining stages ST..end for NC components held in v[c * E ...]; the caller
+// has already run stage ST-1's butterflies.  Ends with the last stage's
+// butterflies done (outputs in registers).
+template <int L, int S, int NT, int NC, bool INV, bool REV, int ST, bool DONE = (ST >= Plan<L>::S)>
+struct ColStagesSel;
+template <int L, int S, int NT, int NC, bool INV, bool REV, int ST>
+struct ColStagesSel<L, S, NT, NC, INV, REV, ST, true> {
+  __device__ __forceinline__ static void run(float2*, float2*, const float2*, int) {}
+};
+template <int L, int S, int NT, int NC, bool INV, bool REV, int ST>
+struct ColStagesSel<L, S, NT, NC, INV, REV, ST, false> {
+  __device__ __forceinline__ static void run(float2* v, float2* buf, const float2* tw, int twmul) {
+    constexpr int E = ColCfg<L, S, NT>::E;
+    using Prev = PlanAt<L, REV, ST - 1>;
+    using Cur = PlanAt<L, REV, ST>;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      reg_to_lds<L, S, NT, Prev::R, Prev::Ns>(v + c * E, buf);
+      __syncthreads();
+      lds_to_reg<L, S, NT, Cur::R>(v + c * E, buf);
+      __syncthreads();
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) reg_butterflies<L, S, NT, Cur::R, Cur::Ns, INV>(v + c * E, tw, twmul);
+    ColStagesSel<L, S, NT, NC, INV, REV, ST + 1>::run(v, buf, tw, twmul);
+  }
+};
+
+// Full transform of NC components whose first-stage inputs are already in v
+// (element j + r L/R0 of column q for butterfly (q, j)).  Outputs stay in v:
+// element j + r L/R_last of column q for butterfly (q, j) of the last stage.
+template <int L, int S, int NT, int NC, bool INV, bool REV>
+__device__ __forceinline__ void col_fft(float2* v, float2* buf, const float2* tw, int twmul) {
+  constexpr int E = ColCfg<L, S, NT>::E;
+  using First = PlanAt<L, REV, 0>;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) reg_butterflies<L, S, NT, First::R, 1, INV>(v + c * E, tw, twmul);
+  ColStagesSel<L, S, NT, NC, INV, REV, 1>::run(v, buf, tw, twmul);
+}
+
+}  // namespace pm

@@ -193,95 +193,207 @@ __global__ __launch_bounds__(NT) void k_xpass(float2* spec, long long comp_strid
 }
 
 // ----------------------------------------------------------------------------
-// y pass: c2c along y for T kx-columns of one z plane of one component.
+// Column passes.  A block owns T kx-columns of one z plane (y pass) or one ky
+// row (z pass).  Twiddles are staged in LDS; the first stage reads HBM into
+// registers and the last stage writes registers to HBM (see col_fft).
 // ----------------------------------------------------------------------------
-template <int L, int T, int NT, bool INV>
-__global__ __launch_bounds__(NT) void k_ypass(float2* spec, long long comp_stride, int P, int ncols,
-                                              const float2* __restrict__ tw) {
-  constexpr int IS = T + 1;
-  extern __shared__ float2 lds[];
-  const int x0 = blockIdx.x * T;
-  const int z = blockIdx.y;
-  const int nv = min(T, ncols - x0);
-  float2* base = spec + blockIdx.z * comp_stride + (long long)z * L * P + x0;
-  for (int b = threadIdx.x; b < T * L; b += NT) {
-    const int q = b % T, i = b / T;
-    lds[i * IS + q] = (q < nv) ? base[(long long)i * P + q] : make_float2(0.0f, 0.0f);
-  }
-  __syncthreads();
-  block_fft<L, T, NT, true, INV>(lds, 1, IS, tw, 1);
-  for (int b = threadIdx.x; b < T * L; b += NT) {
-    const int q = b % T, i = b / T;
-    if (q < nv) base[(long long)i * P + q] = lds[i * IS + q];
+template <int L>
+__device__ __forceinline__ void load_twiddles(float2* tw_s, const float2* __restrict__ tw, int NT) {
+  for (int t = threadIdx.x; t < L; t += NT) tw_s[t] = tw[t];
+}
+
+// Loads the first-stage inputs (radix R) of column q = b mod T from
+// src + i * row_stride + q for the NC components, zero for q >= nv.
+template <int L, int T, int NT, int R>
+__device__ __forceinline__ void load_cols(float2* v, int E, const float2* const* src, int nc, long long row_stride,
+                                          int nv) {
+  using B = Bfly<L, T, NT, R>;
+#pragma unroll
+  for (int u = 0; u < B::BPT; ++u) {
+    const int b = threadIdx.x + u * NT;
+    if (!B::valid(b)) continue;
+    const int q = b % T, j = b / T;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const long long off = (long long)(j + r * (L / R)) * row_stride + q;
+      for (int c = 0; c < nc; ++c)
+        v[c * E + u * R + r] = (q < nv) ? src[c][off] : make_float2(0.0f, 0.0f);
+    }
   }
 }
 
-// ----------------------------------------------------------------------------
-// z pass: forward z transform, spectral operator, inverse z transform, for T
-// kx-columns of one ky row, all components at once.
-// ----------------------------------------------------------------------------
-enum { Z_FWD = 0, Z_INV = 1, Z_NEWTON = 2, Z_CURL = 3, Z_CURL_FINAL = 4, Z_DIV = 5 };
+template <int L, int T, int NT, int R>
+__device__ __forceinline__ void store_cols(const float2* v, int E, float2* const* dst, int nc, long long row_stride,
+                                           int nv) {
+  using B = Bfly<L, T, NT, R>;
+#pragma unroll
+  for (int u = 0; u < B::BPT; ++u) {
+    const int b = threadIdx.x + u * NT;
+    if (!B::valid(b)) continue;
+    const int q = b % T, j = b / T;
+    if (q >= nv) continue;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const long long off = (long long)(j + r * (L / R)) * row_stride + q;
+      for (int c = 0; c < nc; ++c) dst[c][off] = v[c * E + u * R + r];
+    }
+  }
+}
 
+template <int L, int T, int NT, bool INV>
+__global__ __launch_bounds__(NT) void k_ypass(float2* spec, long long comp_stride, int P, int ncols,
+                                              const float2* __restrict__ tw) {
+  constexpr int E = ColCfg<L, T, NT>::E;
+  extern __shared__ float2 lds[];
+  float2* tw_s = lds + L * (T + 1);
+  const int x0 = blockIdx.x * T;
+  const int nv = min(T, ncols - x0);
+  float2* base = spec + blockIdx.z * comp_stride + (long long)blockIdx.y * L * P + x0;
+  load_twiddles<L>(tw_s, tw, NT);
+  float2 v[E];
+  using First = PlanAt<L, false, 0>;
+  using Last = PlanAt<L, false, Plan<L>::S - 1>;
+  const float2* src[1] = {base};
+  load_cols<L, T, NT, First::R>(v, E, src, 1, P, nv);
+  __syncthreads();
+  col_fft<L, T, NT, 1, INV, false>(v, lds, tw_s, 1);
+  float2* dst[1] = {base};
+  store_cols<L, T, NT, Last::R>(v, E, dst, 1, P, nv);
+}
 
+enum { Z_FWD = 0, Z_INV = 1, Z_NEWTON = 2, Z_CURL = 3, Z_CURL_FINAL = 4, Z_DIV = 5, Z_NEWTON_H0 = 6 };
+
+template <int ZOP> struct ZComp;
+template <> struct ZComp<Z_FWD>        { static constexpr int IN = 1, OUT = 1; };
+template <> struct ZComp<Z_INV>        { static constexpr int IN = 1, OUT = 1; };
+template <> struct ZComp<Z_NEWTON>     { static constexpr int IN = 1, OUT = 3; };
+template <> struct ZComp<Z_NEWTON_H0>  { static constexpr int IN = 4, OUT = 3; };
+template <> struct ZComp<Z_CURL>       { static constexpr int IN = 3, OUT = 3; };
+template <> struct ZComp<Z_CURL_FINAL> { static constexpr int IN = 3, OUT = 1; };
+template <> struct ZComp<Z_DIV>        { static constexpr int IN = 3, OUT = 3; };
+
+// z pass: forward z transform of the input components, the spectral operator
+// at every (kx, ky, kz) in registers, inverse z transform, store.
+//   Z_NEWTON    : in = rho_hat (x, y transformed, in phiN); stores phi_N_hat =
+//                 -4 pi G A rho_hat into phiN and outputs g_N_hat = -i kappa
+//                 phi_N_hat (/N^3) as three components; accumulates the
+//                 Parseval sum of |g_N_hat|^2 per block.
+//   Z_NEWTON_H0 : as Z_NEWTON plus the x, y transformed H0 components from spec.
+//   Z_CURL      : g <- kt At (kt . g) / N^3
+//   Z_CURL_FINAL: phi_hat = i At (kt . g) / N^3 (one output component)
+//   Z_DIV       : F = F' + kt At kt . (g_N - F'), g_N = -i kappa phi_N (/N^3)
 template <int L, int T, int NT, int ZOP>
 __global__ __launch_bounds__(NT) void k_zpass(ZArgs a, const float2* __restrict__ tw) {
-  constexpr int NCMAX = 3;
-  constexpr int S = NCMAX * T;
-  constexpr int IS = S + 1;
+  constexpr int E = ColCfg<L, T, NT>::E;
+  constexpr int NIN = ZComp<ZOP>::IN, NOUT = ZComp<ZOP>::OUT;
+  constexpr int NV = NIN > NOUT ? NIN : NOUT;
   extern __shared__ float2 lds[];
+  float2* tw_s = lds + L * (T + 1);
   const int x0 = blockIdx.x * T;
   const int y = blockIdx.y;
   const int nv = min(T, a.ncols - x0);
-  const long long row = (long long)L * a.P;   // stride between z planes
+  const long long row = (long long)L * a.P;
   const long long off = (long long)y * a.P + x0;
+  load_twiddles<L>(tw_s, tw, NT);
 
-  // inputs: how many components come from where
-  const int nin = (ZOP == Z_FWD || ZOP == Z_INV) ? a.nc
-                  : (ZOP == Z_NEWTON) ? (a.with_h0 ? 4 : 1) : 3;
-  // sequence layout: q = c * T + col for c < 3; for Z_NEWTON with H0 the
-  // density spectrum uses slot 0 and H0's three components are loaded later.
-  for (int b = threadIdx.x; b < NCMAX * T * L; b += NT) {
-    const int q = b % S, i = b / S;
-    const int c = q / T, col = q % T;
-    float2 v = make_float2(0.0f, 0.0f);
-    if (col < nv) {
-      if (ZOP == Z_NEWTON) {
-        if (c == 0) v = a.phiN[(long long)i * row + off + col];
-      } else if (c < nin) {
-        v = a.spec[c * a.comp_stride + (long long)i * row + off + col];
-      }
-    }
-    lds[i * IS + q] = v;
+  float2 v[NV * E];
+  using First = PlanAt<L, false, 0>;
+  using Last = PlanAt<L, false, Plan<L>::S - 1>;
+  const float2* src[4];
+  if (ZOP == Z_NEWTON || ZOP == Z_NEWTON_H0) {
+    src[0] = a.phiN + off;
+    for (int c = 1; c < NIN; ++c) src[c] = a.spec + (c - 1) * a.comp_stride + off;
+  } else {
+    for (int c = 0; c < NIN; ++c) src[c] = a.spec + c * a.comp_stride + off;
   }
+  if (ZOP == Z_INV) {
+    load_cols<L, T, NT, First::R>(v, E, src, NIN, row, nv);
+    __syncthreads();
+    col_fft<L, T, NT, 1, true, false>(v, lds, tw_s, 1);
+    float2* dst[1] = {a.spec + off};
+    store_cols<L, T, NT, Last::R>(v, E, dst, 1, row, nv);
+    return;
+  }
+  load_cols<L, T, NT, First::R>(v, E, src, NIN, row, nv);
   __syncthreads();
-  if (ZOP != Z_INV) block_fft<L, S, NT, true, false>(lds, 1, IS, tw, 1);
+  col_fft<L, T, NT, NIN, false, false>(v, lds, tw_s, 1);
+  if (ZOP == Z_FWD) {
+    float2* dst[1] = {a.spec + off};
+    store_cols<L, T, NT, Last::R>(v, E, dst, 1, row, nv);
+    return;
+  }
 
-  if (ZOP == Z_NEWTON) {
-    double acc = 0.0;
-    const float ky = a.kv[y];
-    const float kapy = a.kap[y];
-    for (int b = threadIdx.x; b < T * L; b += NT) {
-      const int col = b % T, i = b / T;
-      const int kxi = x0 + col;
-      float2 rh = lds[i * IS + col];
-      const float kx = a.kv[kxi < L ? kxi : 0], kz = a.kv[i];
-      const float k2 = kx * kx + ky * ky + kz * kz;
-      const float A = (k2 > 0.0f) ? 1.0f / k2 : 0.0f;
-      const float2 ph = cscale(rh, a.newton_coef * A);       // phi_N hat (raw DFT)
-      if (col < nv) a.phiN[(long long)i * row + off + col] = ph;
-      const float kpx = (kxi < L / 2) ? a.kap[kxi] : 0.0f;
-      const float kpz = a.kap[i];
-      // g_N hat = -i kappa phi_N hat, scaled for the unnormalised inverse
-      const float2 g = cscale(mul_mi<false>(ph), a.scale);
-      lds[i * IS + col] = cscale(g, kpx);
-      lds[i * IS + T + col] = cscale(g, kapy);
-      lds[i * IS + 2 * T + col] = cscale(g, kpz);
-      if (col < nv) {
-        const double w = (kxi == 0 || kxi == L / 2) ? 1.0 : 2.0;
-        const double m2 = (double)ph.x * ph.x + (double)ph.y * ph.y;
-        acc += w * m2 * ((double)kpx * kpx + (double)kapy * kapy + (double)kpz * kpz);
+  // ---- spectral operator on the last stage's elements kz = j + r L / RL
+  constexpr int RL = Last::R;
+  using BL = Bfly<L, T, NT, RL>;
+  double acc = 0.0;
+  const float ky = a.kv[y], ty = a.kt[y], kapy = a.kap[y];
+#pragma unroll
+  for (int u = 0; u < BL::BPT; ++u) {
+    const int b = threadIdx.x + u * NT;
+    if (!BL::valid(b)) continue;
+    const int q = b % T, j = b / T;
+    const int kxi = x0 + q;
+    const bool inb = q < nv;
+    const float kx = a.kv[kxi < L ? kxi : 0];
+    const float tx = (kxi < L / 2) ? a.kt[kxi] : 0.0f;
+    const float kpx = (kxi < L / 2) ? a.kap[kxi] : 0.0f;
+#pragma unroll
+    for (int r = 0; r < RL; ++r) {
+      const int kz = j + r * (L / RL);
+      const int e = u * RL + r;
+      if (ZOP == Z_NEWTON || ZOP == Z_NEWTON_H0) {
+        const float kzz = a.kv[kz];
+        const float k2 = kx * kx + ky * ky + kzz * kzz;
+        const float A = (k2 > 0.0f) ? 1.0f / k2 : 0.0f;
+        const float2 ph = cscale(v[e], a.newton_coef * A);     // phi_N hat (raw DFT)
+        if (inb) a.phiN[(long long)kz * row + off + q] = ph;
+        const float kpz = a.kap[kz];
+        const float2 g = cscale(mul_mi<false>(ph), a.scale);
+        float2 o0 = cscale(g, kpx), o1 = cscale(g, kapy), o2 = cscale(g, kpz);
+        if (ZOP == Z_NEWTON_H0) {
+          o0 = cadd(o0, cscale(v[1 * E + e], a.scale));
+          o1 = cadd(o1, cscale(v[2 * E + e], a.scale));
+          o2 = cadd(o2, cscale(v[3 * E + e], a.scale));
+        }
+        v[e] = o0;
+        v[E + e] = o1;
+        v[2 * E + e] = o2;
+        if (inb) {
+          const double w = (kxi == 0 || kxi == L / 2) ? 1.0 : 2.0;
+          const double m2 = (double)ph.x * ph.x + (double)ph.y * ph.y;
+          acc += w * m2 * ((double)kpx * kpx + (double)kapy * kapy + (double)kpz * kpz);
+        }
+      } else {
+        const float tz = a.kt[kz];
+        const float t2 = tx * tx + ty * ty + tz * tz;
+        const float At = (t2 > 0.0f) ? 1.0f / t2 : 0.0f;
+        float2 g0 = v[e], g1 = v[E + e], g2 = v[2 * E + e];
+        if (ZOP == Z_DIV) {
+          const float2 ph = inb ? a.phiN[(long long)kz * row + off + q] : make_float2(0.0f, 0.0f);
+          const float2 mph = mul_mi<false>(ph);
+          const float2 d0 = csub(cscale(mph, kpx), g0);
+          const float2 d1 = csub(cscale(mph, kapy), g1);
+          const float2 d2 = csub(cscale(mph, a.kap[kz]), g2);
+          const float2 dd = cscale(cadd(cadd(cscale(d0, tx), cscale(d1, ty)), cscale(d2, tz)), At);
+          v[e] = cscale(cadd(g0, cscale(dd, tx)), a.scale);
+          v[E + e] = cscale(cadd(g1, cscale(dd, ty)), a.scale);
+          v[2 * E + e] = cscale(cadd(g2, cscale(dd, tz)), a.scale);
+        } else {
+          const float2 dot = cadd(cadd(cscale(g0, tx), cscale(g1, ty)), cscale(g2, tz));
+          if (ZOP == Z_CURL) {
+            const float2 sc = cscale(dot, At * a.scale);
+            v[e] = cscale(sc, tx);
+            v[E + e] = cscale(sc, ty);
+            v[2 * E + e] = cscale(sc, tz);
+          } else {
+            v[e] = cscale(mul_mi<true>(dot), At * a.scale);    // phi_hat = i At kt.g
+          }
+        }
       }
     }
+  }
+  if (ZOP == Z_NEWTON || ZOP == Z_NEWTON_H0) {
     __shared__ double red[NT / 64];
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
@@ -291,89 +403,14 @@ __global__ __launch_bounds__(NT) void k_zpass(ZArgs a, const float2* __restrict_
       for (int w = 0; w < NT / 64; ++w) t += red[w];
       a.partials[blockIdx.y * gridDim.x + blockIdx.x] = t;
     }
-    if (a.with_h0) {
-      // H0's (kx, ky, z) spectra: forward z, add (scaled) to the g_N terms.
-      // Reuse the LDS: stash g_N terms in registers is not possible for all
-      // elements, so transform H0 in place after saving g_N to the output
-      // layout first.
-      __syncthreads();
-      for (int b = threadIdx.x; b < NCMAX * T * L; b += NT) {
-        const int q = b % S, i = b / S;
-        const int c = q / T, col = q % T;
-        if (col < nv) {
-          // swap: LDS gets H0, spec gets g_N term (temporarily)
-          const long long gi = c * a.comp_stride + (long long)i * row + off + col;
-          const float2 h = a.spec[gi];
-          a.spec[gi] = lds[i * IS + q];
-          lds[i * IS + q] = h;
-        } else {
-          lds[i * IS + q] = make_float2(0.0f, 0.0f);
-        }
-      }
-      __syncthreads();
-      block_fft<L, S, NT, true, false>(lds, 1, IS, tw, 1);
-      for (int b = threadIdx.x; b < NCMAX * T * L; b += NT) {
-        const int q = b % S, i = b / S;
-        const int c = q / T, col = q % T;
-        if (col < nv) {
-          const long long gi = c * a.comp_stride + (long long)i * row + off + col;
-          lds[i * IS + q] = cadd(a.spec[gi], cscale(lds[i * IS + q], a.scale));
-        }
-      }
-    }
-    __syncthreads();
-  } else if (ZOP == Z_CURL || ZOP == Z_CURL_FINAL || ZOP == Z_DIV) {
-    const float ty = a.kt[y];
-    for (int b = threadIdx.x; b < T * L; b += NT) {
-      const int col = b % T, i = b / T;
-      const int kxi = x0 + col;
-      const float tx = (kxi < L / 2) ? a.kt[kxi] : 0.0f;
-      const float tz = a.kt[i];
-      const float t2 = tx * tx + ty * ty + tz * tz;
-      const float At = (t2 > 0.0f) ? 1.0f / t2 : 0.0f;
-      float2 g0 = lds[i * IS + col], g1 = lds[i * IS + T + col], g2 = lds[i * IS + 2 * T + col];
-      if (ZOP == Z_DIV) {
-        // F = F' + kt At kt.(g_N - F'), g_N = -i kappa phi_N
-        float2 ph = make_float2(0.0f, 0.0f);
-        if (col < nv) ph = a.phiN[(long long)i * row + off + col];
-        const float kpx = (kxi < L / 2) ? a.kap[kxi] : 0.0f;
-        const float2 mph = mul_mi<false>(ph);
-        const float2 d0 = csub(cscale(mph, kpx), g0);
-        const float2 d1 = csub(cscale(mph, a.kap[y]), g1);
-        const float2 d2 = csub(cscale(mph, a.kap[i]), g2);
-        const float2 dd = cscale(cadd(cadd(cscale(d0, tx), cscale(d1, ty)), cscale(d2, tz)), At);
-        g0 = cscale(cadd(g0, cscale(dd, tx)), a.scale);
-        g1 = cscale(cadd(g1, cscale(dd, ty)), a.scale);
-        g2 = cscale(cadd(g2, cscale(dd, tz)), a.scale);
-      } else {
-        const float2 dot = cadd(cadd(cscale(g0, tx), cscale(g1, ty)), cscale(g2, tz));
-        if (ZOP == Z_CURL) {
-          const float2 s = cscale(dot, At * a.scale);
-          g0 = cscale(s, tx);
-          g1 = cscale(s, ty);
-          g2 = cscale(s, tz);
-        } else {
-          // phi_hat = i At kt.g_hat
-          g0 = cscale(mul_mi<true>(dot), At * a.scale);
-          g1 = make_float2(0.0f, 0.0f);
-          g2 = make_float2(0.0f, 0.0f);
-        }
-      }
-      lds[i * IS + col] = g0;
-      lds[i * IS + T + col] = g1;
-      lds[i * IS + 2 * T + col] = g2;
-    }
-    __syncthreads();
   }
 
-  if (ZOP != Z_FWD) block_fft<L, S, NT, true, true>(lds, 1, IS, tw, 1);
-
-  const int nout = (ZOP == Z_FWD || ZOP == Z_INV) ? a.nc : (ZOP == Z_CURL_FINAL ? 1 : 3);
-  for (int b = threadIdx.x; b < NCMAX * T * L; b += NT) {
-    const int q = b % S, i = b / S;
-    const int c = q / T, col = q % T;
-    if (col < nv && c < nout) a.spec[c * a.comp_stride + (long long)i * row + off + col] = lds[i * IS + q];
-  }
+  // ---- inverse z transform with the reversed plan: its first stage takes the
+  // elements the forward last stage produced, so no exchange is needed here.
+  col_fft<L, T, NT, NOUT, true, true>(v, lds, tw_s, 1);
+  float2* dst[3];
+  for (int c = 0; c < NOUT; ++c) dst[c] = a.spec + c * a.comp_stride + off;
+  store_cols<L, T, NT, First::R>(v, E, dst, NOUT, row, nv);
 }
 
 // Sum of partials[0..n) into out[0] (FP64), one block.
@@ -402,8 +439,8 @@ template <int N>
 struct Cfg {
   static constexpr int H = N / 2;
   static constexpr int ROWS = (1024 / H) < 1 ? 1 : ((1024 / H) > 64 ? 64 : (1024 / H));
-  static constexpr int TY = (8192 / N) > 16 ? 16 : (8192 / N);
-  static constexpr int TZ = (4096 / N) > 16 ? 16 : ((4096 / N) < 1 ? 1 : (4096 / N));
+  static constexpr int TY = 16;
+  static constexpr int TZ = 8;
 };
 
 template <int N, int XMODE, int NC>
@@ -421,7 +458,7 @@ template <int N, bool INV>
 hipError_t launch_y(const FftGeom& g, float2* spec, int ncomp, hipStream_t st) {
   using C = Cfg<N>;
   const int tiles = (C::H + 1 + C::TY - 1) / C::TY;
-  const size_t sh = sizeof(float2) * (size_t)N * (C::TY + 1);
+  const size_t sh = sizeof(float2) * ((size_t)N * (C::TY + 1) + N);
   hipLaunchKernelGGL((k_ypass<N, C::TY, kNT, INV>), dim3(tiles, N, ncomp), dim3(kNT), sh, st, spec,
                      g.comp_stride, g.P, C::H + 1, g.tw);
   return hipGetLastError();
@@ -431,7 +468,7 @@ template <int N, int ZOP>
 hipError_t launch_z(const FftGeom& g, ZArgs a, hipStream_t st) {
   using C = Cfg<N>;
   const int tiles = (C::H + 1 + C::TZ - 1) / C::TZ;
-  const size_t sh = sizeof(float2) * (size_t)N * (3 * C::TZ + 1);
+  const size_t sh = sizeof(float2) * ((size_t)N * (C::TZ + 1) + N);
   a.comp_stride = g.comp_stride;
   a.P = g.P;
   a.ncols = C::H + 1;
@@ -456,7 +493,8 @@ hipError_t run_pass(const FftGeom& g, const PassDesc& d, hipStream_t st) {
     case PASS_Y_INV: return launch_y<N, true>(g, d.spec, d.ncomp, st);
     case PASS_Z_FWD: return launch_z<N, Z_FWD>(g, d.z, st);
     case PASS_Z_INV: return launch_z<N, Z_INV>(g, d.z, st);
-    case PASS_Z_NEWTON: return launch_z<N, Z_NEWTON>(g, d.z, st);
+    case PASS_Z_NEWTON:
+      return d.z.with_h0 ? launch_z<N, Z_NEWTON_H0>(g, d.z, st) : launch_z<N, Z_NEWTON>(g, d.z, st);
     case PASS_Z_CURL: return launch_z<N, Z_CURL>(g, d.z, st);
     case PASS_Z_CURL_FINAL: return launch_z<N, Z_CURL_FINAL>(g, d.z, st);
     case PASS_Z_DIV: return launch_z<N, Z_DIV>(g, d.z, st);
@@ -473,8 +511,7 @@ int x_blocks(int N) {
 }
 int z_blocks(int N) {
   const int H = N / 2;
-  int tz = 4096 / N;
-  tz = tz > 16 ? 16 : (tz < 1 ? 1 : tz);
+  const int tz = 8;
   return ((H + 1 + tz - 1) / tz) * N;
 }
 
