@@ -96,6 +96,8 @@ __global__ __launch_bounds__(NT) void k_xpass(float2* spec, long long comp_strid
   extern __shared__ float2 lds[];
   const int row0 = blockIdx.x * ROWS;
   const int N = 2 * H;
+  float2* tw_s = lds + (H + 1) * IS;
+  for (int t = threadIdx.x; t < N; t += NT) tw_s[t] = tw[t];
 
   // ---- load
   if (XMODE == X_FWD_REAL) {
@@ -119,8 +121,8 @@ __global__ __launch_bounds__(NT) void k_xpass(float2* spec, long long comp_strid
   __syncthreads();
 
   if (XMODE != X_FWD_REAL) {
-    c2r_merge<H, S, NT>(lds, IS, tw);
-    block_fft<H, S, NT, true, true>(lds, 1, IS, tw, 2);
+    c2r_merge<H, S, NT>(lds, IS, tw_s);
+    block_fft<H, S, NT, true, true>(lds, 1, IS, tw_s, 2);
   }
 
   if (XMODE == X_FUSED_NU || XMODE == X_FUSED_MU) {
@@ -171,8 +173,8 @@ __global__ __launch_bounds__(NT) void k_xpass(float2* spec, long long comp_strid
   }
 
   if (XMODE != X_INV_REAL) {
-    block_fft<H, S, NT, true, false>(lds, 1, IS, tw, 2);
-    r2c_split<H, S, NT>(lds, IS, tw);
+    block_fft<H, S, NT, true, false>(lds, 1, IS, tw_s, 2);
+    r2c_split<H, S, NT>(lds, IS, tw_s);
     for (int b = threadIdx.x; b < S * H; b += NT) {
       const int q = b / H, k = b % H;
       const int c = q / ROWS, r = q % ROWS;
@@ -188,6 +190,162 @@ __global__ __launch_bounds__(NT) void k_xpass(float2* spec, long long comp_strid
       const int c = q / ROWS, r = q % ROWS;
       float2* dst = reinterpret_cast<float2*>(real + c * real_comp_stride + (long long)(row0 + r) * N);
       dst[m] = lds[m * IS + q];
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// x pass for n_pad = 512 (rows of H = 256 complex): one 16-lane group per
+// row, four rows per wave, four waves per block.  Lane j of a group holds the
+// elements k = j + 16 r (r < 16) of its row for every component, so
+//  - the 256-point FFT is 16 x 16: a radix-16 DFT in registers, one exchange
+//    through a wave-private LDS buffer, twiddles, a radix-16 DFT, and the
+//    output is again at k = j + 16 r;
+//  - the partner H - k of element k (even/odd split of the real transform)
+//    sits in lane 16 - j, register 15 - r (lane 0 pairs within itself), so the
+//    split and merge are cross-lane shuffles;
+//  - nu / mu act on the registers.
+// No block-wide barrier is needed after the twiddle table is loaded.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int xpad(int p) { return p + (p >> 4); }
+
+// 256-point FFT of the group's row held as v[r] = x[j + 16 r]; result in the
+// same layout.  xb: the group's 272-entry LDS row.
+template <bool INV>
+__device__ __forceinline__ void fft256_group(float2* v, float2* xb, int j, const float2* tw_s) {
+  Dft<16, INV>::run(v);                                  // outputs y[16 j + r]
+#pragma unroll
+  for (int r = 0; r < 16; ++r) xb[xpad(16 * j + r)] = v[r];
+  wave_sync();
+#pragma unroll
+  for (int r = 0; r < 16; ++r) v[r] = xb[xpad(j + 16 * r)];
+  wave_sync();
+#pragma unroll
+  for (int r = 1; r < 16; ++r) {
+    float2 w = tw_s[2 * r * j];                          // w_256^(r j) from the 512-entry table
+    if (INV) w.y = -w.y;
+    v[r] = cmul(v[r], w);
+  }
+  Dft<16, INV>::run(v);                                  // outputs y[j + 16 r]
+}
+
+template <int XMODE, int NC>
+__global__ __launch_bounds__(256) void k_xpass256(float2* spec, long long comp_stride, int P, float* real,
+                                                  long long real_comp_stride, const float2* __restrict__ tw,
+                                                  int mu_mode, float inv_a0, float* fprev, double* partials) {
+  constexpr int H = 256, N = 512;
+  extern __shared__ float2 lds[];
+  float2* tw_s = lds;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int g = lane >> 4, j = lane & 15;
+  float2* xb = lds + N + (wave * 4 + g) * 272;
+  const long long row = (long long)blockIdx.x * 16 + wave * 4 + g;
+  for (int t = threadIdx.x; t < N; t += 256) tw_s[t] = tw[t];
+  __syncthreads();
+
+  float2 v[NC][16];
+  const int pl = (lane & ~15) | ((16 - j) & 15);          // lane of the partner elements
+
+  if (XMODE == X_FWD_REAL) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const float2* src = reinterpret_cast<const float2*>(real + c * real_comp_stride + row * N);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) v[c][r] = src[j + 16 * r];
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const float2* src = spec + c * comp_stride + row * P;
+      float2 x[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) x[r] = src[j + 16 * r];
+      const float2 nyq = src[H];
+      // merge: Z[k] = (Xk + conj Xm) + i (Xk - conj Xm) conj(W^k), Xm = X[H - k]
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        float2 xm;
+        xm.x = __shfl(x[15 - r].x, pl, 64);
+        xm.y = __shfl(x[15 - r].y, pl, 64);
+        if (j == 0) xm = (r == 0) ? nyq : x[(16 - r) & 15];
+        const int k = j + 16 * r;
+        const float2 a = cadd(x[r], cconj(xm));
+        const float2 d = cmul(csub(x[r], cconj(xm)), cconj(tw_s[k]));
+        v[c][r] = cadd(a, mul_mi<true>(d));
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) fft256_group<true>(v[c], xb, j, tw_s);
+  }
+
+  if (XMODE == X_FUSED_NU || XMODE == X_FUSED_MU) {
+    double acc = 0.0;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      float2 a0 = v[0][r], a1 = v[1][r], a2 = v[2][r];
+      if (XMODE == X_FUSED_NU && fprev != nullptr) {
+        const long long e = row * N + 2 * (j + 16 * r);
+        const long long cs = (long long)N * N * N;
+        float2* f0 = reinterpret_cast<float2*>(fprev + e);
+        float2* f1 = reinterpret_cast<float2*>(fprev + cs + e);
+        float2* f2 = reinterpret_cast<float2*>(fprev + 2 * cs + e);
+        const float2 p0 = *f0, p1 = *f1, p2 = *f2;
+        const double d0 = (double)a0.x - p0.x, d1 = (double)a1.x - p1.x, d2 = (double)a2.x - p2.x;
+        const double e0 = (double)a0.y - p0.y, e1 = (double)a1.y - p1.y, e2 = (double)a2.y - p2.y;
+        acc += d0 * d0 + d1 * d1 + d2 * d2 + e0 * e0 + e1 * e1 + e2 * e2;
+        *f0 = a0; *f1 = a1; *f2 = a2;
+      }
+      const float m0 = sqrtf(a0.x * a0.x + a1.x * a1.x + a2.x * a2.x);
+      const float m1 = sqrtf(a0.y * a0.y + a1.y * a1.y + a2.y * a2.y);
+      const float f0 = (XMODE == X_FUSED_NU) ? nu_ratio(mu_mode, m0, inv_a0) : mu_ratio(mu_mode, m0, inv_a0);
+      const float f1 = (XMODE == X_FUSED_NU) ? nu_ratio(mu_mode, m1, inv_a0) : mu_ratio(mu_mode, m1, inv_a0);
+      v[0][r] = make_float2(a0.x * f0, a0.y * f1);
+      v[1][r] = make_float2(a1.x * f0, a1.y * f1);
+      v[2][r] = make_float2(a2.x * f0, a2.y * f1);
+    }
+    if (XMODE == X_FUSED_NU && fprev != nullptr) {
+      __shared__ double red[4];
+      for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+      if (lane == 0) red[wave] = acc;
+      __syncthreads();
+      if (threadIdx.x == 0) partials[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+    }
+  }
+
+  if (XMODE == X_INV_REAL) {
+    float2* dst = reinterpret_cast<float2*>(real + row * N);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) dst[j + 16 * r] = v[0][r];
+    return;
+  }
+
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    fft256_group<false>(v[c], xb, j, tw_s);
+    float2* dst = spec + c * comp_stride + row * P;
+    // split: X[k] = E + W^k O, E = (Zk + conj Zm)/2, O = -i (Zk - conj Zm)/2
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      float2 zm;
+      zm.x = __shfl(v[c][15 - r].x, pl, 64);
+      zm.y = __shfl(v[c][15 - r].y, pl, 64);
+      if (j == 0) zm = v[c][(16 - r) & 15];
+      const float2 zk = v[c][r];
+      const int k = j + 16 * r;
+      const float2 e = cscale(cadd(zk, cconj(zm)), 0.5f);
+      const float2 o = cscale(mul_mi<false>(csub(zk, cconj(zm))), 0.5f);
+      if (k == 0) {
+        dst[0] = make_float2(zk.x + zk.y, 0.0f);
+        dst[H] = make_float2(zk.x - zk.y, 0.0f);
+      } else {
+        dst[k] = cadd(e, cmul(tw_s[k], o));
+      }
     }
   }
 }
@@ -434,6 +592,7 @@ __global__ __launch_bounds__(1024) void k_reduce_partials(const double* __restri
 // ----------------------------------------------------------------------------
 namespace {
 constexpr int kNT = 256;
+constexpr int kNTZ = 512;
 
 template <int N>
 struct Cfg {
@@ -447,8 +606,14 @@ template <int N, int XMODE, int NC>
 hipError_t launch_x(const FftGeom& g, float2* spec, float* real, long long real_cs, int mu_mode,
                     float inv_a0, float* fprev, double* partials, hipStream_t st) {
   using C = Cfg<N>;
+  if (N == 512) {
+    const size_t sh = sizeof(float2) * (512 + 16 * 272);
+    hipLaunchKernelGGL((k_xpass256<XMODE, NC>), dim3(N * N / 16), dim3(256), sh, st, spec, g.comp_stride, g.P,
+                       real, real_cs, g.tw, mu_mode, inv_a0, fprev, partials);
+    return hipGetLastError();
+  }
   const int blocks = N * N / C::ROWS;
-  const size_t sh = sizeof(float2) * (size_t)(C::H + 1) * (NC * C::ROWS + 1);
+  const size_t sh = sizeof(float2) * ((size_t)(C::H + 1) * (NC * C::ROWS + 1) + N);
   hipLaunchKernelGGL((k_xpass<C::H, C::ROWS, NC, kNT, XMODE>), dim3(blocks), dim3(kNT), sh, st, spec,
                      g.comp_stride, g.P, real, real_cs, g.tw, mu_mode, inv_a0, fprev, partials);
   return hipGetLastError();
@@ -472,7 +637,7 @@ hipError_t launch_z(const FftGeom& g, ZArgs a, hipStream_t st) {
   a.comp_stride = g.comp_stride;
   a.P = g.P;
   a.ncols = C::H + 1;
-  hipLaunchKernelGGL((k_zpass<N, C::TZ, kNT, ZOP>), dim3(tiles, N), dim3(kNT), sh, st, a, g.tw);
+  hipLaunchKernelGGL((k_zpass<N, C::TZ, kNTZ, ZOP>), dim3(tiles, N), dim3(kNTZ), sh, st, a, g.tw);
   return hipGetLastError();
 }
 
@@ -504,6 +669,7 @@ hipError_t run_pass(const FftGeom& g, const PassDesc& d, hipStream_t st) {
 }  // namespace
 
 int x_blocks(int N) {
+  if (N == 512) return N * N / 16;
   const int H = N / 2;
   int rows = 1024 / H;
   rows = rows < 1 ? 1 : (rows > 64 ? 64 : rows);

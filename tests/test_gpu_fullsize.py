@@ -1,0 +1,150 @@
+"""Parity at the throughput workload's full size: 256^3 grid in a 512^3 FFT
+box, 2^20 particles of the isothermal sphere, in the launch configuration the
+benchmark times.
+
+Whole-field checks where the FP64 oracle fits in seconds (one 3D transform,
+a solve with one or two iterations), sampled outputs otherwise: the density
+at cells the oracle recomputes one by one from the particles whose ball
+contains them, and the forces of sampled particles.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import pm as orc  # noqa: E402
+import workloads as W  # noqa: E402
+from tests.gpu_util import dev, host, oparams, rel_l2, rel_max, grid  # noqa: E402
+
+N = 512
+
+
+def _log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def M():
+    from paper_2312_02968_amd import mondpm
+    mondpm.lib()
+    return mondpm
+
+
+@pytest.fixture(scope="module")
+def iso():
+    return W.isothermal_sphere(seed=0)
+
+
+@pytest.fixture(scope="module")
+def rho_sub(iso):
+    """Oracle density of a 2^14-particle subsample carrying the full mass."""
+    p = oparams(iso["params"])
+    idx = np.random.default_rng(1).choice(len(iso["mass"]), 1 << 14, replace=False)
+    m = iso["mass"].astype(np.float64)[idx] * (len(iso["mass"]) / len(idx))
+    return orc.deposit(p, iso["pos"].astype(np.float64)[idx], m).astype(np.float32)
+
+
+@pytest.mark.timeout(300)
+def test_fft_512(M):
+    _log("fft 512")
+    rng = np.random.default_rng(512)
+    x = rng.standard_normal((N, N, N)).astype(np.float32)
+    ctx = M.pm_create(W.params(256), 0)
+    P = M.pm_spectrum_pitch(N)
+    spec = torch.zeros(N * N * P * 2, dtype=torch.float32, device="cuda")
+    M.pm_fft_r2c(ctx, dev(x), spec)
+    s = host(spec).reshape(N, N, P, 2)
+    got = s[:, :, : N // 2 + 1, 0] + 1j * s[:, :, : N // 2 + 1, 1]
+    del s
+    import scipy.fft as sfft
+    ref = sfft.rfftn(x.astype(np.float64), workers=orc.WORKERS)
+    assert rel_l2(got, ref) < 3e-6
+    del got, ref
+    out = grid(N)
+    M.pm_fft_c2r(ctx, spec, out)
+    back = host(out).reshape(N, N, N) / N ** 3
+    assert rel_l2(back, x) < 3e-6
+    ctx.close()
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("K", [1, 2])
+def test_solve_512(M, iso, rho_sub, K):
+    _log("solve 512 K", K)
+    p = dict(iso["params"], iters=K, flags=M.PM_F_RESIDUAL)
+    phi_ref, info_ref = orc.aqual_solve(oparams(p), rho_sub.astype(np.float64))
+    ctx = M.pm_create(p, 0)
+    phi = grid(N)
+    info = M.aqual_solve(ctx, dev(rho_sub), phi)
+    got = host(phi).reshape(N, N, N)
+    assert rel_l2(got, phi_ref) < 1e-5
+    assert rel_max(got, phi_ref) < 1e-5
+    for a, b in zip(info["residuals"], info_ref.residuals):
+        assert a == pytest.approx(b, rel=1e-3)
+    ctx.close()
+
+
+def _oracle_rho_at(p, pos, mass, cells):
+    """rho at the given grid cells (z, y, x) from the particles whose ball covers them."""
+    out = np.zeros(len(cells))
+    x = pos / p.s
+    c = np.floor(x + 0.5).astype(np.int64) + p.n_pad // 2
+    R2 = (p.cutoff * p.sigma) ** 2
+    for t, (cz, cy, cx) in enumerate(cells):
+        d = np.stack([cx - c[:, 0], cy - c[:, 1], cz - c[:, 2]], axis=1)
+        sel = np.nonzero((d * d).sum(1) < R2)[0]
+        if len(sel) == 0:
+            continue
+        idx, w = orc.kernel_weights(p, pos[sel])
+        hit = (idx[..., 0] == cx) & (idx[..., 1] == cy) & (idx[..., 2] == cz)
+        out[t] = (mass[sel][:, None] * w * hit).sum() / p.s ** 3
+    return out
+
+
+@pytest.mark.timeout(300)
+def test_deposit_512_sampled(M, iso):
+    _log("deposit 512 sampled")
+    p = iso["params"]
+    n = len(iso["mass"])
+    ctx = M.pm_create(p, n)
+    rho = grid(N)
+    M.pm_deposit(ctx, dev(iso["pos"]), dev(iso["mass"]), rho)
+    got = host(rho).reshape(N, N, N)
+    # total mass and samples: 96 cells of the densest region, 96 random cells
+    # inside the physical region, 32 random cells in the margin
+    assert abs(got.sum() - iso["mass"].sum()) < 1e-5 * iso["mass"].sum()
+    rng = np.random.default_rng(7)
+    flat = np.argsort(got.ravel())[-2000:]
+    dense = np.array(np.unravel_index(rng.choice(flat, 96, replace=False), got.shape)).T
+    inner = rng.integers(N // 2 - 60, N // 2 + 60, (96, 3))
+    outer = rng.integers(0, N, (32, 3))
+    cells = np.concatenate([dense, inner, outer])
+    ref = _oracle_rho_at(oparams(p), iso["pos"].astype(np.float64), iso["mass"].astype(np.float64), cells)
+    val = got[cells[:, 0], cells[:, 1], cells[:, 2]]
+    scale = got.max()
+    assert np.max(np.abs(val - ref)) < 1e-6 * scale
+    ctx.close()
+
+
+@pytest.mark.timeout(300)
+def test_gather_512_sampled(M, iso, rho_sub):
+    _log("gather 512 sampled")
+    p = dict(iso["params"], iters=1)
+    phi_ref, _ = orc.aqual_solve(oparams(p), rho_sub.astype(np.float64))
+    phi32 = phi_ref.astype(np.float32)
+    del phi_ref
+    n = len(iso["mass"])
+    ctx = M.pm_create(p, n)
+    acc = torch.zeros(3 * n, dtype=torch.float32, device="cuda")
+    M.smooth_accel(ctx, dev(phi32), dev(iso["pos"]), acc)
+    got = host(acc).reshape(-1, 3)
+    idx = np.random.default_rng(3).choice(n, 4096, replace=False)
+    ref = orc.smooth_accel(oparams(p), phi32.astype(np.float64), iso["pos"][idx].astype(np.float64))
+    assert rel_l2(got[idx], ref) < 1e-5
+    assert rel_max(got[idx], ref) < 1e-5
+    ctx.close()
