@@ -232,6 +232,24 @@ struct PlanAt<L, REV, 0> {
   static constexpr int Ns = 1;
 };
 
+// LDS address of element i of column q in the exchange buffer.  For 8-column
+// tiles the rows are 16 dwords and a padding row follows every 8 rows, so the
+// row sets a stage touches together (8 apart on the write side of the first
+// stage, consecutive elsewhere) fall on different bank quarters; wider tiles
+// pad each row by one element.
+#ifndef PM_ZSKEW
+#define PM_ZSKEW 0
+#endif
+template <int S>
+__device__ __forceinline__ int col_addr(int i, int q) {
+  if constexpr (S == 8 && PM_ZSKEW) return (i + (i >> 3)) * 8 + q;
+  else return i * (S + 1) + q;
+}
+template <int L, int S>
+struct ColBuf {
+  static constexpr int elems = (S == 8 && PM_ZSKEW) ? (L + L / 8) * 8 : L * (S + 1);
+};
+
 // Register elements per thread: the largest BPT * R over the stages of the
 // plan (when a stage has fewer butterflies than threads, a thread still holds
 // one whole butterfly).
@@ -291,7 +309,7 @@ __device__ __forceinline__ void reg_to_lds(const float2* v, float2* buf) {
     const int q = b % S, j = b / S, k = j % Ns;
     const int base = (j - k) * R + k;
 #pragma unroll
-    for (int r = 0; r < R; ++r) buf[(base + r * Ns) * IS + q] = v[u * R + r];
+    for (int r = 0; r < R; ++r) buf[col_addr<S>(base + r * Ns, q)] = v[u * R + r];
   }
 }
 
@@ -306,7 +324,7 @@ __device__ __forceinline__ void lds_to_reg(float2* v, const float2* buf) {
     if (!B::valid(b)) continue;
     const int q = b % S, j = b / S;
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[u * R + r] = buf[(j + r * (L / R)) * IS + q];
+    for (int r = 0; r < R; ++r) v[u * R + r] = buf[col_addr<S>(j + r * (L / R), q)];
   }
 }
 

@@ -19,7 +19,24 @@
 #include "pm_device.h"
 #include "pm_internal.h"
 
+// Tile widths (kx columns per block) of the y and z passes and the z pass's
+// block size; compile-time launch shapes, chosen by measurement.
+#ifndef PM_TY
+#define PM_TY 8
+#endif
+#ifndef PM_TZ
+#define PM_TZ 8
+#endif
+#ifndef PM_NTZ
+#define PM_NTZ 512
+#endif
+#ifndef PM_HZ
+#define PM_HZ 1
+#endif
+
 namespace pm {
+
+int z_blocks(int N);
 
 // ----------------------------------------------------------------------------
 // x pass
@@ -284,7 +301,7 @@ __global__ __launch_bounds__(256) void k_xpass256(float2* spec, long long comp_s
     for (int c = 0; c < NC; ++c) fft256_group<true>(v[c], xb, j, tw_s);
   }
 
-  if (XMODE == X_FUSED_NU || XMODE == X_FUSED_MU) {
+  if constexpr (XMODE == X_FUSED_NU || XMODE == X_FUSED_MU) {
     double acc = 0.0;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
@@ -360,11 +377,11 @@ __device__ __forceinline__ void load_twiddles(float2* tw_s, const float2* __rest
   for (int t = threadIdx.x; t < L; t += NT) tw_s[t] = tw[t];
 }
 
-// Loads the first-stage inputs (radix R) of column q = b mod T from
-// src + i * row_stride + q for the NC components, zero for q >= nv.
-template <int L, int T, int NT, int R>
-__device__ __forceinline__ void load_cols(float2* v, int E, const float2* const* src, int nc, long long row_stride,
-                                          int nv) {
+// Loads the first-stage inputs (radix R) of column q = b mod T of each
+// component c from src[c] + i * row_stride + q; zero for q >= nv[c].
+template <int L, int T, int NT, int R, int NC>
+__device__ __forceinline__ void load_cols(float2* v, int E, const float2* const* src, const int* nv,
+                                          long long row_stride) {
   using B = Bfly<L, T, NT, R>;
 #pragma unroll
   for (int u = 0; u < B::BPT; ++u) {
@@ -374,49 +391,53 @@ __device__ __forceinline__ void load_cols(float2* v, int E, const float2* const*
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const long long off = (long long)(j + r * (L / R)) * row_stride + q;
-      for (int c = 0; c < nc; ++c)
-        v[c * E + u * R + r] = (q < nv) ? src[c][off] : make_float2(0.0f, 0.0f);
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        v[c * E + u * R + r] = (q < nv[c]) ? src[c][off] : make_float2(0.0f, 0.0f);
     }
   }
 }
 
-template <int L, int T, int NT, int R>
-__device__ __forceinline__ void store_cols(const float2* v, int E, float2* const* dst, int nc, long long row_stride,
-                                           int nv) {
+template <int L, int T, int NT, int R, int NC>
+__device__ __forceinline__ void store_cols(const float2* v, int E, float2* const* dst, const int* nv,
+                                           long long row_stride) {
   using B = Bfly<L, T, NT, R>;
 #pragma unroll
   for (int u = 0; u < B::BPT; ++u) {
     const int b = threadIdx.x + u * NT;
     if (!B::valid(b)) continue;
     const int q = b % T, j = b / T;
-    if (q >= nv) continue;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const long long off = (long long)(j + r * (L / R)) * row_stride + q;
-      for (int c = 0; c < nc; ++c) dst[c][off] = v[c * E + u * R + r];
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        if (q < nv[c]) dst[c][off] = v[c * E + u * R + r];
     }
   }
 }
 
+// y pass: a tile of 2 T columns of one z plane, handled as two halves of T
+// columns that share the LDS exchange buffer (the halves of one 128-byte line
+// are loaded and stored together, the buffer holds only T columns).
 template <int L, int T, int NT, bool INV>
 __global__ __launch_bounds__(NT) void k_ypass(float2* spec, long long comp_stride, int P, int ncols,
                                               const float2* __restrict__ tw) {
   constexpr int E = ColCfg<L, T, NT>::E;
   extern __shared__ float2 lds[];
-  float2* tw_s = lds + L * (T + 1);
-  const int x0 = blockIdx.x * T;
-  const int nv = min(T, ncols - x0);
+  float2* tw_s = lds + ColBuf<L, T>::elems;
+  const int x0 = blockIdx.x * 2 * T;
   float2* base = spec + blockIdx.z * comp_stride + (long long)blockIdx.y * L * P + x0;
   load_twiddles<L>(tw_s, tw, NT);
-  float2 v[E];
+  float2 v[2 * E];
   using First = PlanAt<L, false, 0>;
   using Last = PlanAt<L, false, Plan<L>::S - 1>;
-  const float2* src[1] = {base};
-  load_cols<L, T, NT, First::R>(v, E, src, 1, P, nv);
+  const int nv[2] = {min(T, ncols - x0), min(T, ncols - x0 - T)};
+  float2* ptr[2] = {base, base + T};
+  load_cols<L, T, NT, First::R, 2>(v, E, ptr, nv, P);
   __syncthreads();
-  col_fft<L, T, NT, 1, INV, false>(v, lds, tw_s, 1);
-  float2* dst[1] = {base};
-  store_cols<L, T, NT, Last::R>(v, E, dst, 1, P, nv);
+  col_fft<L, T, NT, 2, INV, false>(v, lds, tw_s, 1);
+  store_cols<L, T, NT, Last::R, 2>(v, E, ptr, nv, P);
 }
 
 enum { Z_FWD = 0, Z_INV = 1, Z_NEWTON = 2, Z_CURL = 3, Z_CURL_FINAL = 4, Z_DIV = 5, Z_NEWTON_H0 = 6 };
@@ -431,7 +452,10 @@ template <> struct ZComp<Z_CURL_FINAL> { static constexpr int IN = 3, OUT = 1; }
 template <> struct ZComp<Z_DIV>        { static constexpr int IN = 3, OUT = 3; };
 
 // z pass: forward z transform of the input components, the spectral operator
-// at every (kx, ky, kz) in registers, inverse z transform, store.
+// at every (kx, ky, kz) in registers, inverse z transform, store.  A block
+// owns 2 T kx-columns of one ky row as two halves of T columns (slot 2 c + h
+// holds field component c of half h); the halves share the LDS exchange
+// buffer, and together they read and write whole 128-byte lines.
 //   Z_NEWTON    : in = rho_hat (x, y transformed, in phiN); stores phi_N_hat =
 //                 -4 pi G A rho_hat into phiN and outputs g_N_hat = -i kappa
 //                 phi_N_hat (/N^3) as three components; accumulates the
@@ -440,44 +464,55 @@ template <> struct ZComp<Z_DIV>        { static constexpr int IN = 3, OUT = 3; }
 //   Z_CURL      : g <- kt At (kt . g) / N^3
 //   Z_CURL_FINAL: phi_hat = i At (kt . g) / N^3 (one output component)
 //   Z_DIV       : F = F' + kt At kt . (g_N - F'), g_N = -i kappa phi_N (/N^3)
-template <int L, int T, int NT, int ZOP>
+template <int L, int T, int NT, int HZ, int ZOP>
 __global__ __launch_bounds__(NT) void k_zpass(ZArgs a, const float2* __restrict__ tw) {
   constexpr int E = ColCfg<L, T, NT>::E;
   constexpr int NIN = ZComp<ZOP>::IN, NOUT = ZComp<ZOP>::OUT;
   constexpr int NV = NIN > NOUT ? NIN : NOUT;
   extern __shared__ float2 lds[];
-  float2* tw_s = lds + L * (T + 1);
-  const int x0 = blockIdx.x * T;
-  const int y = blockIdx.y;
-  const int nv = min(T, a.ncols - x0);
+  float2* tw_s = lds + ColBuf<L, T>::elems;
+  const int ntile = (a.ncols + HZ * T - 1) / (HZ * T);
+  const int tile = blockIdx.x % ntile, y = blockIdx.x / ntile;
+  const int x0 = tile * HZ * T;
   const long long row = (long long)L * a.P;
   const long long off = (long long)y * a.P + x0;
   load_twiddles<L>(tw_s, tw, NT);
+  int nvh[HZ];
+#pragma unroll
+  for (int h = 0; h < HZ; ++h) nvh[h] = min(T, a.ncols - x0 - h * T);
 
-  float2 v[NV * E];
+  float2 v[HZ * NV * E];
   using First = PlanAt<L, false, 0>;
   using Last = PlanAt<L, false, Plan<L>::S - 1>;
-  const float2* src[4];
-  if (ZOP == Z_NEWTON || ZOP == Z_NEWTON_H0) {
-    src[0] = a.phiN + off;
-    for (int c = 1; c < NIN; ++c) src[c] = a.spec + (c - 1) * a.comp_stride + off;
-  } else {
-    for (int c = 0; c < NIN; ++c) src[c] = a.spec + c * a.comp_stride + off;
+  const float2* src[HZ * NIN];
+  int nvs[HZ * NV];
+#pragma unroll
+  for (int c = 0; c < NV; ++c)
+#pragma unroll
+    for (int h = 0; h < HZ; ++h) nvs[HZ * c + h] = nvh[h];
+#pragma unroll
+  for (int c = 0; c < NIN; ++c) {
+    const float2* p = (ZOP == Z_NEWTON || ZOP == Z_NEWTON_H0)
+                          ? (c == 0 ? a.phiN + off : a.spec + (c - 1) * a.comp_stride + off)
+                          : a.spec + c * a.comp_stride + off;
+#pragma unroll
+    for (int h = 0; h < HZ; ++h) src[HZ * c + h] = p + h * T;
   }
+  float2* dst1[HZ];
+#pragma unroll
+  for (int h = 0; h < HZ; ++h) dst1[h] = a.spec + off + h * T;
   if (ZOP == Z_INV) {
-    load_cols<L, T, NT, First::R>(v, E, src, NIN, row, nv);
+    load_cols<L, T, NT, First::R, HZ>(v, E, src, nvs, row);
     __syncthreads();
-    col_fft<L, T, NT, 1, true, false>(v, lds, tw_s, 1);
-    float2* dst[1] = {a.spec + off};
-    store_cols<L, T, NT, Last::R>(v, E, dst, 1, row, nv);
+    col_fft<L, T, NT, HZ, true, false>(v, lds, tw_s, 1);
+    store_cols<L, T, NT, Last::R, HZ>(v, E, dst1, nvs, row);
     return;
   }
-  load_cols<L, T, NT, First::R>(v, E, src, NIN, row, nv);
+  load_cols<L, T, NT, First::R, HZ * NIN>(v, E, src, nvs, row);
   __syncthreads();
-  col_fft<L, T, NT, NIN, false, false>(v, lds, tw_s, 1);
+  col_fft<L, T, NT, HZ * NIN, false, false>(v, lds, tw_s, 1);
   if (ZOP == Z_FWD) {
-    float2* dst[1] = {a.spec + off};
-    store_cols<L, T, NT, Last::R>(v, E, dst, 1, row, nv);
+    store_cols<L, T, NT, Last::R, HZ>(v, E, dst1, nvs, row);
     return;
   }
 
@@ -491,61 +526,68 @@ __global__ __launch_bounds__(NT) void k_zpass(ZArgs a, const float2* __restrict_
     const int b = threadIdx.x + u * NT;
     if (!BL::valid(b)) continue;
     const int q = b % T, j = b / T;
-    const int kxi = x0 + q;
-    const bool inb = q < nv;
-    const float kx = a.kv[kxi < L ? kxi : 0];
-    const float tx = (kxi < L / 2) ? a.kt[kxi] : 0.0f;
-    const float kpx = (kxi < L / 2) ? a.kap[kxi] : 0.0f;
 #pragma unroll
-    for (int r = 0; r < RL; ++r) {
-      const int kz = j + r * (L / RL);
-      const int e = u * RL + r;
-      if (ZOP == Z_NEWTON || ZOP == Z_NEWTON_H0) {
-        const float kzz = a.kv[kz];
-        const float k2 = kx * kx + ky * ky + kzz * kzz;
-        const float A = (k2 > 0.0f) ? 1.0f / k2 : 0.0f;
-        const float2 ph = cscale(v[e], a.newton_coef * A);     // phi_N hat (raw DFT)
-        if (inb) a.phiN[(long long)kz * row + off + q] = ph;
-        const float kpz = a.kap[kz];
-        const float2 g = cscale(mul_mi<false>(ph), a.scale);
-        float2 o0 = cscale(g, kpx), o1 = cscale(g, kapy), o2 = cscale(g, kpz);
-        if (ZOP == Z_NEWTON_H0) {
-          o0 = cadd(o0, cscale(v[1 * E + e], a.scale));
-          o1 = cadd(o1, cscale(v[2 * E + e], a.scale));
-          o2 = cadd(o2, cscale(v[3 * E + e], a.scale));
-        }
-        v[e] = o0;
-        v[E + e] = o1;
-        v[2 * E + e] = o2;
-        if (inb) {
-          const double w = (kxi == 0 || kxi == L / 2) ? 1.0 : 2.0;
-          const double m2 = (double)ph.x * ph.x + (double)ph.y * ph.y;
-          acc += w * m2 * ((double)kpx * kpx + (double)kapy * kapy + (double)kpz * kpz);
-        }
-      } else {
-        const float tz = a.kt[kz];
-        const float t2 = tx * tx + ty * ty + tz * tz;
-        const float At = (t2 > 0.0f) ? 1.0f / t2 : 0.0f;
-        float2 g0 = v[e], g1 = v[E + e], g2 = v[2 * E + e];
-        if (ZOP == Z_DIV) {
-          const float2 ph = inb ? a.phiN[(long long)kz * row + off + q] : make_float2(0.0f, 0.0f);
-          const float2 mph = mul_mi<false>(ph);
-          const float2 d0 = csub(cscale(mph, kpx), g0);
-          const float2 d1 = csub(cscale(mph, kapy), g1);
-          const float2 d2 = csub(cscale(mph, a.kap[kz]), g2);
-          const float2 dd = cscale(cadd(cadd(cscale(d0, tx), cscale(d1, ty)), cscale(d2, tz)), At);
-          v[e] = cscale(cadd(g0, cscale(dd, tx)), a.scale);
-          v[E + e] = cscale(cadd(g1, cscale(dd, ty)), a.scale);
-          v[2 * E + e] = cscale(cadd(g2, cscale(dd, tz)), a.scale);
+    for (int h = 0; h < HZ; ++h) {
+      const int kxi = x0 + h * T + q;
+      const bool inb = q < nvh[h];
+      const float kx = a.kv[kxi < L ? kxi : 0];
+      const float tx = (kxi < L / 2) ? a.kt[kxi] : 0.0f;
+      const float kpx = (kxi < L / 2) ? a.kap[kxi] : 0.0f;
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        const int kz = j + r * (L / RL);
+        const int e = u * RL + r;
+        float2* v0 = v + (0 * HZ + h) * E + e;
+        float2* v1 = v + (1 * HZ + h) * E + e;
+        float2* v2 = v + (2 * HZ + h) * E + e;
+        if (ZOP == Z_NEWTON || ZOP == Z_NEWTON_H0) {
+          const float kzz = a.kv[kz];
+          const float k2 = kx * kx + ky * ky + kzz * kzz;
+          const float A = (k2 > 0.0f) ? 1.0f / k2 : 0.0f;
+          const float2 ph = cscale(*v0, a.newton_coef * A);     // phi_N hat (raw DFT)
+          if (inb) a.phiN[(long long)kz * row + off + h * T + q] = ph;
+          const float kpz = a.kap[kz];
+          const float2 g = cscale(mul_mi<false>(ph), a.scale);
+          float2 o0 = cscale(g, kpx), o1 = cscale(g, kapy), o2 = cscale(g, kpz);
+          if (ZOP == Z_NEWTON_H0) {
+            // H0 components arrived in input slots 1..3 (component c at slot HZ c + h)
+            o0 = cadd(o0, cscale(v[(1 * HZ + h) * E + e], a.scale));
+            o1 = cadd(o1, cscale(v[(2 * HZ + h) * E + e], a.scale));
+            o2 = cadd(o2, cscale(v[(3 * HZ + h) * E + e], a.scale));
+          }
+          *v0 = o0;
+          *v1 = o1;
+          *v2 = o2;
+          if (inb) {
+            const double w = (kxi == 0 || kxi == L / 2) ? 1.0 : 2.0;
+            const double m2 = (double)ph.x * ph.x + (double)ph.y * ph.y;
+            acc += w * m2 * ((double)kpx * kpx + (double)kapy * kapy + (double)kpz * kpz);
+          }
         } else {
-          const float2 dot = cadd(cadd(cscale(g0, tx), cscale(g1, ty)), cscale(g2, tz));
-          if (ZOP == Z_CURL) {
-            const float2 sc = cscale(dot, At * a.scale);
-            v[e] = cscale(sc, tx);
-            v[E + e] = cscale(sc, ty);
-            v[2 * E + e] = cscale(sc, tz);
+          const float tz = a.kt[kz];
+          const float t2 = tx * tx + ty * ty + tz * tz;
+          const float At = (t2 > 0.0f) ? 1.0f / t2 : 0.0f;
+          const float2 g0 = *v0, g1 = *v1, g2 = *v2;
+          if (ZOP == Z_DIV) {
+            const float2 ph = inb ? a.phiN[(long long)kz * row + off + h * T + q] : make_float2(0.0f, 0.0f);
+            const float2 mph = mul_mi<false>(ph);
+            const float2 d0 = csub(cscale(mph, kpx), g0);
+            const float2 d1 = csub(cscale(mph, kapy), g1);
+            const float2 d2 = csub(cscale(mph, a.kap[kz]), g2);
+            const float2 dd = cscale(cadd(cadd(cscale(d0, tx), cscale(d1, ty)), cscale(d2, tz)), At);
+            *v0 = cscale(cadd(g0, cscale(dd, tx)), a.scale);
+            *v1 = cscale(cadd(g1, cscale(dd, ty)), a.scale);
+            *v2 = cscale(cadd(g2, cscale(dd, tz)), a.scale);
           } else {
-            v[e] = cscale(mul_mi<true>(dot), At * a.scale);    // phi_hat = i At kt.g
+            const float2 dot = cadd(cadd(cscale(g0, tx), cscale(g1, ty)), cscale(g2, tz));
+            if (ZOP == Z_CURL) {
+              const float2 sc = cscale(dot, At * a.scale);
+              *v0 = cscale(sc, tx);
+              *v1 = cscale(sc, ty);
+              *v2 = cscale(sc, tz);
+            } else {
+              *v0 = cscale(mul_mi<true>(dot), At * a.scale);    // phi_hat = i At kt.g
+            }
           }
         }
       }
@@ -559,16 +601,19 @@ __global__ __launch_bounds__(NT) void k_zpass(ZArgs a, const float2* __restrict_
     if (threadIdx.x == 0) {
       double t = 0.0;
       for (int w = 0; w < NT / 64; ++w) t += red[w];
-      a.partials[blockIdx.y * gridDim.x + blockIdx.x] = t;
+      a.partials[blockIdx.x] = t;
     }
   }
 
   // ---- inverse z transform with the reversed plan: its first stage takes the
   // elements the forward last stage produced, so no exchange is needed here.
-  col_fft<L, T, NT, NOUT, true, true>(v, lds, tw_s, 1);
-  float2* dst[3];
-  for (int c = 0; c < NOUT; ++c) dst[c] = a.spec + c * a.comp_stride + off;
-  store_cols<L, T, NT, First::R>(v, E, dst, NOUT, row, nv);
+  col_fft<L, T, NT, HZ * NOUT, true, true>(v, lds, tw_s, 1);
+  float2* dst[HZ * NOUT];
+#pragma unroll
+  for (int c = 0; c < NOUT; ++c)
+#pragma unroll
+    for (int h = 0; h < HZ; ++h) dst[HZ * c + h] = a.spec + c * a.comp_stride + off + h * T;
+  store_cols<L, T, NT, First::R, HZ * NOUT>(v, E, dst, nvs, row);
 }
 
 // Sum of partials[0..n) into out[0] (FP64), one block.
@@ -592,14 +637,14 @@ __global__ __launch_bounds__(1024) void k_reduce_partials(const double* __restri
 // ----------------------------------------------------------------------------
 namespace {
 constexpr int kNT = 256;
-constexpr int kNTZ = 512;
+constexpr int kNTZ = PM_NTZ;
 
 template <int N>
 struct Cfg {
   static constexpr int H = N / 2;
   static constexpr int ROWS = (1024 / H) < 1 ? 1 : ((1024 / H) > 64 ? 64 : (1024 / H));
-  static constexpr int TY = 16;
-  static constexpr int TZ = 8;
+  static constexpr int TY = PM_TY;
+  static constexpr int TZ = PM_TZ;
 };
 
 template <int N, int XMODE, int NC>
@@ -622,8 +667,8 @@ hipError_t launch_x(const FftGeom& g, float2* spec, float* real, long long real_
 template <int N, bool INV>
 hipError_t launch_y(const FftGeom& g, float2* spec, int ncomp, hipStream_t st) {
   using C = Cfg<N>;
-  const int tiles = (C::H + 1 + C::TY - 1) / C::TY;
-  const size_t sh = sizeof(float2) * ((size_t)N * (C::TY + 1) + N);
+  const int tiles = (C::H + 1 + 2 * C::TY - 1) / (2 * C::TY);
+  const size_t sh = sizeof(float2) * ((size_t)ColBuf<N, C::TY>::elems + N);
   hipLaunchKernelGGL((k_ypass<N, C::TY, kNT, INV>), dim3(tiles, N, ncomp), dim3(kNT), sh, st, spec,
                      g.comp_stride, g.P, C::H + 1, g.tw);
   return hipGetLastError();
@@ -632,12 +677,11 @@ hipError_t launch_y(const FftGeom& g, float2* spec, int ncomp, hipStream_t st) {
 template <int N, int ZOP>
 hipError_t launch_z(const FftGeom& g, ZArgs a, hipStream_t st) {
   using C = Cfg<N>;
-  const int tiles = (C::H + 1 + C::TZ - 1) / C::TZ;
-  const size_t sh = sizeof(float2) * ((size_t)N * (C::TZ + 1) + N);
+  const size_t sh = sizeof(float2) * ((size_t)ColBuf<N, C::TZ>::elems + N);
   a.comp_stride = g.comp_stride;
   a.P = g.P;
   a.ncols = C::H + 1;
-  hipLaunchKernelGGL((k_zpass<N, C::TZ, kNTZ, ZOP>), dim3(tiles, N), dim3(kNTZ), sh, st, a, g.tw);
+  hipLaunchKernelGGL((k_zpass<N, C::TZ, kNTZ, PM_HZ, ZOP>), dim3(z_blocks(N)), dim3(kNTZ), sh, st, a, g.tw);
   return hipGetLastError();
 }
 
@@ -677,8 +721,8 @@ int x_blocks(int N) {
 }
 int z_blocks(int N) {
   const int H = N / 2;
-  const int tz = 8;
-  return ((H + 1 + tz - 1) / tz) * N;
+  const int w = PM_TZ * PM_HZ;
+  return ((H + 1 + w - 1) / w) * N;
 }
 
 hipError_t fft_pass(const FftGeom& g, const PassDesc& d, hipStream_t st) {
