@@ -6,7 +6,7 @@
 
 #include <vector>
 
-#include "../../include/mondpm.h"
+#include "mondpm.h"
 #include "pm_internal.h"
 
 using namespace pm;
@@ -47,6 +47,7 @@ struct pm_ctx {
   float* kap = nullptr;
   int* ball = nullptr;
   int* ibuf = nullptr;        // sort buffers
+  double* snorm = nullptr;    // per-particle kernel normalisation (pm_step: deposit -> gather)
   std::vector<void*> allocs;
   FftGeom fg{};
   KernelGeom kg{};
@@ -204,7 +205,8 @@ pm_status pm_create(const pm_params* p, int64_t max_particles, void* stream, pm_
   const int ext = ball_extent(Rb);
   const size_t lds_need = sizeof(float) * (((ball.size() + 3) & ~(size_t)3) + (size_t)(8 + 2 * (ext + 1)) *
                                                                                    (8 + 2 * (ext + 1)) * (8 + 2 * (ext + 1)));
-  if (lds_need > prop.sharedMemPerBlock) {
+  // plus the per-block chunk plan of the particle kernels (4 lists of 512 ints)
+  if (lds_need + 4 * 512 * sizeof(int) + 64 > prop.sharedMemPerBlock) {
     delete c;
     return inval("kernel ball too large for the LDS of this device");
   }
@@ -230,6 +232,7 @@ pm_status pm_create(const pm_params* p, int64_t max_particles, void* stream, pm_
   const size_t mp = (size_t)(max_particles > 0 ? max_particles : 1);
   const size_t nb = ((size_t)ntiles + 1023) / 1024;
   ALLOC(c->ibuf, 4 * mp + 2 * ((size_t)ntiles + 1) + nb + 16);
+  ALLOC(c->snorm, mp);
 #undef ALLOC
   if (hipHostMalloc(reinterpret_cast<void**>(&c->hacc), 128 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
     pm_destroy(c);
@@ -270,6 +273,11 @@ pm_status pm_create(const pm_params* p, int64_t max_particles, void* stream, pm_
   c->kg.ball = c->ball;
   c->kg.analytic = (p->flags & PM_F_ANALYTIC_NORM) ? 1 : 0;
   c->kg.analytic_norm = pow(2.0 * M_PI, 1.5) * p->sigma * p->sigma * p->sigma;
+  {
+    // one deposit tile copy per wave when four copies fit in 96 KB of LDS
+    const size_t te = 8 + 2 * (size_t)ext;
+    c->kg.private_tiles = (4 * te * te * te * sizeof(float) <= 96 * 1024) ? 1 : 0;
+  }
 
   int* ib = c->ibuf;
   c->sb.keys = ib; ib += mp;
@@ -454,7 +462,7 @@ pm_status pm_deposit(pm_ctx* c, const float* pos, const float* mass, int64_t n, 
   const long long R = (long long)c->N * c->N * c->N;
   { Timed t(c, PM_T_FILL); HIPCHK(fill_zero(rho, R, c->st)); }
   { Timed t(c, PM_T_SORT); HIPCHK(sort_particles(c->kg, c->sb, pos, n, c->st)); }
-  { Timed t(c, PM_T_DEPOSIT); HIPCHK(deposit_sorted(c->kg, c->sb, pos, mass, n, rho, c->st)); }
+  { Timed t(c, PM_T_DEPOSIT); HIPCHK(deposit_sorted(c->kg, c->sb, pos, mass, n, rho, nullptr, c->st)); }
   return PM_OK;
 }
 
@@ -464,7 +472,8 @@ pm_status smooth_accel(pm_ctx* c, const float* phi, const float* pos, int64_t n,
   if (!phi || (n > 0 && (!pos || !acc))) return inval("NULL buffer");
   { Timed t(c, PM_T_SORT); HIPCHK(sort_particles(c->kg, c->sb, pos, n, c->st)); }
   { Timed t(c, PM_T_GATHER);
-    HIPCHK(gather_sorted(c->kg, c->sb, phi, const_cast<float*>(pos), nullptr, acc, n, 0.f, 0.f, 0, c->st)); }
+    HIPCHK(gather_sorted(c->kg, c->sb, phi, const_cast<float*>(pos), nullptr, acc, n, 0.f, 0.f, 0, nullptr,
+                         c->st)); }
   return PM_OK;
 }
 
@@ -475,7 +484,8 @@ pm_status interp_push(pm_ctx* c, const float* phi, float* pos, float* vel, int64
   if (!phi || (n > 0 && (!pos || !vel))) return inval("NULL buffer");
   { Timed t(c, PM_T_SORT); HIPCHK(sort_particles(c->kg, c->sb, pos, n, c->st)); }
   { Timed t(c, PM_T_GATHER);
-    HIPCHK(gather_sorted(c->kg, c->sb, phi, pos, vel, nullptr, n, (float)dt_kick, (float)dt_drift, 1, c->st)); }
+    HIPCHK(gather_sorted(c->kg, c->sb, phi, pos, vel, nullptr, n, (float)dt_kick, (float)dt_drift, 1, nullptr,
+                         c->st)); }
   return PM_OK;
 }
 
@@ -488,11 +498,11 @@ pm_status pm_step(pm_ctx* c, float* pos, float* vel, const float* mass, int64_t 
   if (info) HIPCHK(fill_zero(reinterpret_cast<float*>(c->sb.flags), 1, c->st));
   { Timed t(c, PM_T_FILL); HIPCHK(fill_zero(c->rho, R, c->st)); }
   { Timed t(c, PM_T_SORT); HIPCHK(sort_particles(c->kg, c->sb, pos, n, c->st)); }
-  { Timed t(c, PM_T_DEPOSIT); HIPCHK(deposit_sorted(c->kg, c->sb, pos, mass, n, c->rho, c->st)); }
+  { Timed t(c, PM_T_DEPOSIT); HIPCHK(deposit_sorted(c->kg, c->sb, pos, mass, n, c->rho, c->snorm, c->st)); }
   s = run_solve(c, c->rho, nullptr, c->phi, info, info != nullptr);
   if (s != PM_OK) return s;
   { Timed t(c, PM_T_GATHER);
-    HIPCHK(gather_sorted(c->kg, c->sb, c->phi, pos, vel, nullptr, n, (float)dt, (float)dt, 1, c->st)); }
+    HIPCHK(gather_sorted(c->kg, c->sb, c->phi, pos, vel, nullptr, n, (float)dt, (float)dt, 1, c->snorm, c->st)); }
   if (info) {
     int flag = 0;
     HIPCHK(hipMemcpyAsync(&flag, c->sb.flags, sizeof(int), hipMemcpyDeviceToHost, c->st));

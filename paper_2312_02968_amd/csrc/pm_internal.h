@@ -67,6 +67,7 @@ struct KernelGeom {
   const int* ball;  // packed offsets (dx+16) | (dy+16) << 8 | (dz+16) << 16
   int analytic;     // literal prefactor instead of the ball-sum normalisation
   double analytic_norm;  // (2 pi)^1.5 sigma^3
+  int private_tiles;     // deposit: one LDS tile copy per wave (no LDS atomics)
 };
 
 struct SortBufs {
@@ -83,11 +84,14 @@ struct SortBufs {
 
 hipError_t sort_particles(const KernelGeom& kg, const SortBufs& sb, const float* pos, int64_t n,
                           hipStream_t st);
+// s_store (nullable): receives each particle's kernel normalisation (FP64)
 hipError_t deposit_sorted(const KernelGeom& kg, const SortBufs& sb, const float* pos, const float* mass,
-                          int64_t n, float* rho, hipStream_t st);
+                          int64_t n, float* rho, double* s_store, hipStream_t st);
 // mode 0: acc = g; mode 1: v += g dt_kick, r += v dt_drift
+// s_store (nullable): normalisations written by deposit_sorted for the same positions
 hipError_t gather_sorted(const KernelGeom& kg, const SortBufs& sb, const float* phi, float* pos, float* vel,
-                         float* acc, int64_t n, float dt_kick, float dt_drift, int mode, hipStream_t st);
+                         float* acc, int64_t n, float dt_kick, float dt_drift, int mode, const double* s_store,
+                         hipStream_t st);
 hipError_t fill_zero(float* p, long long count, hipStream_t st);
 hipError_t diagnostics(const KernelGeom& kg, const float* pos, const float* vel, const float* mass,
                        const float* phi, int64_t n, double* out_dev, hipStream_t st);

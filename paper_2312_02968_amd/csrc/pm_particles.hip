@@ -51,14 +51,15 @@ __device__ __forceinline__ void unpack(int e, int& dx, int& dy, int& dz) {
   dz = ((e >> 16) & 255) - 16;
 }
 
-// Central pixel and 1D weights of particle i, then S (all lanes take part).
-__device__ __forceinline__ Part particle_setup(const KernelGeom& kg, const int* __restrict__ ball_lds,
-                                               const float* __restrict__ pos, int i, int lane) {
+// Central pixel and 1D weights of the particle at (px, py, pz), then S (all
+// lanes take part; the coordinates are wave-uniform).
+__device__ __forceinline__ Part particle_setup(const KernelGeom& kg, const int* __restrict__ ball_lds, float px,
+                                               float py, float pz, int lane, bool with_sum = true) {
   const int W = 2 * kg.ext + 1;
   Part p;
-  const double ux = (double)pos[3 * i + 0] * kg.inv_s;
-  const double uy = (double)pos[3 * i + 1] * kg.inv_s;
-  const double uz = (double)pos[3 * i + 2] * kg.inv_s;
+  const double ux = (double)px * kg.inv_s;
+  const double uy = (double)py * kg.inv_s;
+  const double uz = (double)pz * kg.inv_s;
   const double cxd = floor(ux + 0.5), cyd = floor(uy + 0.5), czd = floor(uz + 0.5);
   const int half = kg.N / 2;
   p.cx = wrapi((int)cxd + half, kg.N);
@@ -69,6 +70,8 @@ __device__ __forceinline__ Part particle_setup(const KernelGeom& kg, const int* 
   const double frac = axis == 0 ? cxd - ux : (axis == 1 ? cyd - uy : czd - uz);
   const float d = (float)o + (float)frac;
   p.w1 = (axis < 3) ? expf(-d * d * kg.inv2sig2) : 0.0f;
+  p.S = 0.0;
+  if (!with_sum || kg.analytic) return p;
   double acc = 0.0;
   const int nit = (kg.nball + 63) / 64;
   for (int it = 0; it < nit; ++it) {
@@ -82,6 +85,11 @@ __device__ __forceinline__ Part particle_setup(const KernelGeom& kg, const int* 
   }
   p.S = wave_sum_d(acc);
   return p;
+}
+
+__device__ __forceinline__ Part particle_setup(const KernelGeom& kg, const int* __restrict__ ball_lds,
+                                               const float* __restrict__ pos, int i, int lane) {
+  return particle_setup(kg, ball_lds, pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], lane);
 }
 
 __global__ __launch_bounds__(256) void k_keys(const float* __restrict__ pos, int64_t n, int N, int nphys,
@@ -172,89 +180,232 @@ __global__ __launch_bounds__(256) void k_fill(float* p, long long count) {
 }
 
 // ---------------------------------------------------------------------------
+// Chunk plan.  A block owns kChunk consecutive particles of the sorted order.
+// Its particles fall into pieces (the part of a tile's segment inside the
+// chunk).  A piece whose balls cover more cells than the tile plus halo is
+// "dense" and goes through an LDS copy of the tile; the particles of the
+// other pieces form one flat "sparse" list that the waves share without
+// per-piece synchronisation.
+// ---------------------------------------------------------------------------
+struct ChunkPlan {
+  int nsparse;
+  int npieces;
+  int sparse[kChunk];    // sorted-order indices of sparse particles
+  int pstart[kChunk];    // dense pieces: [pstart, pend) of tile ptile
+  int pend[kChunk];
+  int ptile[kChunk];
+};
+
+__device__ __forceinline__ void plan_chunk(ChunkPlan& pl, const int* __restrict__ skey,
+                                           const int* __restrict__ offsets, int64_t a0, int64_t a1,
+                                           int64_t dense_min) {
+  if (threadIdx.x == 0) { pl.nsparse = 0; pl.npieces = 0; }
+  __syncthreads();
+  for (int64_t j = a0 + threadIdx.x; j < a1; j += kNT) {
+    const int t = skey[j];
+    const int64_t ps = max((int64_t)offsets[t], a0), pe = min((int64_t)offsets[t + 1], a1);
+    if (pe - ps < dense_min) {
+      pl.sparse[atomicAdd(&pl.nsparse, 1)] = (int)j;
+    } else if (j == ps) {
+      const int k = atomicAdd(&pl.npieces, 1);
+      pl.pstart[k] = (int)ps;
+      pl.pend[k] = (int)pe;
+      pl.ptile[k] = t;
+    }
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
 // deposit
 // ---------------------------------------------------------------------------
+// Deposits particle (x, y, z, m) of the wave: into the LDS tile (origin o*,
+// edge TE) when tile != nullptr, else straight into rho with global atomics.
+// LDS selects the tile path at compile time, so the tile pointer is known to
+// address LDS (ds_add_f32) rather than a generic address (flat atomics).
+template <bool LDS>
+__device__ __forceinline__ void deposit_one(const KernelGeom& kg, const int* __restrict__ ball, float x, float y,
+                                            float z, float m, double s3, float* tile, int TE, int ox, int oy,
+                                            int oz, float* rho, double* s_out, int lane) {
+  const int W = 2 * kg.ext + 1, N = kg.N;
+  const Part p = particle_setup(kg, ball, x, y, z, lane);
+  const double norm = kg.analytic ? kg.analytic_norm : p.S;
+  if (s_out != nullptr && lane == 0) *s_out = norm;
+  const float scale = (float)((double)m / (norm * s3));
+  const int nit = (kg.nball + 63) / 64;
+  for (int it = 0; it < nit; ++it) {
+    const int b = it * 64 + lane;
+    int dx = 0, dy = 0, dz = 0;
+    if (b < kg.nball) unpack(ball[b], dx, dy, dz);
+    const float wx = __shfl(p.w1, dx + kg.ext, 64);
+    const float wy = __shfl(p.w1, W + dy + kg.ext, 64);
+    const float wz = __shfl(p.w1, 2 * W + dz + kg.ext, 64);
+    if (b < kg.nball) {
+      const float v = wx * wy * wz * scale;
+      if constexpr (LDS) {
+        const int lx = p.cx + dx - ox, ly = p.cy + dy - oy, lz = p.cz + dz - oz;
+        if (kg.private_tiles) {
+          // the wave's own copy: its lanes hold distinct cells and its LDS
+          // operations execute in order, so a plain read-add-write suffices
+          tile[(lz * TE + ly) * TE + lx] += v;
+        } else {
+          atomicAdd(&tile[(lz * TE + ly) * TE + lx], v);
+        }
+      } else {
+        const long long g = ((long long)wrapi(p.cz + dz, N) * N + wrapi(p.cy + dy, N)) * N + wrapi(p.cx + dx, N);
+        unsafeAtomicAdd(&rho[g], v);
+      }
+    }
+  }
+}
+
 __global__ __launch_bounds__(kNT) void k_deposit(KernelGeom kg, const int* __restrict__ perm,
                                                  const int* __restrict__ skey, const int* __restrict__ offsets,
                                                  const float* __restrict__ pos, const float* __restrict__ mass,
-                                                 int64_t n, float* rho) {
+                                                 int64_t n, float* rho, double* s_store) {
   extern __shared__ float smem[];
+  __shared__ ChunkPlan pl;
   int* ball = reinterpret_cast<int*>(smem);
   float* tile = smem + ((kg.nball + 3) & ~3);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int b = threadIdx.x; b < kg.nball; b += kNT) ball[b] = kg.ball[b];
   const int TE = kTile + 2 * kg.ext;
   const int TE3 = TE * TE * TE;
-  const int W = 2 * kg.ext + 1;
+  const int ncopy = kg.private_tiles ? kWaves : 1;        // tile copies in LDS
+  float* my_tile = tile + (kg.private_tiles ? wave * TE3 : 0);
   const int N = kg.N;
   const int nt = N / kTile;
   const double s3 = (double)kg.s * kg.s * kg.s;
-  __syncthreads();
-
   const int64_t a0 = (int64_t)blockIdx.x * kChunk;
   const int64_t a1 = min(a0 + (int64_t)kChunk, n);
-  int64_t a = a0;
-  while (a < a1) {
-    const int t = skey[a];
-    int64_t e = min((int64_t)offsets[t + 1], a1);
-    if (e <= a) e = a + 1;   // sorted order guarantees progress; never stall
-    const int cnt = (int)(e - a);
-    const bool use_lds = (int64_t)cnt * kg.nball >= (int64_t)TE3;
+  plan_chunk(pl, skey, offsets, a0, a1, (ncopy * TE3 + kg.nball - 1) / kg.nball);
+
+  // sparse particles: 64 per wave fetched at once, broadcast one by one
+  for (int jb = wave * 64; jb < pl.nsparse; jb += kWaves * 64) {
+    const bool has = jb + lane < pl.nsparse;
+    const int il = has ? perm[pl.sparse[jb + lane]] : 0;
+    const float xl = has ? pos[3 * il] : 0.f, yl = has ? pos[3 * il + 1] : 0.f,
+                zl = has ? pos[3 * il + 2] : 0.f, ml = has ? mass[il] : 0.f;
+    const int nb = min(64, pl.nsparse - jb);
+    for (int t = 0; t < nb; ++t) {
+      const int it_ = __shfl(il, t, 64);
+      deposit_one<false>(kg, ball, __shfl(xl, t, 64), __shfl(yl, t, 64), __shfl(zl, t, 64), __shfl(ml, t, 64),
+                         s3, nullptr, TE, 0, 0, 0, rho, s_store ? s_store + it_ : nullptr, lane);
+    }
+  }
+
+  // dense pieces through the LDS tile
+  for (int k = 0; k < pl.npieces; ++k) {
+    const int t = pl.ptile[k];
+    const int ps = pl.pstart[k], pe = pl.pend[k];
     const int tx = t % nt, ty = (t / nt) % nt, tz = t / (nt * nt);
     const int ox = tx * kTile - kg.ext, oy = ty * kTile - kg.ext, oz = tz * kTile - kg.ext;
-    if (use_lds) {
-      for (int j = threadIdx.x; j < TE3; j += kNT) tile[j] = 0.0f;
-      __syncthreads();
-    }
-    for (int64_t j = a + wave; j < e; j += kWaves) {
-      const int i = perm[j];
-      const Part p = particle_setup(kg, ball, pos, i, lane);
-      const double norm = kg.analytic ? kg.analytic_norm : p.S;
-      const float scale = (float)((double)mass[i] / (norm * s3));
-      const int nit = (kg.nball + 63) / 64;
-      for (int it = 0; it < nit; ++it) {
-        const int b = it * 64 + lane;
-        int dx = 0, dy = 0, dz = 0;
-        if (b < kg.nball) unpack(ball[b], dx, dy, dz);
-        const float wx = __shfl(p.w1, dx + kg.ext, 64);
-        const float wy = __shfl(p.w1, W + dy + kg.ext, 64);
-        const float wz = __shfl(p.w1, 2 * W + dz + kg.ext, 64);
-        if (b < kg.nball) {
-          const float v = wx * wy * wz * scale;
-          if (use_lds) {
-            const int lx = p.cx + dx - ox, ly = p.cy + dy - oy, lz = p.cz + dz - oz;
-            atomicAdd(&tile[(lz * TE + ly) * TE + lx], v);
-          } else {
-            const long long g = ((long long)wrapi(p.cz + dz, N) * N + wrapi(p.cy + dy, N)) * N + wrapi(p.cx + dx, N);
-            unsafeAtomicAdd(&rho[g], v);
-          }
-        }
+    for (int j = threadIdx.x; j < ncopy * TE3; j += kNT) tile[j] = 0.0f;
+    __syncthreads();
+    for (int jb = ps + wave; jb < pe; jb += kWaves * 64) {
+      const int jl = jb + kWaves * lane;
+      const bool has = jl < pe;
+      const int il = has ? perm[jl] : 0;
+      const float xl = has ? pos[3 * il] : 0.f, yl = has ? pos[3 * il + 1] : 0.f,
+                  zl = has ? pos[3 * il + 2] : 0.f, ml = has ? mass[il] : 0.f;
+      const int nb = min(64, (pe - jb + kWaves - 1) / kWaves);
+      for (int u = 0; u < nb; ++u) {
+        const int iu = __shfl(il, u, 64);
+        deposit_one<true>(kg, ball, __shfl(xl, u, 64), __shfl(yl, u, 64), __shfl(zl, u, 64), __shfl(ml, u, 64),
+                          s3, my_tile, TE, ox, oy, oz, rho, s_store ? s_store + iu : nullptr, lane);
       }
     }
-    if (use_lds) {
-      __syncthreads();
-      for (int j = threadIdx.x; j < TE3; j += kNT) {
-        const float v = tile[j];
-        if (v != 0.0f) {
-          const int lx = j % TE, ly = (j / TE) % TE, lz = j / (TE * TE);
-          const long long g = ((long long)wrapi(oz + lz, N) * N + wrapi(oy + ly, N)) * N + wrapi(ox + lx, N);
-          unsafeAtomicAdd(&rho[g], v);
-        }
+    __syncthreads();
+    for (int j = threadIdx.x; j < TE3; j += kNT) {
+      float v = tile[j];
+      for (int c = 1; c < ncopy; ++c) v += tile[c * TE3 + j];
+      if (v != 0.0f) {
+        const int lx = j % TE, ly = (j / TE) % TE, lz = j / (TE * TE);
+        const long long g = ((long long)wrapi(oz + lz, N) * N + wrapi(oy + ly, N)) * N + wrapi(ox + lx, N);
+        unsafeAtomicAdd(&rho[g], v);
       }
-      __syncthreads();
     }
-    a = e;
+    __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------------------
 // gather + push
 // ---------------------------------------------------------------------------
+// Smoothed acceleration of the wave's particle at (x, y, z) from the LDS
+// tile of phi (origin o*, edge TE) when tile != nullptr, else from phi.
+template <bool LDS>
+__device__ __forceinline__ float3 gather_one(const KernelGeom& kg, const int* __restrict__ ball, float x, float y,
+                                             float z, const float* tile, int TE, int ox, int oy, int oz,
+                                             const float* __restrict__ phi, double s_known, int lane) {
+  const int W = 2 * kg.ext + 1, N = kg.N;
+  // with a stored normalisation (s_known > 0) the ball sum is not recomputed
+  const Part p = particle_setup(kg, ball, x, y, z, lane, s_known <= 0.0);
+  const double norm = s_known > 0.0 ? s_known : (kg.analytic ? kg.analytic_norm : p.S);
+  float gx = 0.f, gy = 0.f, gz = 0.f;
+  const int nit = (kg.nball + 63) / 64;
+  for (int it = 0; it < nit; ++it) {
+    const int b = it * 64 + lane;
+    int dx = 0, dy = 0, dz = 0;
+    if (b < kg.nball) unpack(ball[b], dx, dy, dz);
+    const float wx = __shfl(p.w1, dx + kg.ext, 64);
+    const float wy = __shfl(p.w1, W + dy + kg.ext, 64);
+    const float wz = __shfl(p.w1, 2 * W + dz + kg.ext, 64);
+    if (b < kg.nball) {
+      const float w = wx * wy * wz;
+      float xp, xm, yp, ym, zp, zm;
+      if constexpr (LDS) {
+        const int lx = p.cx + dx - ox, ly = p.cy + dy - oy, lz = p.cz + dz - oz;
+        const int c = (lz * TE + ly) * TE + lx;
+        xp = tile[c + 1]; xm = tile[c - 1];
+        yp = tile[c + TE]; ym = tile[c - TE];
+        zp = tile[c + TE * TE]; zm = tile[c - TE * TE];
+      } else {
+        const int X = p.cx + dx, Y = p.cy + dy, Z = p.cz + dz;
+        const long long zr = (long long)wrapi(Z, N) * N, zrp = (long long)wrapi(Z + 1, N) * N,
+                        zrm = (long long)wrapi(Z - 1, N) * N;
+        const int yw = wrapi(Y, N), xw = wrapi(X, N);
+        xp = phi[(zr + yw) * N + wrapi(X + 1, N)];
+        xm = phi[(zr + yw) * N + wrapi(X - 1, N)];
+        yp = phi[(zr + wrapi(Y + 1, N)) * N + xw];
+        ym = phi[(zr + wrapi(Y - 1, N)) * N + xw];
+        zp = phi[(zrp + yw) * N + xw];
+        zm = phi[(zrm + yw) * N + xw];
+      }
+      gx = fmaf(w, xp - xm, gx);
+      gy = fmaf(w, yp - ym, gy);
+      gz = fmaf(w, zp - zm, gz);
+    }
+  }
+  const float f = (float)(-1.0 / (2.0 * (double)kg.s * norm));
+  return make_float3(wave_sum_f(gx) * f, wave_sum_f(gy) * f, wave_sum_f(gz) * f);
+}
+
+// Writes the result of lane's particle il (acceleration, or kick + drift).
+__device__ __forceinline__ void gather_store(int il, float3 g, float x, float y, float z, float* pos, float* vel,
+                                             float* acc, float dt_kick, float dt_drift, int mode) {
+  if (mode == 0) {
+    acc[3 * il] = g.x;
+    acc[3 * il + 1] = g.y;
+    acc[3 * il + 2] = g.z;
+  } else {
+    const float vx = fmaf(g.x, dt_kick, vel[3 * il]);
+    const float vy = fmaf(g.y, dt_kick, vel[3 * il + 1]);
+    const float vz = fmaf(g.z, dt_kick, vel[3 * il + 2]);
+    vel[3 * il] = vx; vel[3 * il + 1] = vy; vel[3 * il + 2] = vz;
+    pos[3 * il] = fmaf(vx, dt_drift, x);
+    pos[3 * il + 1] = fmaf(vy, dt_drift, y);
+    pos[3 * il + 2] = fmaf(vz, dt_drift, z);
+  }
+}
+
 __global__ __launch_bounds__(kNT) void k_gather(KernelGeom kg, const int* __restrict__ perm,
                                                 const int* __restrict__ skey, const int* __restrict__ offsets,
                                                 const float* __restrict__ phi, float* pos, float* vel, float* acc,
-                                                int64_t n, float dt_kick, float dt_drift, int mode) {
+                                                int64_t n, float dt_kick, float dt_drift, int mode,
+                                                const double* __restrict__ s_store) {
   extern __shared__ float smem[];
+  __shared__ ChunkPlan pl;
   int* ball = reinterpret_cast<int*>(smem);
   float* tile = smem + ((kg.nball + 3) & ~3);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -262,86 +413,57 @@ __global__ __launch_bounds__(kNT) void k_gather(KernelGeom kg, const int* __rest
   const int he = kg.ext + 1;                  // halo: ball plus the FD stencil
   const int TE = kTile + 2 * he;
   const int TE3 = TE * TE * TE;
-  const int W = 2 * kg.ext + 1;
   const int N = kg.N;
   const int nt = N / kTile;
-  __syncthreads();
-
   const int64_t a0 = (int64_t)blockIdx.x * kChunk;
   const int64_t a1 = min(a0 + (int64_t)kChunk, n);
-  int64_t a = a0;
-  while (a < a1) {
-    const int t = skey[a];
-    int64_t e = min((int64_t)offsets[t + 1], a1);
-    if (e <= a) e = a + 1;   // sorted order guarantees progress; never stall
-    const int cnt = (int)(e - a);
-    const bool use_lds = (int64_t)cnt * kg.nball * 6 >= (int64_t)TE3 * 2;
+  // staging the tile costs TE^3 loads; a particle read straight from memory
+  // costs 6 per ball cell
+  plan_chunk(pl, skey, offsets, a0, a1, (2 * TE3 + 6 * kg.nball - 1) / (6 * kg.nball));
+
+  for (int jb = wave * 64; jb < pl.nsparse; jb += kWaves * 64) {
+    const bool has = jb + lane < pl.nsparse;
+    const int il = has ? perm[pl.sparse[jb + lane]] : 0;
+    const float xl = has ? pos[3 * il] : 0.f, yl = has ? pos[3 * il + 1] : 0.f,
+                zl = has ? pos[3 * il + 2] : 0.f;
+    const double sl = (has && s_store) ? s_store[il] : 0.0;
+    float3 mine = make_float3(0.f, 0.f, 0.f);
+    const int nb = min(64, pl.nsparse - jb);
+    for (int t = 0; t < nb; ++t) {
+      const float3 g = gather_one<false>(kg, ball, __shfl(xl, t, 64), __shfl(yl, t, 64), __shfl(zl, t, 64),
+                                         nullptr, TE, 0, 0, 0, phi, __shfl(sl, t, 64), lane);
+      if (lane == t) mine = g;
+    }
+    if (has) gather_store(il, mine, xl, yl, zl, pos, vel, acc, dt_kick, dt_drift, mode);
+  }
+
+  for (int k = 0; k < pl.npieces; ++k) {
+    const int t = pl.ptile[k];
+    const int ps = pl.pstart[k], pe = pl.pend[k];
     const int tx = t % nt, ty = (t / nt) % nt, tz = t / (nt * nt);
     const int ox = tx * kTile - he, oy = ty * kTile - he, oz = tz * kTile - he;
-    if (use_lds) {
-      for (int j = threadIdx.x; j < TE3; j += kNT) {
-        const int lx = j % TE, ly = (j / TE) % TE, lz = j / (TE * TE);
-        tile[j] = phi[((long long)wrapi(oz + lz, N) * N + wrapi(oy + ly, N)) * N + wrapi(ox + lx, N)];
-      }
-      __syncthreads();
+    for (int j = threadIdx.x; j < TE3; j += kNT) {
+      const int lx = j % TE, ly = (j / TE) % TE, lz = j / (TE * TE);
+      tile[j] = phi[((long long)wrapi(oz + lz, N) * N + wrapi(oy + ly, N)) * N + wrapi(ox + lx, N)];
     }
-    for (int64_t j = a + wave; j < e; j += kWaves) {
-      const int i = perm[j];
-      const Part p = particle_setup(kg, ball, pos, i, lane);
-      const double norm = kg.analytic ? kg.analytic_norm : p.S;
-      float gx = 0.f, gy = 0.f, gz = 0.f;
-      const int nit = (kg.nball + 63) / 64;
-      for (int it = 0; it < nit; ++it) {
-        const int b = it * 64 + lane;
-        int dx = 0, dy = 0, dz = 0;
-        if (b < kg.nball) unpack(ball[b], dx, dy, dz);
-        const float wx = __shfl(p.w1, dx + kg.ext, 64);
-        const float wy = __shfl(p.w1, W + dy + kg.ext, 64);
-        const float wz = __shfl(p.w1, 2 * W + dz + kg.ext, 64);
-        if (b < kg.nball) {
-          const float w = wx * wy * wz;
-          float xp, xm, yp, ym, zp, zm;
-          if (use_lds) {
-            const int lx = p.cx + dx - ox, ly = p.cy + dy - oy, lz = p.cz + dz - oz;
-            const int c = (lz * TE + ly) * TE + lx;
-            xp = tile[c + 1]; xm = tile[c - 1];
-            yp = tile[c + TE]; ym = tile[c - TE];
-            zp = tile[c + TE * TE]; zm = tile[c - TE * TE];
-          } else {
-            const int X = p.cx + dx, Y = p.cy + dy, Z = p.cz + dz;
-            const long long zr = (long long)wrapi(Z, N) * N, zrp = (long long)wrapi(Z + 1, N) * N,
-                            zrm = (long long)wrapi(Z - 1, N) * N;
-            const int yw = wrapi(Y, N), xw = wrapi(X, N);
-            xp = phi[(zr + yw) * N + wrapi(X + 1, N)];
-            xm = phi[(zr + yw) * N + wrapi(X - 1, N)];
-            yp = phi[(zr + wrapi(Y + 1, N)) * N + xw];
-            ym = phi[(zr + wrapi(Y - 1, N)) * N + xw];
-            zp = phi[(zrp + yw) * N + xw];
-            zm = phi[(zrm + yw) * N + xw];
-          }
-          gx = fmaf(w, xp - xm, gx);
-          gy = fmaf(w, yp - ym, gy);
-          gz = fmaf(w, zp - zm, gz);
-        }
+    __syncthreads();
+    for (int jb = ps + wave; jb < pe; jb += kWaves * 64) {
+      const int jl = jb + kWaves * lane;
+      const bool has = jl < pe;
+      const int il = has ? perm[jl] : 0;
+      const float xl = has ? pos[3 * il] : 0.f, yl = has ? pos[3 * il + 1] : 0.f,
+                  zl = has ? pos[3 * il + 2] : 0.f;
+      const double sl = (has && s_store) ? s_store[il] : 0.0;
+      float3 mine = make_float3(0.f, 0.f, 0.f);
+      const int nb = min(64, (pe - jb + kWaves - 1) / kWaves);
+      for (int u = 0; u < nb; ++u) {
+        const float3 g = gather_one<true>(kg, ball, __shfl(xl, u, 64), __shfl(yl, u, 64), __shfl(zl, u, 64),
+                                          tile, TE, ox, oy, oz, phi, __shfl(sl, u, 64), lane);
+        if (lane == u) mine = g;
       }
-      gx = wave_sum_f(gx);
-      gy = wave_sum_f(gy);
-      gz = wave_sum_f(gz);
-      const float f = (float)(-1.0 / (2.0 * (double)kg.s * norm));
-      gx *= f; gy *= f; gz *= f;
-      if (lane < 3) {
-        const float g = lane == 0 ? gx : (lane == 1 ? gy : gz);
-        if (mode == 0) {
-          acc[3 * i + lane] = g;
-        } else {
-          const float v = fmaf(g, dt_kick, vel[3 * i + lane]);
-          vel[3 * i + lane] = v;
-          pos[3 * i + lane] = fmaf(v, dt_drift, pos[3 * i + lane]);
-        }
-      }
+      if (has) gather_store(il, mine, xl, yl, zl, pos, vel, acc, dt_kick, dt_drift, mode);
     }
-    if (use_lds) __syncthreads();
-    a = e;
+    __syncthreads();
   }
 }
 
@@ -445,20 +567,23 @@ static size_t particle_lds(const KernelGeom& kg, int halo) {
 }
 
 hipError_t deposit_sorted(const KernelGeom& kg, const SortBufs& sb, const float* pos, const float* mass,
-                          int64_t n, float* rho, hipStream_t st) {
+                          int64_t n, float* rho, double* s_store, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   const unsigned blocks = (unsigned)((n + kChunk - 1) / kChunk);
-  hipLaunchKernelGGL(k_deposit, dim3(blocks), dim3(kNT), particle_lds(kg, kg.ext), st, kg, sb.perm, sb.skey,
-                     sb.offsets, pos, mass, n, rho);
+  const int TE = kTile + 2 * kg.ext;
+  const size_t sh = sizeof(float) * (((kg.nball + 3) & ~3) + (size_t)(kg.private_tiles ? kWaves : 1) * TE * TE * TE);
+  hipLaunchKernelGGL(k_deposit, dim3(blocks), dim3(kNT), sh, st, kg, sb.perm, sb.skey, sb.offsets, pos, mass, n,
+                     rho, s_store);
   return hipGetLastError();
 }
 
 hipError_t gather_sorted(const KernelGeom& kg, const SortBufs& sb, const float* phi, float* pos, float* vel,
-                         float* acc, int64_t n, float dt_kick, float dt_drift, int mode, hipStream_t st) {
+                         float* acc, int64_t n, float dt_kick, float dt_drift, int mode, const double* s_store,
+                         hipStream_t st) {
   if (n <= 0) return hipSuccess;
   const unsigned blocks = (unsigned)((n + kChunk - 1) / kChunk);
   hipLaunchKernelGGL(k_gather, dim3(blocks), dim3(kNT), particle_lds(kg, kg.ext + 1), st, kg, sb.perm, sb.skey,
-                     sb.offsets, phi, pos, vel, acc, n, dt_kick, dt_drift, mode);
+                     sb.offsets, phi, pos, vel, acc, n, dt_kick, dt_drift, mode, s_store);
   return hipGetLastError();
 }
 
