@@ -71,6 +71,43 @@ def copy_probe():
     print("copy probe: 3 x 1 GiB device copy done", flush=True)
 
 
+def fft_compare(n_pad=512, reps=20):
+    """Times this library's real 3D transforms (pm_fft_r2c / pm_fft_c2r) beside
+    torch.fft.rfftn / irfftn (rocFFT) on the same n_pad^3 FP32 input, for
+    context only; prints one JSON line."""
+    import torch
+    from paper_2312_02968_amd import mondpm as M
+    import workloads as W
+    p = W.params(n_pad // 2, n_pad=n_pad)
+    ctx = M.pm_create(p, 0)
+    g = torch.Generator(device="cpu").manual_seed(0)
+    x = torch.randn(n_pad ** 3, generator=g).cuda()
+    spec = torch.empty(2 * n_pad * n_pad * M.pm_spectrum_pitch(n_pad), device="cuda")
+    back = torch.empty_like(x)
+    x3 = x.view(n_pad, n_pad, n_pad)
+
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        s.record()
+        for _ in range(reps):
+            fn()
+        e.record()
+        torch.cuda.synchronize()
+        return s.elapsed_time(e) / reps
+
+    res = {"n_pad": n_pad, "reps": reps,
+           "pm_r2c_ms": timed(lambda: M.pm_fft_r2c(ctx, x, spec)),
+           "pm_c2r_ms": timed(lambda: M.pm_fft_c2r(ctx, spec, back))}
+    xs = torch.fft.rfftn(x3)
+    res["rocfft_r2c_ms"] = timed(lambda: torch.fft.rfftn(x3))
+    res["rocfft_c2r_ms"] = timed(lambda: torch.fft.irfftn(xs, s=x3.shape))
+    ctx.close()
+    print(json.dumps({k: (round(v, 4) if isinstance(v, float) else v) for k, v in res.items()}), flush=True)
+
+
 def make_workload(name):
     import workloads as W
     if name == "isothermal":
@@ -187,9 +224,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--timing", action="store_true", help="print per-kernel timing table to stderr")
     ap.add_argument("--copy-probe", action="store_true", help="only run the counter-calibration copy")
+    ap.add_argument("--fft-compare", action="store_true",
+                    help="only time this library's 512^3 real transforms beside rocFFT's")
     a = ap.parse_args()
     if a.copy_probe:
         copy_probe()
+        return
+    if a.fft_compare:
+        fft_compare()
         return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the path has no multi-GPU "

@@ -118,7 +118,7 @@ pm_status pm_deposit(pm_ctx* ctx, const float* pos, const float* mass, int64_t N
 
 /* MOND potential phi from rho by the fixed-point iteration of Sect. 2.1:
  * Newton field g_N from rho (-4 pi G A rho_hat, finite-difference gradient),
- * H = H0 (or 0), then K times: F = g_N + H, g_M = nu(|F|/a0) F, curl-free
+ * H = the divergence-free part of H0 (or 0), then K times: F = g_N + H, g_M = nu(|F|/a0) F, curl-free
  * projection in Fourier space, and (except after the K-th) F' = mu(|g_M|/a0)
  * g_M, H = divergence-free part of F' - g_N.  phi comes from the last
  * projection.  rho: device float [n_pad^3] (read); H0: device float

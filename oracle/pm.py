@@ -297,7 +297,9 @@ def aqual_solve(p: Params, rho: np.ndarray, H0: np.ndarray | None = None,
                 keep_fields: bool = False):
     """Potential phi of Eq. PDE from rho by the fixed-point iteration of Sect. 2.1.
 
-    g_N is solved once and stored; H starts at H0 (zero by default).  Each
+    g_N is solved once and stored; H starts at the divergence-free part of H0
+    (zero by default; H is a curl field in the decomposition of Sect. 2.1, so
+    a start value is projected like every later iterate).  Each
     iteration: F = g_N + H; g_M = nu(F) F; project g_M curl-free in Fourier
     space (giving phi_hat); stop at the K-th evaluation of nu (the flow scheme
     exits after the projection of the fourth iteration); otherwise
@@ -308,7 +310,11 @@ def aqual_solve(p: Params, rho: np.ndarray, H0: np.ndarray | None = None,
     loop stops at iteration k once r_{k-1} <= tol.
     """
     _, gN = newton_potential(p, rho)
-    H = np.zeros_like(gN) if H0 is None else np.asarray(H0, dtype=np.float64).copy()
+    if H0 is None:
+        H = np.zeros_like(gN)
+    else:
+        H0 = np.asarray(H0, dtype=np.float64)
+        H = np.stack([ifft3_real(c) for c in project_div_free(p, np.stack([fft3(H0[c]) for c in range(3)]))])
     norm_gN = math.sqrt(float((gN * gN).sum()))
     info = SolveInfo()
     K = max(int(p.iters), 1)

@@ -460,7 +460,8 @@ template <> struct ZComp<Z_DIV>        { static constexpr int IN = 3, OUT = 3; }
 //                 -4 pi G A rho_hat into phiN and outputs g_N_hat = -i kappa
 //                 phi_N_hat (/N^3) as three components; accumulates the
 //                 Parseval sum of |g_N_hat|^2 per block.
-//   Z_NEWTON_H0 : as Z_NEWTON plus the x, y transformed H0 components from spec.
+//   Z_NEWTON_H0 : as Z_NEWTON plus the divergence-free part of the x, y
+//                 transformed H0 components from spec.
 //   Z_CURL      : g <- kt At (kt . g) / N^3
 //   Z_CURL_FINAL: phi_hat = i At (kt . g) / N^3 (one output component)
 //   Z_DIV       : F = F' + kt At kt . (g_N - F'), g_N = -i kappa phi_N (/N^3)
@@ -550,10 +551,16 @@ __global__ __launch_bounds__(NT) void k_zpass(ZArgs a, const float2* __restrict_
           const float2 g = cscale(mul_mi<false>(ph), a.scale);
           float2 o0 = cscale(g, kpx), o1 = cscale(g, kapy), o2 = cscale(g, kpz);
           if (ZOP == Z_NEWTON_H0) {
-            // H0 components arrived in input slots 1..3 (component c at slot HZ c + h)
-            o0 = cadd(o0, cscale(v[(1 * HZ + h) * E + e], a.scale));
-            o1 = cadd(o1, cscale(v[(2 * HZ + h) * E + e], a.scale));
-            o2 = cadd(o2, cscale(v[(3 * HZ + h) * E + e], a.scale));
+            // H0 components arrived in input slots 1..3 (component c at slot HZ c + h);
+            // H starts at their divergence-free part h - kt At (kt . h)
+            const float tz = a.kt[kz];
+            const float t2 = tx * tx + ty * ty + tz * tz;
+            const float At = (t2 > 0.0f) ? 1.0f / t2 : 0.0f;
+            const float2 h0 = v[(1 * HZ + h) * E + e], h1 = v[(2 * HZ + h) * E + e], h2 = v[(3 * HZ + h) * E + e];
+            const float2 dd = cscale(cadd(cadd(cscale(h0, tx), cscale(h1, ty)), cscale(h2, tz)), At);
+            o0 = cadd(o0, cscale(csub(h0, cscale(dd, tx)), a.scale));
+            o1 = cadd(o1, cscale(csub(h1, cscale(dd, ty)), a.scale));
+            o2 = cadd(o2, cscale(csub(h2, cscale(dd, tz)), a.scale));
           }
           *v0 = o0;
           *v1 = o1;

@@ -1,0 +1,179 @@
+"""Pins of the learned-start oracle (network, its gradients, Adam, the input
+features and the start field).  The network is not in the paper, so these
+pins come from definitions: brute-force sums, adjoint identities, finite
+differences of the loss, the closed form of Adam's first step and a library
+BF16 conversion."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import convnet as cn
+from oracle import learned as ol
+from oracle import pm
+
+
+def test_conv3d_brute_force():
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal((2, 4, 3, 5))
+    w = rng.standard_normal((27, 2, 3))
+    b = rng.standard_normal(3)
+    got = cn.conv3d(x, w, b)
+    C, D, H, W = x.shape
+    for o in range(3):
+        for z in range(D):
+            for y in range(H):
+                for xx in range(W):
+                    s = b[o]
+                    t = 0
+                    for dz in (-1, 0, 1):
+                        for dy in (-1, 0, 1):
+                            for dx in (-1, 0, 1):
+                                zz, yy, x2 = z + dz, y + dy, xx + dx
+                                if 0 <= zz < D and 0 <= yy < H and 0 <= x2 < W:
+                                    for c in range(C):
+                                        s += x[c, zz, yy, x2] * w[t, c, o]
+                                t += 1
+                    assert abs(got[o, z, y, xx] - s) < 1e-12
+
+
+def test_conv3d_delta_response_fixes_tap_orientation():
+    # a unit impulse at v0 in channel c gives out[o, v0 - tap_t] = w[t, c, o]
+    rng = np.random.default_rng(1)
+    w = rng.standard_normal((27, 3, 2))
+    x = np.zeros((3, 5, 5, 5))
+    x[1, 2, 2, 2] = 1.0
+    out = cn.conv3d(x, w, np.zeros(2))
+    t = 0
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                assert np.allclose(out[:, 2 - dz, 2 - dy, 2 - dx], w[t, 1])
+                t += 1
+
+
+@pytest.mark.parametrize("taps", [27, 1])
+def test_conv_backward_is_the_adjoint(taps):
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal((3, 4, 4, 6))
+    w = rng.standard_normal((taps, 3, 5))
+    g = rng.standard_normal((5, 4, 4, 6))
+    y = cn.conv3d(x, w, np.zeros(5))
+    gx, gw, gb = cn.conv3d_backward(x, w, g)
+    ip = float((y * g).sum())
+    assert abs(ip - float((gx * x).sum())) < 1e-10 * abs(ip)
+    assert abs(ip - float((gw * w).sum())) < 1e-10 * abs(ip)
+    assert np.allclose(gb, g.sum(axis=(1, 2, 3)))
+
+
+def test_pool_and_upsample_adjoints():
+    rng = np.random.default_rng(3)
+    a = rng.standard_normal((2, 4, 6, 8))
+    b = rng.standard_normal((2, 2, 3, 4))
+    assert abs(float((cn.pool2(a) * b).sum()) - float((a * cn.pool2_backward(b)).sum())) < 1e-12
+    assert abs(float((cn.up2(b) * a).sum()) - float((b * cn.up2_backward(a)).sum())) < 1e-12
+    assert np.allclose(cn.pool2(cn.up2(b)), b)
+    assert cn.pool2(a)[1, 0, 1, 2] == pytest.approx(a[1, 0:2, 2:4, 4:6].mean())
+
+
+def test_parameter_count():
+    p = cn.init_params(0)
+    n = sum(v.size for v in p.values())
+    assert n == sum(k ** 3 * ci * co + co for _, ci, co, k in cn.LAYERS)
+    assert 3.0e5 < n < 4.0e5
+
+
+def _loss(p, x, t):
+    y, _ = cn.forward(p, x)
+    return cn.mse(y, t)[0]
+
+
+def test_network_gradient_matches_finite_differences():
+    rng = np.random.default_rng(4)
+    p = cn.init_params(1)
+    for k in p:
+        if k.endswith(".b"):
+            p[k] = 0.1 * rng.standard_normal(p[k].shape)
+    x = rng.standard_normal((4, 8, 8, 8))
+    t = rng.standard_normal((3, 8, 8, 8))
+    y, cache = cn.forward(p, x)
+    _, gy = cn.mse(y, t)
+    g = cn.backward(p, cache, gy)
+    eps = 1e-6
+    for k in p:
+        flat = p[k].reshape(-1)
+        for i in rng.choice(flat.size, size=min(3, flat.size), replace=False):
+            old = flat[i]
+            flat[i] = old + eps
+            lp = _loss(p, x, t)
+            flat[i] = old - eps
+            lm = _loss(p, x, t)
+            flat[i] = old
+            fd = (lp - lm) / (2 * eps)
+            an = g[k].reshape(-1)[i]
+            # FD rounding: about 1e-16 loss / eps = 1e-10
+            assert abs(fd - an) <= 1e-5 * abs(an) + 1e-9, (k, i, fd, an)
+
+
+def test_bf16_rounding_matches_torch():
+    rng = np.random.default_rng(5)
+    v = np.concatenate([rng.standard_normal(5000) * 10.0 ** rng.integers(-30, 30, 5000),
+                        1.0 + np.array([1, 2, 3, 5]) * 2.0 ** -8,      # ties and near-ties
+                        [-(1.0 + 3 * 2.0 ** -8), 0.0, -0.0]]).astype(np.float32)
+    ref = torch.from_numpy(v).to(torch.bfloat16).float().numpy().astype(np.float64)
+    assert np.array_equal(cn.bf16_round(v), ref)
+    assert cn.bf16_round(np.float32(1 + 2 ** -8)) == 1.0                 # tie to even
+    assert cn.bf16_round(np.float32(1 + 3 * 2 ** -8)) == 1 + 2 ** -6
+
+
+def test_adam_first_step_closed_form():
+    # after one step with zero moments, m_hat = g and v_hat = g^2, so each
+    # parameter moves by lr g / (|g| + eps)
+    rng = np.random.default_rng(6)
+    p = {"a": rng.standard_normal(10)}
+    g = {"a": rng.standard_normal(10)}
+    p0 = p["a"].copy()
+    st = {}
+    cn.adam_step(p, g, st, lr=0.01)
+    assert np.allclose(p["a"], p0 - 0.01 * g["a"] / (np.abs(g["a"]) + 1e-8), rtol=1e-12)
+    # a constant gradient keeps the step at lr
+    for _ in range(5):
+        cn.adam_step(p, {"a": np.full(10, 0.3)}, st, lr=0.01)
+    q = {"a": p["a"].copy()}
+    st2 = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in st.items()}
+    cn.adam_step(q, {"a": np.full(10, 0.3)}, st2, lr=0.01)
+    assert np.all(q["a"] < p["a"])
+
+
+def test_training_reduces_loss_on_a_fixed_pair():
+    rng = np.random.default_rng(7)
+    p = cn.init_params(2, scale=0.5)
+    x = rng.standard_normal((4, 8, 8, 8))
+    t = 0.3 * x[:3] + 0.1
+    st = {}
+    l0 = _loss(p, x, t)
+    for _ in range(30):
+        y, cache = cn.forward(p, x)
+        _, gy = cn.mse(y, t)
+        cn.adam_step(p, cn.backward(p, cache, gy), st, lr=1e-3)
+    assert _loss(p, x, t) < 0.5 * l0
+
+
+def test_net_input_and_start_field():
+    p = pm.Params(n=8, n_pad=16, box=8.0, a0=2.0)
+    rng = np.random.default_rng(8)
+    gN = rng.standard_normal((3, 16, 16, 16))
+    x, rms = ol.net_input(p, gN)
+    r = slice(4, 12)
+    g = gN[:, r, r, r]
+    assert x.shape == (4, 8, 8, 8)
+    assert rms == pytest.approx(math.sqrt((g ** 2).sum() / 8 ** 3))
+    assert ((x[:3] ** 2).sum(axis=0).mean()) == pytest.approx(1.0)
+    assert np.allclose(10.0 ** x[3], np.sqrt((g ** 2).sum(axis=0)) / 2.0 + 1e-30)
+    y = rng.standard_normal((3, 8, 8, 8))
+    H0 = ol.start_field(p, y, rms)
+    assert np.allclose(H0[:, r, r, r], rms * y)
+    H0[:, r, r, r] = 0.0
+    assert not H0.any()
+    assert np.allclose(ol.target(p, ol.start_field(p, y, rms), rms), y)

@@ -248,3 +248,32 @@ def test_divergence_free_projection_keeps_mean():
     means = info.H.reshape(3, -1).mean(axis=1)
     assert np.allclose(means, Fp.reshape(3, -1).mean(axis=1), rtol=1e-9, atol=1e-18)
     assert np.max(np.abs(means)) > 0.0
+
+
+def test_start_value_is_taken_divergence_free():
+    # H is a curl field (Sect. 2.1): a start value enters through its
+    # divergence-free part.  A spectral gradient start i kt psi_hat (kt the
+    # wavevector with the Nyquist entry zeroed, built here from its definition)
+    # therefore acts like H0 = 0, and restarting from the H of a longer solve
+    # continues that solve: its first change equals the change the longer
+    # solve would make next.
+    p, pos, mass, rho = _cloud(2, 16, 30, W.MU_STANDARD, iters=3)
+    phi0, info0 = pm.aqual_solve(p, rho)
+    N = p.n_pad
+    m = np.fft.fftfreq(N, 1.0 / N)
+    kt = np.where(m == -N // 2, 0.0, 2 * np.pi * m / (N * p.s))
+    psi_h = np.fft.fftn(np.random.default_rng(5).standard_normal((N, N, N)))
+    grads = [kt[None, None, :], kt[None, :, None], kt[:, None, None]]       # x, y, z on [z, y, x]
+    H0 = np.stack([np.fft.ifftn(1j * g * psi_h).real for g in grads])
+    phi1, info1 = pm.aqual_solve(p, rho, H0=H0 * (np.abs(rho).max() / np.abs(H0).max()))
+    assert np.max(np.abs(phi1 - phi0)) < 1e-9 * np.max(np.abs(phi0))
+    assert np.allclose(info1.residuals, info0.residuals, rtol=1e-8)
+
+    q6 = pm.Params.from_dict({**p.__dict__, "iters": 6})
+    _, long = pm.aqual_solve(q6, rho)
+    q4 = pm.Params.from_dict({**p.__dict__, "iters": 4})
+    _, mid = pm.aqual_solve(q4, rho, keep_fields=True)
+    q3 = pm.Params.from_dict({**p.__dict__, "iters": 3})
+    _, rest = pm.aqual_solve(q3, rho, H0=mid.H)
+    # mid made residuals r_1..r_3; the restart's r_1, r_2 are the long run's r_4, r_5
+    assert np.allclose(rest.residuals, long.residuals[3:5], rtol=1e-7)
