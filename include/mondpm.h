@@ -176,6 +176,81 @@ pm_status pm_set_timing(pm_ctx* ctx, int enable);
  * (host arrays the caller zeroes), then forgets them. */
 pm_status pm_read_timing(pm_ctx* ctx, double* total_ms, int64_t* launches);
 
+/* Newton potential alone (the flow scheme's Newton step): phi_N = inverse FFT
+ * of -4 pi G A rho_hat on the n_pad^3 box.  rho, phiN: device float
+ * [n_pad^3]; they may not overlap.  Used to form the learned start's input. */
+pm_status pm_newton_potential(pm_ctx* ctx, const float* rho, float* phiN);
+
+/* aqual_solve that also returns F = g_N + H of its last iteration (the field
+ * whose nu gave phi) in F: device float [3][n_pad^3].  Requires a context
+ * created with PM_F_RESIDUAL or tol > 0 (it keeps F); otherwise PM_E_INVAL.
+ * The fixed point's H is F - g_N. */
+pm_status aqual_solve_field(pm_ctx* ctx, const float* rho, const float* H0, float* phi, float* F,
+                            pm_solve_info* info);
+
+/* ---- Learned starting guess --------------------------------------------
+ * Sect. 2.1 lets the iteration start from any divergence-free H; the paper
+ * starts from zero and notes that a good start saves iterations.  A 3-level
+ * encoder-decoder of 3x3x3 convolutions (16 / 32 / 64 channels, ReLU, 2x
+ * average pooling, nearest 2x upsampling with skip concatenation, a 1x1x1
+ * head to 3 channels) maps the Newton field on the physical n^3 region to a
+ * start:  rms = sqrt(mean |g_N|^2) over the region,
+ *         x = [g_N / rms, log10(|g_N| / a0 + 1e-30)],
+ *         H0 = rms * net(x) on the region, zero outside;
+ * aqual_solve then starts from the divergence-free part of H0.  Operands are
+ * BF16 on the matrix cores with FP32 accumulation; parameters are FP32.
+ * Parameter vector (pm_net_param_count floats): for each layer in the order
+ * e1a (4->16), e1b (16->16), e2a (16->32), e2b (32->32), b3a (32->64),
+ * b3b (64->64), d2a (96->32), d2b (32->32), d1a (48->16), d1b (16->16),
+ * out (16->3, 1x1x1): weights [taps][cin][cout] (tap = (dz+1) 9 + (dy+1) 3 +
+ * (dx+1)) then bias [cout].  A net's buffers belong to one stream at a time:
+ * calls taking a context run on the context's stream, the others on the
+ * stream given to pm_net_create. */
+typedef struct pm_net pm_net;
+int64_t   pm_net_param_count(void);
+/* n: region size (power of two, 8..1024); max_batch: slots for training
+ * pairs (1..64).  Parameters start at zero; set them with pm_net_set_params.
+ * Synchronises. */
+pm_status pm_net_create(int32_t n, int32_t max_batch, void* stream, pm_net** out);
+pm_status pm_net_destroy(pm_net* net);
+/* params (host float [P]) in; also clears the optimiser state.  Synchronises. */
+pm_status pm_net_set_params(pm_net* net, const float* params);
+/* host float [P] out.  Synchronises. */
+pm_status pm_net_get_params(pm_net* net, float* params);
+/* gradients of the last pm_net_backward, host float [P].  Synchronises. */
+pm_status pm_net_get_grads(pm_net* net, float* grads);
+/* input channels of slot from phiN (device float [n_pad^3], the Newton
+ * potential of the context's box; g_N = -D phi_N by central differences). */
+pm_status pm_net_input(pm_ctx* ctx, pm_net* net, const float* phiN, int32_t slot);
+/* training target of slot: (F - g_N) / rms on the region, F as returned by
+ * aqual_solve_field for the same rho, rms that of pm_net_input for the slot. */
+pm_status pm_net_target(pm_ctx* ctx, pm_net* net, const float* phiN, const float* F, int32_t slot);
+/* direct input / target of a slot: x device float [4][n^3], y device float
+ * [3][n^3] (region voxels, x fastest). */
+pm_status pm_net_set_input(pm_net* net, int32_t slot, const float* x);
+pm_status pm_net_set_target(pm_net* net, int32_t slot, const float* y);
+/* the input channels of a slot as stored (BF16 values), device float [4][n^3]. */
+pm_status pm_net_get_input(pm_net* net, int32_t slot, float* x);
+/* the target of a slot, device float [3][n^3]. */
+pm_status pm_net_get_target(pm_net* net, int32_t slot, float* y);
+/* forward pass over slots [0, batch); outputs kept in the net. */
+pm_status pm_net_run(pm_net* net, int32_t batch);
+/* output of slot after pm_net_run / pm_net_backward: device float [3][n^3]. */
+pm_status pm_net_output(pm_net* net, int32_t slot, float* y);
+/* rms of slot (host double out).  Synchronises. */
+pm_status pm_net_get_rms(pm_net* net, int32_t slot, double* rms);
+/* forward and backward over slots [0, batch) with the loss
+ * mean((net(x) - y)^2) over all slots, channels and voxels; loss (host,
+ * nullable) synchronises. */
+pm_status pm_net_backward(pm_net* net, int32_t batch, double* loss);
+/* one Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with the last gradients. */
+pm_status pm_net_adam(pm_net* net, float lr);
+pm_status pm_net_train_step(pm_net* net, int32_t batch, float lr, double* loss);
+/* the learned start for the context's box: input from phiN, forward, H0
+ * (device float [3][n_pad^3], overwritten: rms * net(x) on the region, zero
+ * elsewhere).  Uses slot 0. */
+pm_status pm_net_forward(pm_ctx* ctx, pm_net* net, const float* phiN, float* H0);
+
 /* Last HIP error string seen by the library (host, static storage). */
 const char* pm_last_error(void);
 

@@ -25,9 +25,9 @@ ReLU after every convolution except the last 1x1x1 one):
 
 Arrays are channels-first [C, D, H, W] here; 3x3x3 weights are [27, Cin, Cout]
 with tap t = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1), the 1x1x1 head is
-[1, 16, 3].  With bf16=True every activation stored between layers is rounded
-to BF16 (round to nearest even), as the GPU stores them; weights are taken
-as given.
+[1, 16, 3].  With bf16=True the input and every activation stored between
+layers is rounded to BF16 (round to nearest even), as the GPU stores them;
+the output stays unrounded, and weights are taken as given.
 """
 from __future__ import annotations
 
@@ -128,7 +128,7 @@ def forward(p, x, bf16=False):
     def cr(name, a, relu=True):
         z = conv3d(a, p[name + ".w"], p[name + ".b"])
         cache[name] = (a, z)
-        return r(np.maximum(z, 0.0)) if relu else r(z)
+        return r(np.maximum(z, 0.0)) if relu else z
 
     x = r(x)
     s1 = cr("e1b", cr("e1a", x))

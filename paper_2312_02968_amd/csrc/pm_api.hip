@@ -8,13 +8,15 @@
 
 #include "mondpm.h"
 #include "pm_internal.h"
+#include "pm_net.h"
 
 using namespace pm;
 
 static thread_local char g_err[512] = "";
 
 static pm_status dev_fail(hipError_t e, const char* where) {
-  snprintf(g_err, sizeof g_err, "%s: %s", where, hipGetErrorString(e));
+  const char* step = net::last_failure();
+  snprintf(g_err, sizeof g_err, "%s: %s%s%s", where, hipGetErrorString(e), step[0] ? " at " : "", step);
   return PM_E_DEVICE;
 }
 static pm_status inval(const char* msg) {
@@ -101,6 +103,7 @@ static int timer_of(PassKind k) {
     case PASS_Z_CURL: return PM_T_Z_CURL;
     case PASS_Z_CURL_FINAL: return PM_T_Z_CURL_FINAL;
     case PASS_Z_DIV: return PM_T_Z_DIV;
+    case PASS_Z_POISSON: return PM_T_Z_NEWTON;
   }
   return PM_T_REDUCE;
 }
@@ -578,5 +581,317 @@ pm_status pm_read_timing(pm_ctx* c, double* total_ms, int64_t* launches) {
     launches[k] += 1;
   }
   c->ev_used = 0;
+  return PM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Newton potential alone, and a solve that also returns its last F
+// ---------------------------------------------------------------------------
+
+pm_status pm_newton_potential(pm_ctx* c, const float* rho, float* phiN) {
+  if (!c) return inval("ctx is NULL");
+  if (!rho || !phiN) return inval("rho and phiN are required");
+  PassDesc d = pdesc(PASS_X_FWD_REAL, c->spec);
+  d.real = const_cast<float*>(rho);
+  HIPCHK(pass(c, d));
+  HIPCHK(pass(c, pdesc(PASS_Y_FWD, c->spec, 1)));
+  PassDesc z = pdesc(PASS_Z_POISSON, c->spec);
+  z.z = zargs(c);
+  HIPCHK(pass(c, z));
+  HIPCHK(pass(c, pdesc(PASS_Y_INV, c->spec, 1)));
+  PassDesc x = pdesc(PASS_X_INV_REAL, c->spec);
+  x.real = phiN;
+  HIPCHK(pass(c, x));
+  return PM_OK;
+}
+
+pm_status aqual_solve_field(pm_ctx* c, const float* rho, const float* H0, float* phi, float* F,
+                            pm_solve_info* info) {
+  if (!c) return inval("ctx is NULL");
+  if (!rho || !phi || !F) return inval("rho, phi and F are required");
+  if (!c->fprev) return inval("aqual_solve_field needs a context created with PM_F_RESIDUAL or tol > 0");
+  pm_status s = run_solve(c, rho, H0, phi, info, info != nullptr);
+  if (s != PM_OK) return s;
+  if (info) info->bounds_flag = 0;
+  const size_t R = (size_t)c->N * c->N * c->N;
+  HIPCHK(hipMemcpyAsync(F, c->fprev, 3 * R * sizeof(float), hipMemcpyDeviceToDevice, c->st));
+  return PM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Learned starting guess
+// ---------------------------------------------------------------------------
+
+struct pm_net {
+  net::Buffers b;
+  hipStream_t st = nullptr;
+  int adam_step = 0;
+  std::vector<void*> allocs;
+};
+
+template <typename T>
+static pm_status nalloc(pm_net* m, T** ptr, size_t count) {
+  void* v = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc(&v, count * sizeof(T));
+  if (e != hipSuccess) {
+    snprintf(g_err, sizeof g_err, "hipMalloc(%zu bytes): %s", count * sizeof(T), hipGetErrorString(e));
+    return PM_E_NOMEM;
+  }
+  m->allocs.push_back(v);
+  *ptr = static_cast<T*>(v);
+  return PM_OK;
+}
+
+int64_t pm_net_param_count(void) { return net::param_count(); }
+
+pm_status pm_net_destroy(pm_net* m) {
+  if (!m) return PM_OK;
+  (void)(m->st ? hipStreamSynchronize(m->st) : hipDeviceSynchronize());
+  for (void* v : m->allocs) (void)hipFree(v);
+  delete m;
+  return PM_OK;
+}
+
+pm_status pm_net_create(int32_t n, int32_t max_batch, void* stream, pm_net** out) {
+  if (!out) return inval("out is NULL");
+  *out = nullptr;
+  if (!pow2(n) || n < 8 || n > 1024) return inval("net region n must be a power of two in [8, 1024]");
+  if (max_batch < 1 || max_batch > 64) return inval("max_batch must be in [1, 64]");
+  pm_net* m = new pm_net();
+  m->st = static_cast<hipStream_t>(stream);
+  net::Buffers& b = m->b;
+  b.n = n;
+  b.max_batch = max_batch;
+  const size_t V1 = (size_t)net::level_voxels(n, 0) * max_batch;
+  const size_t V2 = (size_t)net::level_voxels(n, 1) * max_batch;
+  const size_t V3 = (size_t)net::level_voxels(n, 2) * max_batch;
+  const size_t P = (size_t)net::param_count();
+#define NALLOC(ptr, cnt)                                   \
+  do {                                                     \
+    pm_status s_ = nalloc(m, &(ptr), (cnt));               \
+    if (s_ != PM_OK) { pm_net_destroy(m); return s_; }     \
+  } while (0)
+  NALLOC(b.params, P);
+  NALLOC(b.grads, P);
+  NALLOC(b.adam_m, P);
+  NALLOC(b.adam_v, P);
+  for (int l = 0; l < net::NLAYER; ++l) {
+    const size_t cnt = (size_t)net::kLayers[l].taps * net::kLayers[l].cin_p * net::kLayers[l].cout;
+    NALLOC(b.wf[l], cnt);
+    NALLOC(b.wb[l], cnt);
+  }
+  NALLOC(b.x, 16 * V1);
+  NALLOC(b.a1, 16 * V1);
+  NALLOC(b.s1, 16 * V1);
+  NALLOC(b.a5, 16 * V1);
+  NALLOC(b.d1, 16 * V1);
+  NALLOC(b.g16a, 16 * V1);
+  NALLOC(b.g16b, 16 * V1);
+  NALLOC(b.gc1, 48 * V1);
+  NALLOC(b.p1, 16 * V2);
+  NALLOC(b.a2, 32 * V2);
+  NALLOC(b.s2, 32 * V2);
+  NALLOC(b.a4, 32 * V2);
+  NALLOC(b.d2, 32 * V2);
+  NALLOC(b.g32a, 32 * V2);
+  NALLOC(b.g32b, 32 * V2);
+  NALLOC(b.gc2, 96 * V2);
+  NALLOC(b.gp1, 16 * V2);
+  NALLOC(b.p2, 32 * V3);
+  NALLOC(b.a3, 64 * V3);
+  NALLOC(b.b3, 64 * V3);
+  NALLOC(b.g64a, 64 * V3);
+  NALLOC(b.g64b, 64 * V3);
+  NALLOC(b.gp2, 32 * V3);
+  NALLOC(b.yhat, 3 * V1);
+  NALLOC(b.target, 3 * V1);
+  NALLOC(b.rms, (size_t)max_batch);
+  NALLOC(b.sums, (size_t)max_batch + 64);
+  // weight-gradient partials: brick groups x 27 taps x the largest cin x cout (b3b: 64 x 64)
+  int64_t cc_max = 0;
+  for (int l = 0; l < net::NLAYER; ++l) {
+    const int64_t cc = (int64_t)net::kLayers[l].cin_p * net::kLayers[l].cout;
+    cc_max = cc > cc_max ? cc : cc_max;
+  }
+  b.partial_floats = (int64_t)net::kWgradGroups * 27 * cc_max;
+  NALLOC(b.partial, (size_t)b.partial_floats);
+  b.dpartial_count = 1024 * 52;
+  NALLOC(b.dpartial, (size_t)b.dpartial_count);
+#undef NALLOC
+  // zero-initialised parameters and optimiser state until pm_net_set_params
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = hipMemsetAsync(b.params, 0, P * sizeof(float), m->st);
+  if (e == hipSuccess) e = hipMemsetAsync(b.adam_m, 0, P * sizeof(float), m->st);
+  if (e == hipSuccess) e = hipMemsetAsync(b.adam_v, 0, P * sizeof(float), m->st);
+  if (e == hipSuccess) e = hipMemsetAsync(b.rms, 0, (size_t)max_batch * sizeof(double), m->st);
+  if (e == hipSuccess) e = net::pack_weights(b, m->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(m->st);
+  if (e != hipSuccess) {
+    pm_net_destroy(m);
+    return dev_fail(e, "pm_net_create");
+  }
+  *out = m;
+  return PM_OK;
+}
+
+pm_status pm_net_set_params(pm_net* m, const float* params) {
+  if (!m || !params) return inval("NULL argument");
+  const size_t P = (size_t)net::param_count();
+  HIPCHK(hipMemcpyAsync(m->b.params, params, P * sizeof(float), hipMemcpyHostToDevice, m->st));
+  HIPCHK(hipMemsetAsync(m->b.adam_m, 0, P * sizeof(float), m->st));
+  HIPCHK(hipMemsetAsync(m->b.adam_v, 0, P * sizeof(float), m->st));
+  m->adam_step = 0;
+  HIPCHK(net::pack_weights(m->b, m->st));
+  HIPCHK(hipStreamSynchronize(m->st));
+  return PM_OK;
+}
+
+pm_status pm_net_get_params(pm_net* m, float* params) {
+  if (!m || !params) return inval("NULL argument");
+  HIPCHK(hipMemcpyAsync(params, m->b.params, (size_t)net::param_count() * sizeof(float), hipMemcpyDeviceToHost,
+                        m->st));
+  HIPCHK(hipStreamSynchronize(m->st));
+  return PM_OK;
+}
+
+pm_status pm_net_get_grads(pm_net* m, float* grads) {
+  if (!m || !grads) return inval("NULL argument");
+  HIPCHK(hipMemcpyAsync(grads, m->b.grads, (size_t)net::param_count() * sizeof(float), hipMemcpyDeviceToHost,
+                        m->st));
+  HIPCHK(hipStreamSynchronize(m->st));
+  return PM_OK;
+}
+
+static pm_status check_slot(pm_net* m, int32_t slot) {
+  if (!m) return inval("net is NULL");
+  if (slot < 0 || slot >= m->b.max_batch) return inval("slot out of range");
+  return PM_OK;
+}
+
+static pm_status check_pair(pm_ctx* c, pm_net* m) {
+  if (!c || !m) return inval("NULL argument");
+  if (c->n != m->b.n) return inval("net region n differs from the context's n");
+  return PM_OK;
+}
+
+pm_status pm_net_input(pm_ctx* c, pm_net* m, const float* phiN, int32_t slot) {
+  pm_status s = check_pair(c, m);
+  if (s == PM_OK) s = check_slot(m, slot);
+  if (s != PM_OK) return s;
+  if (!phiN) return inval("phiN is NULL");
+  const double s_px = c->p.box / c->p.n;
+  HIPCHK(net::features(m->b, slot, phiN, c->N, 0.5 / s_px, c->p.a0, c->st));
+  return PM_OK;
+}
+
+pm_status pm_net_target(pm_ctx* c, pm_net* m, const float* phiN, const float* F, int32_t slot) {
+  pm_status s = check_pair(c, m);
+  if (s == PM_OK) s = check_slot(m, slot);
+  if (s != PM_OK) return s;
+  if (!phiN || !F) return inval("phiN and F are required");
+  const double s_px = c->p.box / c->p.n;
+  HIPCHK(net::target_from_field(m->b, slot, phiN, F, c->N, 0.5 / s_px, c->st));
+  return PM_OK;
+}
+
+pm_status pm_net_set_input(pm_net* m, int32_t slot, const float* x) {
+  pm_status s = check_slot(m, slot);
+  if (s != PM_OK) return s;
+  if (!x) return inval("x is NULL");
+  HIPCHK(net::set_input(m->b, slot, x, m->st));
+  return PM_OK;
+}
+
+pm_status pm_net_get_input(pm_net* m, int32_t slot, float* x) {
+  pm_status s = check_slot(m, slot);
+  if (s != PM_OK) return s;
+  if (!x) return inval("x is NULL");
+  HIPCHK(net::get_input(m->b, slot, x, m->st));
+  return PM_OK;
+}
+
+pm_status pm_net_set_target(pm_net* m, int32_t slot, const float* y) {
+  pm_status s = check_slot(m, slot);
+  if (s != PM_OK) return s;
+  if (!y) return inval("y is NULL");
+  const size_t V = (size_t)net::level_voxels(m->b.n, 0);
+  HIPCHK(hipMemcpyAsync(m->b.target + (size_t)slot * 3 * V, y, 3 * V * sizeof(float), hipMemcpyDeviceToDevice,
+                        m->st));
+  return PM_OK;
+}
+
+pm_status pm_net_get_target(pm_net* m, int32_t slot, float* y) {
+  pm_status s = check_slot(m, slot);
+  if (s != PM_OK) return s;
+  if (!y) return inval("y is NULL");
+  const size_t V = (size_t)net::level_voxels(m->b.n, 0);
+  HIPCHK(hipMemcpyAsync(y, m->b.target + (size_t)slot * 3 * V, 3 * V * sizeof(float), hipMemcpyDeviceToDevice,
+                        m->st));
+  return PM_OK;
+}
+
+pm_status pm_net_output(pm_net* m, int32_t slot, float* y) {
+  pm_status s = check_slot(m, slot);
+  if (s != PM_OK) return s;
+  if (!y) return inval("y is NULL");
+  const size_t V = (size_t)net::level_voxels(m->b.n, 0);
+  HIPCHK(hipMemcpyAsync(y, m->b.yhat + (size_t)slot * 3 * V, 3 * V * sizeof(float), hipMemcpyDeviceToDevice,
+                        m->st));
+  return PM_OK;
+}
+
+pm_status pm_net_get_rms(pm_net* m, int32_t slot, double* rms) {
+  pm_status s = check_slot(m, slot);
+  if (s != PM_OK) return s;
+  if (!rms) return inval("rms is NULL");
+  HIPCHK(hipMemcpyAsync(rms, m->b.rms + slot, sizeof(double), hipMemcpyDeviceToHost, m->st));
+  HIPCHK(hipStreamSynchronize(m->st));
+  return PM_OK;
+}
+
+pm_status pm_net_run(pm_net* m, int32_t batch) {
+  if (!m) return inval("net is NULL");
+  if (batch < 1 || batch > m->b.max_batch) return inval("batch out of range");
+  HIPCHK(net::forward(m->b, batch, m->st));
+  return PM_OK;
+}
+
+pm_status pm_net_backward(pm_net* m, int32_t batch, double* loss) {
+  if (!m) return inval("net is NULL");
+  if (batch < 1 || batch > m->b.max_batch) return inval("batch out of range");
+  HIPCHK(net::forward(m->b, batch, m->st));
+  HIPCHK(net::loss_backward(m->b, batch, m->st));
+  if (loss) {
+    HIPCHK(hipMemcpyAsync(loss, m->b.sums + m->b.max_batch, sizeof(double), hipMemcpyDeviceToHost, m->st));
+    HIPCHK(hipStreamSynchronize(m->st));
+  }
+  return PM_OK;
+}
+
+pm_status pm_net_adam(pm_net* m, float lr) {
+  if (!m) return inval("net is NULL");
+  if (!(lr >= 0.0f) || !isfinite(lr)) return inval("lr must be finite and >= 0");
+  m->adam_step += 1;
+  HIPCHK(net::adam(m->b, lr, 0.9f, 0.999f, 1e-8f, m->adam_step, m->st));
+  return PM_OK;
+}
+
+pm_status pm_net_train_step(pm_net* m, int32_t batch, float lr, double* loss) {
+  pm_status s = pm_net_backward(m, batch, loss);
+  if (s != PM_OK) return s;
+  return pm_net_adam(m, lr);
+}
+
+pm_status pm_net_forward(pm_ctx* c, pm_net* m, const float* phiN, float* H0) {
+  pm_status s = check_pair(c, m);
+  if (s != PM_OK) return s;
+  if (!phiN || !H0) return inval("phiN and H0 are required");
+  const double s_px = c->p.box / c->p.n;
+  HIPCHK(net::features(m->b, 0, phiN, c->N, 0.5 / s_px, c->p.a0, c->st));
+  HIPCHK(net::forward(m->b, 1, c->st));
+  const long long R = (long long)c->N * c->N * c->N;
+  HIPCHK(fill_zero(H0, 3 * R, c->st));
+  HIPCHK(net::start_field(m->b, H0, c->N, c->st));
   return PM_OK;
 }

@@ -440,7 +440,7 @@ __global__ __launch_bounds__(NT) void k_ypass(float2* spec, long long comp_strid
   store_cols<L, T, NT, Last::R, 2>(v, E, ptr, nv, P);
 }
 
-enum { Z_FWD = 0, Z_INV = 1, Z_NEWTON = 2, Z_CURL = 3, Z_CURL_FINAL = 4, Z_DIV = 5, Z_NEWTON_H0 = 6 };
+enum { Z_FWD = 0, Z_INV = 1, Z_NEWTON = 2, Z_CURL = 3, Z_CURL_FINAL = 4, Z_DIV = 5, Z_NEWTON_H0 = 6, Z_POISSON = 7 };
 
 template <int ZOP> struct ZComp;
 template <> struct ZComp<Z_FWD>        { static constexpr int IN = 1, OUT = 1; };
@@ -450,6 +450,7 @@ template <> struct ZComp<Z_NEWTON_H0>  { static constexpr int IN = 4, OUT = 3; }
 template <> struct ZComp<Z_CURL>       { static constexpr int IN = 3, OUT = 3; };
 template <> struct ZComp<Z_CURL_FINAL> { static constexpr int IN = 3, OUT = 1; };
 template <> struct ZComp<Z_DIV>        { static constexpr int IN = 3, OUT = 3; };
+template <> struct ZComp<Z_POISSON>    { static constexpr int IN = 1, OUT = 1; };
 
 // z pass: forward z transform of the input components, the spectral operator
 // at every (kx, ky, kz) in registers, inverse z transform, store.  A block
@@ -465,6 +466,7 @@ template <> struct ZComp<Z_DIV>        { static constexpr int IN = 3, OUT = 3; }
 //   Z_CURL      : g <- kt At (kt . g) / N^3
 //   Z_CURL_FINAL: phi_hat = i At (kt . g) / N^3 (one output component)
 //   Z_DIV       : F = F' + kt At kt . (g_N - F'), g_N = -i kappa phi_N (/N^3)
+//   Z_POISSON   : phi_N_hat = -4 pi G A rho_hat / N^3 (one component, in place)
 template <int L, int T, int NT, int HZ, int ZOP>
 __global__ __launch_bounds__(NT) void k_zpass(ZArgs a, const float2* __restrict__ tw) {
   constexpr int E = ColCfg<L, T, NT>::E;
@@ -538,6 +540,13 @@ __global__ __launch_bounds__(NT) void k_zpass(ZArgs a, const float2* __restrict_
       for (int r = 0; r < RL; ++r) {
         const int kz = j + r * (L / RL);
         const int e = u * RL + r;
+        if constexpr (ZOP == Z_POISSON) {
+          const float kzz = a.kv[kz];
+          const float k2 = kx * kx + ky * ky + kzz * kzz;
+          const float A = (k2 > 0.0f) ? 1.0f / k2 : 0.0f;
+          v[h * E + e] = cscale(v[h * E + e], a.newton_coef * A * a.scale);
+          continue;
+        }
         float2* v0 = v + (0 * HZ + h) * E + e;
         float2* v1 = v + (1 * HZ + h) * E + e;
         float2* v2 = v + (2 * HZ + h) * E + e;
@@ -714,6 +723,7 @@ hipError_t run_pass(const FftGeom& g, const PassDesc& d, hipStream_t st) {
     case PASS_Z_CURL: return launch_z<N, Z_CURL>(g, d.z, st);
     case PASS_Z_CURL_FINAL: return launch_z<N, Z_CURL_FINAL>(g, d.z, st);
     case PASS_Z_DIV: return launch_z<N, Z_DIV>(g, d.z, st);
+    case PASS_Z_POISSON: return launch_z<N, Z_POISSON>(g, d.z, st);
   }
   return hipErrorInvalidValue;
 }

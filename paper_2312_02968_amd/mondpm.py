@@ -71,9 +71,36 @@ def lib():
         L.pm_set_timing.argtypes = [VP, ctypes.c_int]
         L.pm_read_timing.argtypes = [VP, P(ctypes.c_double), P(ctypes.c_int64)]
         L.pm_last_error.restype = ctypes.c_char_p
+        I32, F32 = ctypes.c_int32, ctypes.c_float
+        L.pm_newton_potential.argtypes = [VP, VP, VP]
+        L.aqual_solve_field.argtypes = [VP, VP, VP, VP, VP, P(PmSolveInfo)]
+        L.pm_net_param_count.argtypes = []
+        L.pm_net_param_count.restype = I64
+        L.pm_net_create.argtypes = [I32, I32, VP, P(VP)]
+        L.pm_net_destroy.argtypes = [VP]
+        L.pm_net_set_params.argtypes = [VP, VP]
+        L.pm_net_get_params.argtypes = [VP, VP]
+        L.pm_net_get_grads.argtypes = [VP, VP]
+        L.pm_net_input.argtypes = [VP, VP, VP, I32]
+        L.pm_net_target.argtypes = [VP, VP, VP, VP, I32]
+        L.pm_net_set_input.argtypes = [VP, I32, VP]
+        L.pm_net_get_input.argtypes = [VP, I32, VP]
+        L.pm_net_set_target.argtypes = [VP, I32, VP]
+        L.pm_net_get_target.argtypes = [VP, I32, VP]
+        L.pm_net_run.argtypes = [VP, I32]
+        L.pm_net_output.argtypes = [VP, I32, VP]
+        L.pm_net_get_rms.argtypes = [VP, I32, P(D)]
+        L.pm_net_backward.argtypes = [VP, I32, P(D)]
+        L.pm_net_adam.argtypes = [VP, F32]
+        L.pm_net_train_step.argtypes = [VP, I32, F32, P(D)]
+        L.pm_net_forward.argtypes = [VP, VP, VP, VP]
         for f in ("pm_create", "pm_destroy", "pm_deposit", "aqual_solve", "smooth_accel", "interp_push",
                   "pm_step", "pm_diagnostics", "pm_fft_r2c", "pm_fft_c2r", "pm_set_timing",
-                  "pm_read_timing"):
+                  "pm_read_timing", "pm_newton_potential", "aqual_solve_field", "pm_net_create",
+                  "pm_net_destroy", "pm_net_set_params", "pm_net_get_params", "pm_net_get_grads",
+                  "pm_net_input", "pm_net_target", "pm_net_set_input", "pm_net_get_input",
+                  "pm_net_set_target", "pm_net_get_target", "pm_net_run", "pm_net_output", "pm_net_get_rms",
+                  "pm_net_backward", "pm_net_adam", "pm_net_train_step", "pm_net_forward"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -230,3 +257,163 @@ def pm_read_timing(ctx: Ctx):
     cnt = (ctypes.c_int64 * n)()
     _check(lib().pm_read_timing(ctx.handle, ms, cnt), "pm_read_timing")
     return {TIMERS[i]: (ms[i], cnt[i]) for i in range(n) if cnt[i] > 0}
+
+
+# ---------------------------------------------------------------------------
+# Newton potential, field solve and the learned start
+# ---------------------------------------------------------------------------
+
+def pm_newton_potential(ctx: Ctx, rho, phiN):
+    R = ctx.N ** 3
+    _check(lib().pm_newton_potential(ctx.handle, _ptr(rho, numel=R, name="rho"), _ptr(phiN, numel=R, name="phiN")),
+           "pm_newton_potential")
+    return phiN
+
+
+def aqual_solve_field(ctx: Ctx, rho, phi, F, H0=None, want_info=True):
+    R = ctx.N ** 3
+    info = PmSolveInfo()
+    _check(lib().aqual_solve_field(ctx.handle, _ptr(rho, numel=R, name="rho"),
+                                   _ptr(H0, numel=3 * R, name="H0"), _ptr(phi, numel=R, name="phi"),
+                                   _ptr(F, numel=3 * R, name="F"),
+                                   ctypes.byref(info) if want_info else None), "aqual_solve_field")
+    return info.to_dict() if want_info else None
+
+
+def pm_net_param_count() -> int:
+    return int(lib().pm_net_param_count())
+
+
+class Net:
+    """Owns a pm_net (learned-start network) bound to a stream."""
+
+    def __init__(self, n, max_batch=1, stream=None):
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        self.n = int(n)
+        self.max_batch = int(max_batch)
+        h = ctypes.c_void_p()
+        _check(lib().pm_net_create(self.n, self.max_batch, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)),
+               "pm_net_create")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().pm_net_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pm_net_create(n, max_batch=1, stream=None) -> Net:
+    return Net(n, max_batch, stream)
+
+
+def pm_net_destroy(net: Net):
+    net.close()
+
+
+def _host_f32(a, count, name):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.float32).reshape(-1)
+    if a.size != count:
+        raise ValueError(f"{name} has {a.size} elements, needs {count}")
+    return a
+
+
+def pm_net_set_params(net: Net, params):
+    P = pm_net_param_count()
+    a = _host_f32(params, P, "params")
+    _check(lib().pm_net_set_params(net.handle, a.ctypes.data_as(ctypes.c_void_p)), "pm_net_set_params")
+
+
+def pm_net_get_params(net: Net):
+    import numpy as np
+    a = np.empty(pm_net_param_count(), dtype=np.float32)
+    _check(lib().pm_net_get_params(net.handle, a.ctypes.data_as(ctypes.c_void_p)), "pm_net_get_params")
+    return a
+
+
+def pm_net_get_grads(net: Net):
+    import numpy as np
+    a = np.empty(pm_net_param_count(), dtype=np.float32)
+    _check(lib().pm_net_get_grads(net.handle, a.ctypes.data_as(ctypes.c_void_p)), "pm_net_get_grads")
+    return a
+
+
+def pm_net_input(ctx: Ctx, net: Net, phiN, slot=0):
+    _check(lib().pm_net_input(ctx.handle, net.handle, _ptr(phiN, numel=ctx.N ** 3, name="phiN"), int(slot)),
+           "pm_net_input")
+
+
+def pm_net_target(ctx: Ctx, net: Net, phiN, F, slot=0):
+    R = ctx.N ** 3
+    _check(lib().pm_net_target(ctx.handle, net.handle, _ptr(phiN, numel=R, name="phiN"),
+                               _ptr(F, numel=3 * R, name="F"), int(slot)), "pm_net_target")
+
+
+def pm_net_set_input(net: Net, slot, x):
+    _check(lib().pm_net_set_input(net.handle, int(slot), _ptr(x, numel=4 * net.n ** 3, name="x")),
+           "pm_net_set_input")
+
+
+def pm_net_get_input(net: Net, slot, x):
+    _check(lib().pm_net_get_input(net.handle, int(slot), _ptr(x, numel=4 * net.n ** 3, name="x")),
+           "pm_net_get_input")
+    return x
+
+
+def pm_net_set_target(net: Net, slot, y):
+    _check(lib().pm_net_set_target(net.handle, int(slot), _ptr(y, numel=3 * net.n ** 3, name="y")),
+           "pm_net_set_target")
+
+
+def pm_net_get_target(net: Net, slot, y):
+    _check(lib().pm_net_get_target(net.handle, int(slot), _ptr(y, numel=3 * net.n ** 3, name="y")),
+           "pm_net_get_target")
+    return y
+
+
+def pm_net_run(net: Net, batch=1):
+    _check(lib().pm_net_run(net.handle, int(batch)), "pm_net_run")
+
+
+def pm_net_output(net: Net, slot, y):
+    _check(lib().pm_net_output(net.handle, int(slot), _ptr(y, numel=3 * net.n ** 3, name="y")), "pm_net_output")
+    return y
+
+
+def pm_net_get_rms(net: Net, slot=0) -> float:
+    r = ctypes.c_double()
+    _check(lib().pm_net_get_rms(net.handle, int(slot), ctypes.byref(r)), "pm_net_get_rms")
+    return r.value
+
+
+def pm_net_backward(net: Net, batch=1, want_loss=True):
+    loss = ctypes.c_double()
+    _check(lib().pm_net_backward(net.handle, int(batch), ctypes.byref(loss) if want_loss else None),
+           "pm_net_backward")
+    return loss.value if want_loss else None
+
+
+def pm_net_adam(net: Net, lr):
+    _check(lib().pm_net_adam(net.handle, float(lr)), "pm_net_adam")
+
+
+def pm_net_train_step(net: Net, batch, lr, want_loss=True):
+    loss = ctypes.c_double()
+    _check(lib().pm_net_train_step(net.handle, int(batch), float(lr), ctypes.byref(loss) if want_loss else None),
+           "pm_net_train_step")
+    return loss.value if want_loss else None
+
+
+def pm_net_forward(ctx: Ctx, net: Net, phiN, H0):
+    R = ctx.N ** 3
+    _check(lib().pm_net_forward(ctx.handle, net.handle, _ptr(phiN, numel=R, name="phiN"),
+                                _ptr(H0, numel=3 * R, name="H0")), "pm_net_forward")
+    return H0

@@ -40,3 +40,15 @@ def test_host_side_argument_checks_without_gpu():
     assert M.pm_workspace_bytes(dict(good, n_pad=500), 0) == 0     # not a power of two
     assert M.pm_workspace_bytes(dict(good, sigma=3.0), 0) == 0     # ball radius > 10 cells
     assert M.pm_workspace_bytes(dict(good, iters=0), 0) == 0
+
+
+def test_net_parameter_layout_and_argument_checks_without_gpu():
+    from paper_2312_02968_amd import mondpm as M
+    from oracle import convnet as cn
+    import ctypes as C
+    assert M.pm_net_param_count() == sum(v.size for v in cn.init_params(0).values())
+    h = C.c_void_p()
+    L = M.lib()
+    assert L.pm_net_create(12, 1, None, C.byref(h)) == M.PM_E_INVAL      # not a power of two
+    assert L.pm_net_create(16, 0, None, C.byref(h)) == M.PM_E_INVAL      # no slots
+    assert L.pm_net_create(4, 1, None, C.byref(h)) == M.PM_E_INVAL       # too small for 3 levels

@@ -1,0 +1,248 @@
+"""GPU parity of the learned start through the C ABI: the BF16 network's
+forward pass, gradients and Adam step, its input features, training targets
+and start field, each against the FP64 oracle on the same inputs."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import convnet as cn
+from oracle import learned as ol
+from oracle import pm as orc
+import workloads as W
+from tests.gpu_util import dev, host, oparams, rel_l2, grid
+
+pytestmark = pytest.mark.gpu
+
+M = pytest.importorskip("paper_2312_02968_amd.mondpm")
+
+
+def flat(p):
+    return np.concatenate([np.concatenate([p[name + ".w"].reshape(-1), p[name + ".b"]])
+                           for name, _, _, _ in cn.LAYERS])
+
+
+def unflat(v):
+    p, o = {}, 0
+    for name, ci, co, k in cn.LAYERS:
+        nw = k ** 3 * ci * co
+        p[name + ".w"] = v[o:o + nw].reshape(k ** 3, ci, co)
+        p[name + ".b"] = v[o + nw:o + nw + co]
+        o += nw + co
+    return p
+
+
+def gpu_params(seed):
+    """FP32 parameters for the GPU and the oracle's view of them: the GPU uses
+    weights rounded to BF16 and FP32 biases."""
+    rng = np.random.default_rng(seed + 100)
+    p = cn.init_params(seed)
+    for k in p:
+        if k.endswith(".b"):
+            p[k] = 0.05 * rng.standard_normal(p[k].shape)
+    v32 = flat(p).astype(np.float32)
+    po = unflat(v32.astype(np.float64))
+    for k in po:
+        if k.endswith(".w"):
+            po[k] = cn.bf16_round(po[k])
+    return v32, po
+
+
+def net_inputs(rng, n):
+    x = rng.standard_normal((4, n, n, n))
+    x[3] = rng.uniform(-3.0, 2.0, (n, n, n))          # the log10 channel's range
+    return x.astype(np.float32)
+
+
+@pytest.mark.parametrize("n,batch", [(16, 2), (32, 1), (64, 1)])
+def test_net_forward_matches_oracle(n, batch):
+    # The oracle mirrors every BF16 rounding of the stored activations; what
+    # remains is FP32 vs FP64 accumulation, which can move a value across a
+    # BF16 rounding boundary (2^-8 relative) now and then.
+    rng = np.random.default_rng(n)
+    v32, po = gpu_params(1)
+    net = M.Net(n, batch)
+    M.pm_net_set_params(net, v32)
+    xs = [net_inputs(rng, n) for _ in range(batch)]
+    for b in range(batch):
+        M.pm_net_set_input(net, b, dev(xs[b]))
+    M.pm_net_run(net, batch)
+    for b in range(batch):
+        y = host(M.pm_net_output(net, b, torch.empty(3 * n ** 3, device="cuda"))).reshape(3, n, n, n)
+        yo, _ = cn.forward(po, xs[b].astype(np.float64), bf16=True)
+        print(f"forward n={n} slot {b}: rel_l2 {rel_l2(y, yo):.2e}")
+        assert rel_l2(y, yo) < 1e-2, (b, rel_l2(y, yo))
+    net.close()
+
+
+@pytest.mark.parametrize("n,batch", [(16, 2), (32, 2)])
+def test_net_gradients_and_adam_match_oracle(n, batch):
+    lr = 1e-3
+    rng = np.random.default_rng(7)
+    v32, po = gpu_params(2)
+    net = M.Net(n, batch)
+    M.pm_net_set_params(net, v32)
+    xs = [net_inputs(rng, n) for _ in range(batch)]
+    ts = [(0.5 * rng.standard_normal((3, n, n, n))).astype(np.float32) for _ in range(batch)]
+    for b in range(batch):
+        M.pm_net_set_input(net, b, dev(xs[b]))
+        M.pm_net_set_target(net, b, dev(ts[b]))
+    loss = M.pm_net_backward(net, batch)
+    g = unflat(M.pm_net_get_grads(net).astype(np.float64))
+
+    go = {k: np.zeros_like(v) for k, v in po.items()}
+    lo = 0.0
+    for b in range(batch):
+        y, cache = cn.forward(po, xs[b].astype(np.float64), bf16=True)
+        l, gy = cn.mse(y, ts[b].astype(np.float64))
+        lo += l / batch
+        gb = cn.backward(po, cache, gy / batch)
+        for k in go:
+            go[k] += gb[k]
+    assert abs(loss - lo) < 1e-4 * lo
+    # gradient tensors between layers are BF16 on the GPU (2^-9 relative per
+    # rounding, over at most 11 layers; measured up to 1e-3)
+    print("loss", loss, lo, "grad rel_l2:", {k: f"{rel_l2(g[k], go[k]):.1e}" for k in go})
+    for k in go:
+        assert rel_l2(g[k], go[k]) < 5e-3, (k, rel_l2(g[k], go[k]))
+
+    # Adam, first two steps with the same gradient: each moves every parameter
+    # by lr g / (|g| + eps), i.e. by lr against the sign of g where |g| >> eps
+    # signs are certain where |g| is well above the GPU's gradient error (below
+    # 5e-3 of the layer's rms gradient, checked above)
+    p0 = M.pm_net_get_params(net).astype(np.float64)
+    gflat = flat(go)
+    sure = flat({k: np.abs(v) > 0.05 * np.sqrt(np.mean(v * v)) for k, v in go.items()}).astype(bool)
+    print("elements with a certain sign:", sure.mean())
+    assert sure.mean() > 0.5
+    for step in (1, 2):
+        M.pm_net_adam(net, lr)
+        p1 = M.pm_net_get_params(net).astype(np.float64)
+        d = (p1 - p0)[sure]
+        assert np.allclose(d, -lr * np.sign(gflat[sure]), rtol=1e-3, atol=1e-6), step
+        p0 = p1
+    net.close()
+
+
+def test_net_training_step_at_training_size():
+    # 128^3 regions, batch 4 (the training shape; every weight-gradient launch
+    # uses its full set of brick groups).  Sizes the oracle cannot reach; the
+    # head's bias gradient has the closed form 2 mean(y - t) per channel, with
+    # y the output of the same forward pass.
+    n, batch = 128, 4
+    rng = np.random.default_rng(12)
+    v32, _ = gpu_params(5)
+    net = M.Net(n, batch)
+    M.pm_net_set_params(net, v32)
+    for b in range(batch):
+        M.pm_net_set_input(net, b, dev(net_inputs(rng, n)))
+        M.pm_net_set_target(net, b, torch.randn(3 * n ** 3, device="cuda") * 0.5)
+    loss = M.pm_net_backward(net, batch)
+    g = unflat(M.pm_net_get_grads(net).astype(np.float64))
+    d = []
+    for b in range(batch):
+        y = host(M.pm_net_output(net, b, torch.empty(3 * n ** 3, device="cuda"))).reshape(3, -1)
+        t = host(M.pm_net_get_target(net, b, torch.empty(3 * n ** 3, device="cuda"))).reshape(3, -1)
+        d.append(y - t)
+    d = np.concatenate(d, axis=1)
+    assert abs(loss - np.mean(d * d)) < 1e-5 * loss
+    assert np.allclose(g["out.b"], 2.0 * d.sum(axis=1) / d.size, rtol=1e-4, atol=1e-9)
+    assert all(np.all(np.isfinite(v)) for v in g.values())
+    l0 = loss
+    for _ in range(5):
+        M.pm_net_adam(net, 1e-3)
+        loss = M.pm_net_backward(net, batch)
+    assert np.isfinite(loss) and loss < l0
+    net.close()
+
+
+def test_net_training_reduces_loss():
+    n = 16
+    rng = np.random.default_rng(11)
+    v32, _ = gpu_params(3)
+    net = M.Net(n, 1)
+    M.pm_net_set_params(net, v32)
+    x = net_inputs(rng, n)
+    t = (0.3 * x[:3] + 0.1).astype(np.float32)
+    M.pm_net_set_input(net, 0, dev(x))
+    M.pm_net_set_target(net, 0, dev(t))
+    l0 = M.pm_net_train_step(net, 1, 1e-3)
+    for _ in range(40):
+        l = M.pm_net_train_step(net, 1, 1e-3)
+    assert np.isfinite(l) and l < 0.5 * l0
+    net.close()
+
+
+def _cloud_rho(n, seed=3, N=300):
+    w = W.random_cloud(seed, n, N)
+    p = w["params"]
+    rho = orc.deposit(oparams(p), w["pos"].astype(np.float64), w["mass"].astype(np.float64))
+    return p, rho.astype(np.float32)
+
+
+def test_newton_potential_features_and_target():
+    n = 16
+    p, rho32 = _cloud_rho(n)
+    p = dict(p, iters=3, flags=M.PM_F_RESIDUAL)
+    op = oparams(p)
+    N = p["n_pad"]
+    ctx = M.pm_create(p, 0)
+    net = M.Net(n, 2)
+    rho = dev(rho32)
+    phiN = grid(N)
+    M.pm_newton_potential(ctx, rho, phiN)
+    phiN_o, gN_o = orc.newton_potential(op, rho32.astype(np.float64))
+    assert rel_l2(host(phiN).reshape(N, N, N), phiN_o) < 1e-5
+
+    M.pm_net_input(ctx, net, phiN, 1)
+    x = host(M.pm_net_get_input(net, 1, torch.empty(4 * n ** 3, device="cuda"))).reshape(4, n, n, n)
+    xo, rms_o = ol.net_input(op, gN_o)
+    assert abs(M.pm_net_get_rms(net, 1) - rms_o) < 1e-5 * rms_o
+    # stored in BF16: within one BF16 step of the rounded FP64 value
+    assert np.all(np.abs(x - xo) <= 2.0 ** -7 * np.abs(xo) + 1e-4)
+
+    phi = grid(N)
+    F = torch.zeros(3 * N ** 3, device="cuda")
+    info = M.aqual_solve_field(ctx, rho, phi, F)
+    _, io = orc.aqual_solve(op, rho32.astype(np.float64), keep_fields=True)
+    Fo = io.gN + io.H
+    assert info["iterations"] == 3
+    assert rel_l2(host(F).reshape(3, N, N, N), Fo) < 1e-4
+    M.pm_net_target(ctx, net, phiN, F, 1)
+    t = host(M.pm_net_get_target(net, 1, torch.empty(3 * n ** 3, device="cuda"))).reshape(3, n, n, n)
+    to = ol.target(op, io.H, rms_o)
+    assert rel_l2(t, to) < 1e-3
+    net.close()
+    ctx.close()
+
+
+def test_learned_start_field_and_solve():
+    n = 16
+    p, rho32 = _cloud_rho(n, seed=5)
+    op = oparams(p)
+    N = p["n_pad"]
+    v32, po = gpu_params(4)
+    ctx = M.pm_create(p, 0)
+    net = M.Net(n, 1)
+    M.pm_net_set_params(net, v32)
+    rho = dev(rho32)
+    phiN = grid(N)
+    M.pm_newton_potential(ctx, rho, phiN)
+    H0 = torch.empty(3 * N ** 3, device="cuda")
+    M.pm_net_forward(ctx, net, phiN, H0)
+    _, gN_o = orc.newton_potential(op, rho32.astype(np.float64))
+    xo, rms_o = ol.net_input(op, gN_o)
+    yo, _ = cn.forward(po, xo, bf16=True)
+    H0o = ol.start_field(op, yo, rms_o)
+    H0g = host(H0).reshape(3, N, N, N)
+    assert rel_l2(H0g, H0o) < 2e-2
+    r = ol.region(op)
+    outside = H0g.copy()
+    outside[:, r, r, r] = 0.0
+    assert not outside.any()
+    # the solve from this start against the oracle's solve from its own start
+    phi = grid(N)
+    M.aqual_solve(ctx, rho, phi, H0=H0)
+    phio, _ = orc.aqual_solve(op, rho32.astype(np.float64), H0=H0o)
+    assert rel_l2(host(phi).reshape(N, N, N), phio) < 2e-3
+    net.close()
+    ctx.close()
