@@ -193,10 +193,13 @@ pm_status aqual_solve_field(pm_ctx* ctx, const float* rho, const float* H0, floa
  * starts from zero and notes that a good start saves iterations.  A 3-level
  * encoder-decoder of 3x3x3 convolutions (16 / 32 / 64 channels, ReLU, 2x
  * average pooling, nearest 2x upsampling with skip concatenation, a 1x1x1
- * head to 3 channels) maps the Newton field on the physical n^3 region to a
- * start:  rms = sqrt(mean |g_N|^2) over the region,
- *         x = [g_N / rms, log10(|g_N| / a0 + 1e-30)],
- *         H0 = rms * net(x) on the region, zero outside;
+ * head to 3 channels) predicts H from the Newton field.  H fills the whole
+ * periodic box (about half of it lies outside the physical region), so the
+ * network sees the whole box at half resolution, n = n_pad / 2 voxels per
+ * axis, each the mean of a 2x2x2 block of cells, with periodic convolutions:
+ *         g_c = block mean of g_N,  rms = sqrt(mean |g_c|^2),
+ *         x = [g_c / rms, log10(|g_c| / a0 + 1e-30)],
+ *         H0 = rms * net(x), each value repeated over its 2x2x2 block;
  * aqual_solve then starts from the divergence-free part of H0.  Operands are
  * BF16 on the matrix cores with FP32 accumulation; parameters are FP32.
  * Parameter vector (pm_net_param_count floats): for each layer in the order
@@ -208,9 +211,9 @@ pm_status aqual_solve_field(pm_ctx* ctx, const float* rho, const float* H0, floa
  * stream given to pm_net_create. */
 typedef struct pm_net pm_net;
 int64_t   pm_net_param_count(void);
-/* n: region size (power of two, 8..1024); max_batch: slots for training
- * pairs (1..64).  Parameters start at zero; set them with pm_net_set_params.
- * Synchronises. */
+/* n: voxels per axis (power of two, 8..512; n_pad / 2 of the contexts it is
+ * used with); max_batch: slots for training pairs (1..64).  Parameters start
+ * at zero; set them with pm_net_set_params.  Synchronises. */
 pm_status pm_net_create(int32_t n, int32_t max_batch, void* stream, pm_net** out);
 pm_status pm_net_destroy(pm_net* net);
 /* params (host float [P]) in; also clears the optimiser state.  Synchronises. */
@@ -222,11 +225,11 @@ pm_status pm_net_get_grads(pm_net* net, float* grads);
 /* input channels of slot from phiN (device float [n_pad^3], the Newton
  * potential of the context's box; g_N = -D phi_N by central differences). */
 pm_status pm_net_input(pm_ctx* ctx, pm_net* net, const float* phiN, int32_t slot);
-/* training target of slot: (F - g_N) / rms on the region, F as returned by
+/* training target of slot: block mean of (F - g_N) / rms, F as returned by
  * aqual_solve_field for the same rho, rms that of pm_net_input for the slot. */
 pm_status pm_net_target(pm_ctx* ctx, pm_net* net, const float* phiN, const float* F, int32_t slot);
 /* direct input / target of a slot: x device float [4][n^3], y device float
- * [3][n^3] (region voxels, x fastest). */
+ * [3][n^3] (x fastest). */
 pm_status pm_net_set_input(pm_net* net, int32_t slot, const float* x);
 pm_status pm_net_set_target(pm_net* net, int32_t slot, const float* y);
 /* the input channels of a slot as stored (BF16 values), device float [4][n^3]. */
@@ -247,8 +250,7 @@ pm_status pm_net_backward(pm_net* net, int32_t batch, double* loss);
 pm_status pm_net_adam(pm_net* net, float lr);
 pm_status pm_net_train_step(pm_net* net, int32_t batch, float lr, double* loss);
 /* the learned start for the context's box: input from phiN, forward, H0
- * (device float [3][n_pad^3], overwritten: rms * net(x) on the region, zero
- * elsewhere).  Uses slot 0. */
+ * (device float [3][n_pad^3], overwritten).  Uses slot 0. */
 pm_status pm_net_forward(pm_ctx* ctx, pm_net* net, const float* phiN, float* H0);
 
 /* Last HIP error string seen by the library (host, static storage). */

@@ -66,14 +66,15 @@ def init_params(seed=0, scale=1.0):
     return p
 
 
-def conv3d(x, w, b):
-    """Zero-padded 3D convolution (cross-correlation): out[o, v] =
-    b[o] + sum over taps t and input channels c of x[c, v + tap_t] w[t, c, o]."""
+def conv3d(x, w, b, periodic=False):
+    """3D convolution (cross-correlation): out[o, v] = b[o] + sum over taps t
+    and input channels c of x[c, v + tap_t] w[t, c, o], with x zero outside
+    the array, or periodic when periodic=True."""
     C, D, H, W = x.shape
     taps = w.shape[0]
     if taps == 1:
         return np.einsum("cdhw,co->odhw", x, w[0]) + b[:, None, None, None]
-    xp = np.pad(x, ((0, 0), (1, 1), (1, 1), (1, 1)))
+    xp = np.pad(x, ((0, 0), (1, 1), (1, 1), (1, 1)), mode="wrap" if periodic else "constant")
     out = np.zeros((w.shape[2], D, H, W))
     for t, (dz, dy, dx) in enumerate(TAPS):
         xs = xp[:, 1 + dz:1 + dz + D, 1 + dy:1 + dy + H, 1 + dx:1 + dx + W]
@@ -81,7 +82,7 @@ def conv3d(x, w, b):
     return out + b[:, None, None, None]
 
 
-def conv3d_backward(x, w, gout):
+def conv3d_backward(x, w, gout, periodic=False):
     """Gradients of conv3d with respect to x, w and b."""
     C, D, H, W = x.shape
     taps = w.shape[0]
@@ -90,13 +91,21 @@ def conv3d_backward(x, w, gout):
         gw = np.einsum("cdhw,odhw->co", x, gout)[None]
         gx = np.einsum("odhw,co->cdhw", gout, w[0])
         return gx, gw, gb
-    xp = np.pad(x, ((0, 0), (1, 1), (1, 1), (1, 1)))
+    xp = np.pad(x, ((0, 0), (1, 1), (1, 1), (1, 1)), mode="wrap" if periodic else "constant")
     gxp = np.zeros_like(xp)
     gw = np.zeros_like(w)
     for t, (dz, dy, dx) in enumerate(TAPS):
         sl = (slice(None), slice(1 + dz, 1 + dz + D), slice(1 + dy, 1 + dy + H), slice(1 + dx, 1 + dx + W))
         gw[t] = np.einsum("cdhw,odhw->co", xp[sl], gout, optimize=True)
         gxp[sl] += np.einsum("odhw,co->cdhw", gout, w[t], optimize=True)
+    if periodic:
+        # the halo cells are copies of the opposite faces: fold their gradient back
+        # (halo index 0 holds the last cell, index -1 the first)
+        for ax in (1, 2, 3):
+            first, last, h0, h1 = ([slice(None)] * 4 for _ in range(4))
+            first[ax], last[ax], h0[ax], h1[ax] = 1, -2, 0, -1
+            gxp[tuple(last)] += gxp[tuple(h0)]
+            gxp[tuple(first)] += gxp[tuple(h1)]
     return gxp[:, 1:-1, 1:-1, 1:-1], gw, gb
 
 
@@ -120,13 +129,14 @@ def up2_backward(g):
     return g.reshape(C, D // 2, 2, H // 2, 2, W // 2, 2).sum(axis=(2, 4, 6))
 
 
-def forward(p, x, bf16=False):
-    """Network output for input x [4, n, n, n] and the cache for backward."""
+def forward(p, x, bf16=False, periodic=False):
+    """Network output for input x [4, n, n, n] and the cache for backward
+    (periodic: convolutions wrap around the array, as on the FFT box)."""
     r = bf16_round if bf16 else (lambda a: a)
-    cache = {}
+    cache = {"periodic": periodic}
 
     def cr(name, a, relu=True):
-        z = conv3d(a, p[name + ".w"], p[name + ".b"])
+        z = conv3d(a, p[name + ".w"], p[name + ".b"], periodic)
         cache[name] = (a, z)
         return r(np.maximum(z, 0.0)) if relu else z
 
@@ -146,11 +156,13 @@ def backward(p, cache, gy):
     """Gradients of all parameters given dL/dy (activations as in the cache)."""
     g = {}
 
+    periodic = cache["periodic"]
+
     def br(name, gout, relu=True):
         a, z = cache[name]
         if relu:
             gout = gout * (z > 0.0)
-        ga, gw, gb = conv3d_backward(a, p[name + ".w"], gout)
+        ga, gw, gb = conv3d_backward(a, p[name + ".w"], gout, periodic)
         g[name + ".w"], g[name + ".b"] = gw, gb
         return ga
 

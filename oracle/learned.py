@@ -5,16 +5,18 @@ leg may use this module).
 The fixed-point iteration of Sect. 2.1 may start from any divergence-free H;
 the paper starts from zero and notes that a good start (its example: the H of
 the previous time step) cuts the iterations needed.  Here the start is
-predicted from the Newton field on the physical n^3 region (parity unpinned
-against the paper, which has no network):
+predicted from the Newton field (parity unpinned against the paper, which has
+no network).  H lives on the whole periodic n_pad^3 box, half of it outside
+the physical region, so the network sees the whole box at half resolution:
 
-    rms   = sqrt(mean over the region of |g_N|^2)
-    x     = [g_N / rms (3 channels), log10(|g_N| / a0 + 1e-30)]
-    y_hat = net(x)                           (3 channels, the region)
-    H0    = zero extension of rms * y_hat to the n_pad^3 box
+    g_c   = mean of g_N over each 2 x 2 x 2 block of the box ((n_pad/2)^3)
+    rms   = sqrt(mean of |g_c|^2)
+    x     = [g_c / rms (3 channels), log10(|g_c| / a0 + 1e-30)]
+    y_hat = net(x), periodic convolutions       (3 channels, (n_pad/2)^3)
+    H0    = rms * y_hat, each value repeated over its 2 x 2 x 2 block
 
-and the solver takes the divergence-free part of H0.  The training target
-for a solved field H* is H* / rms on the region.
+and the solver takes the divergence-free part of H0.  The training target for
+a solved field H* is the block mean of H* divided by rms.
 """
 from __future__ import annotations
 
@@ -25,11 +27,15 @@ import numpy as np
 from . import pm
 
 
-def region(p: pm.Params):
-    """Index slice of the physical n^3 region inside the n_pad^3 box (the
-    n cells centred on the box centre, Sect. 3)."""
-    lo = p.n_pad // 2 - p.n // 2
-    return slice(lo, lo + p.n)
+def coarse(a):
+    """Mean over 2 x 2 x 2 blocks of the last three axes."""
+    C, D, H, W = a.shape
+    return a.reshape(C, D // 2, 2, H // 2, 2, W // 2, 2).mean(axis=(2, 4, 6))
+
+
+def fine(a):
+    """Each value repeated over a 2 x 2 x 2 block (inverse of coarse on such fields)."""
+    return np.repeat(np.repeat(np.repeat(a, 2, axis=1), 2, axis=2), 2, axis=3)
 
 
 def newton_field(p: pm.Params, rho):
@@ -40,9 +46,8 @@ def newton_field(p: pm.Params, rho):
 
 
 def net_input(p: pm.Params, gN):
-    """Network input [4, n, n, n] and the scale rms."""
-    r = region(p)
-    g = gN[:, r, r, r]
+    """Network input [4, n_pad/2, n_pad/2, n_pad/2] and the scale rms."""
+    g = coarse(gN)
     mag = np.sqrt((g * g).sum(axis=0))
     rms = math.sqrt(float((mag * mag).mean()))
     scale = 1.0 / rms if rms > 0.0 else 0.0
@@ -51,14 +56,10 @@ def net_input(p: pm.Params, gN):
 
 
 def start_field(p: pm.Params, y_hat, rms):
-    """H0 [3, n_pad, n_pad, n_pad]: rms * y_hat on the region, zero outside."""
-    r = region(p)
-    H0 = np.zeros((3, p.n_pad, p.n_pad, p.n_pad))
-    H0[:, r, r, r] = rms * np.asarray(y_hat, dtype=np.float64)
-    return H0
+    """H0 [3, n_pad, n_pad, n_pad] = rms * y_hat repeated over 2 x 2 x 2 blocks."""
+    return rms * fine(np.asarray(y_hat, dtype=np.float64))
 
 
 def target(p: pm.Params, H, rms):
-    """Training target: the solved H on the region divided by rms."""
-    r = region(p)
-    return H[:, r, r, r] / rms
+    """Training target: block mean of the solved H divided by rms."""
+    return coarse(H) / rms

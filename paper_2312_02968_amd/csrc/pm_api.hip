@@ -656,7 +656,7 @@ pm_status pm_net_destroy(pm_net* m) {
 pm_status pm_net_create(int32_t n, int32_t max_batch, void* stream, pm_net** out) {
   if (!out) return inval("out is NULL");
   *out = nullptr;
-  if (!pow2(n) || n < 8 || n > 1024) return inval("net region n must be a power of two in [8, 1024]");
+  if (!pow2(n) || n < 8 || n > 512) return inval("net size n must be a power of two in [8, 512]");
   if (max_batch < 1 || max_batch > 64) return inval("max_batch must be in [1, 64]");
   pm_net* m = new pm_net();
   m->st = static_cast<hipStream_t>(stream);
@@ -771,7 +771,7 @@ static pm_status check_slot(pm_net* m, int32_t slot) {
 
 static pm_status check_pair(pm_ctx* c, pm_net* m) {
   if (!c || !m) return inval("NULL argument");
-  if (c->n != m->b.n) return inval("net region n differs from the context's n");
+  if (c->N != 2 * m->b.n) return inval("net size n must be half the context's n_pad");
   return PM_OK;
 }
 
@@ -781,7 +781,7 @@ pm_status pm_net_input(pm_ctx* c, pm_net* m, const float* phiN, int32_t slot) {
   if (s != PM_OK) return s;
   if (!phiN) return inval("phiN is NULL");
   const double s_px = c->p.box / c->p.n;
-  HIPCHK(net::features(m->b, slot, phiN, c->N, 0.5 / s_px, c->p.a0, c->st));
+  HIPCHK(net::features(m->b, slot, phiN, 0.5 / s_px, c->p.a0, c->st));
   return PM_OK;
 }
 
@@ -791,7 +791,7 @@ pm_status pm_net_target(pm_ctx* c, pm_net* m, const float* phiN, const float* F,
   if (s != PM_OK) return s;
   if (!phiN || !F) return inval("phiN and F are required");
   const double s_px = c->p.box / c->p.n;
-  HIPCHK(net::target_from_field(m->b, slot, phiN, F, c->N, 0.5 / s_px, c->st));
+  HIPCHK(net::target_from_field(m->b, slot, phiN, F, 0.5 / s_px, c->st));
   return PM_OK;
 }
 
@@ -888,10 +888,8 @@ pm_status pm_net_forward(pm_ctx* c, pm_net* m, const float* phiN, float* H0) {
   if (s != PM_OK) return s;
   if (!phiN || !H0) return inval("phiN and H0 are required");
   const double s_px = c->p.box / c->p.n;
-  HIPCHK(net::features(m->b, 0, phiN, c->N, 0.5 / s_px, c->p.a0, c->st));
+  HIPCHK(net::features(m->b, 0, phiN, 0.5 / s_px, c->p.a0, c->st));
   HIPCHK(net::forward(m->b, 1, c->st));
-  const long long R = (long long)c->N * c->N * c->N;
-  HIPCHK(fill_zero(H0, 3 * R, c->st));
-  HIPCHK(net::start_field(m->b, H0, c->N, c->st));
+  HIPCHK(net::start_field(m->b, H0, c->st));
   return PM_OK;
 }

@@ -27,7 +27,7 @@ int64_t bias_offset(int layer);
 
 // Device buffers of one network (owned by the C ABI's pm_net).
 struct Buffers {
-  int n = 0;          // region size per axis (level 1)
+  int n = 0;          // voxels per axis at level 1 (half the FFT box)
   int max_batch = 0;
   float* params = nullptr;   // FP32 master parameters [P]
   float* grads = nullptr;    // [P]
@@ -60,15 +60,17 @@ hipError_t forward(const Buffers& b, int batch, hipStream_t st);
 hipError_t loss_backward(const Buffers& b, int batch, hipStream_t st);
 hipError_t adam(const Buffers& b, float lr, float beta1, float beta2, float eps, int step, hipStream_t st);
 
-// Network input of one slot from the Newton potential phiN on the n_pad^3 box:
-// g_N = -D phi_N (central differences) on the region, rms, and the channels.
-hipError_t features(const Buffers& b, int slot, const float* phiN, int n_pad, double inv_2s, double a0,
-                    hipStream_t st);
-// Training target of one slot: (F - g_N) / rms on the region (F: [3][n_pad^3]).
-hipError_t target_from_field(const Buffers& b, int slot, const float* phiN, const float* F, int n_pad,
-                             double inv_2s, hipStream_t st);
-// H0 [3][n_pad^3]: rms * yhat of slot 0 on the region (the caller zeroes the rest).
-hipError_t start_field(const Buffers& b, float* H0, int n_pad, hipStream_t st);
+// The network works on the periodic FFT box of N = 2 n cells per axis at half
+// resolution (n^3 voxels, each the mean of a 2 x 2 x 2 block of cells).
+// Input of one slot from the Newton potential phiN [N^3]: g_N = -D phi_N
+// (central differences), its block means g_c, rms = sqrt(mean |g_c|^2), and
+// the channels [g_c / rms, log10(|g_c| / a0 + 1e-30)].
+hipError_t features(const Buffers& b, int slot, const float* phiN, double inv_2s, double a0, hipStream_t st);
+// Training target of one slot: block mean of (F - g_N) / rms (F: [3][N^3]).
+hipError_t target_from_field(const Buffers& b, int slot, const float* phiN, const float* F, double inv_2s,
+                             hipStream_t st);
+// H0 [3][N^3]: rms * yhat of slot 0 repeated over each 2 x 2 x 2 block.
+hipError_t start_field(const Buffers& b, float* H0, hipStream_t st);
 // Test helpers: FP32 [4][n^3] (device) -> input channels of a slot.
 hipError_t set_input(const Buffers& b, int slot, const float* x4, hipStream_t st);
 // and back: the 4 input channels of a slot as FP32 [4][n^3] (device).

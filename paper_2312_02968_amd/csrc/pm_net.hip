@@ -69,14 +69,17 @@ __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
 
 __device__ __forceinline__ float bf(bf16 v) { return (float)v; }
 
-// One 16-byte group of 8 input channels of voxel (gx, gy, gz): channels below
-// C0 from src0 (resolution n), the rest from src1 at half resolution (the
-// nearest-neighbour upsampled coarse tensor); zero outside the region.
+// One 16-byte group of 8 input channels of voxel (gx, gy, gz), taken modulo n
+// (the grids are periodic, like the FFT box they sample): channels below C0
+// from src0 (resolution n), the rest from src1 at half resolution (the
+// nearest-neighbour upsampled coarse tensor).  n is a power of two.
 template <int CIN, int C0>
 __device__ __forceinline__ uint4 load_in8(const bf16* src0, const bf16* src1, int n, int b, int gx, int gy, int gz,
                                           int c) {
-  uint4 v = make_uint4(0u, 0u, 0u, 0u);
-  if (gx < 0 || gx >= n || gy < 0 || gy >= n || gz < 0 || gz >= n) return v;
+  uint4 v;
+  gx &= n - 1;
+  gy &= n - 1;
+  gz &= n - 1;
   if (c < C0) {
     const int64_t idx = (((int64_t)b * n + gz) * n + gy) * n + gx;
     v = *reinterpret_cast<const uint4*>(src0 + idx * C0 + c);
@@ -543,13 +546,6 @@ __global__ void k_head_grads(const double* __restrict__ sums, float* gw, float* 
   if (t == 0) *loss = sums[51] * inv_count;
 }
 
-// Region voxel v -> box index of a [n_pad]^3 grid; the region is the n^3
-// block centred on the box centre.
-__device__ __forceinline__ int64_t box_index(int x, int y, int z, int n, int N) {
-  const int lo = N / 2 - n / 2;
-  return (((int64_t)(z + lo)) * N + (y + lo)) * N + (x + lo);
-}
-
 // Central-difference gradient D phi at box cell (x, y, z) (periodic).
 __device__ __forceinline__ void dphi(const float* __restrict__ phi, int x, int y, int z, int N, float inv_2s,
                                      float* d) {
@@ -561,71 +557,104 @@ __device__ __forceinline__ void dphi(const float* __restrict__ phi, int x, int y
   d[2] = (phi[(int64_t)((z + 1) & m) * NN + yr + x] - phi[(int64_t)((z - 1) & m) * NN + yr + x]) * inv_2s;
 }
 
-__global__ __launch_bounds__(NT) void k_feat_sumsq(const float* __restrict__ phi, int n, int N, float inv_2s,
-                                                   double* part) {
+// Block mean of g_N = -D phi_N over the 2 x 2 x 2 cells of coarse voxel (X, Y, Z).
+__device__ __forceinline__ void coarse_gN(const float* __restrict__ phi, int X, int Y, int Z, int N, float inv_2s,
+                                          float* g) {
+  g[0] = g[1] = g[2] = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    float d[3];
+    dphi(phi, 2 * X + (k & 1), 2 * Y + ((k >> 1) & 1), 2 * Z + (k >> 2), N, inv_2s, d);
+    g[0] -= d[0];
+    g[1] -= d[1];
+    g[2] -= d[2];
+  }
+  g[0] *= 0.125f;
+  g[1] *= 0.125f;
+  g[2] *= 0.125f;
+}
+
+// coarse voxel index v of an n^3 grid (n = N / 2) -> (X, Y, Z)
+__device__ __forceinline__ void coarse_xyz(int64_t v, int n, int& X, int& Y, int& Z) {
+  X = (int)(v % n);
+  Y = (int)((v / n) % n);
+  Z = (int)(v / ((int64_t)n * n));
+}
+
+__global__ __launch_bounds__(NT) void k_feat_sumsq(const float* __restrict__ phi, int n, float inv_2s, double* part) {
   double acc[1] = {0.0};
-  const int lo = N / 2 - n / 2;
+  const int N = 2 * n;
   const int64_t nvox = (int64_t)n * n * n;
   for (int64_t v = blockIdx.x * (int64_t)NT + threadIdx.x; v < nvox; v += (int64_t)gridDim.x * NT) {
-    const int x = (int)(v % n), y = (int)((v / n) % n), z = (int)(v / ((int64_t)n * n));
-    float d[3];
-    dphi(phi, x + lo, y + lo, z + lo, N, inv_2s, d);
-    acc[0] += (double)d[0] * d[0] + (double)d[1] * d[1] + (double)d[2] * d[2];
+    int X, Y, Z;
+    coarse_xyz(v, n, X, Y, Z);
+    float g[3];
+    coarse_gN(phi, X, Y, Z, N, inv_2s, g);
+    acc[0] += (double)g[0] * g[0] + (double)g[1] * g[1] + (double)g[2] * g[2];
   }
   block_reduce_store<1>(acc, part);
 }
 
-// x[v] = [g / rms, log10(|g| / a0 + 1e-30), 0 ...] with g = -D phi_N.
-__global__ __launch_bounds__(NT) void k_feat_write(const float* __restrict__ phi, int n, int N, float inv_2s,
-                                                   float inv_a0, const double* __restrict__ sumsq, double* rms_out,
+// x[v] = [g_c / rms, log10(|g_c| / a0 + 1e-30), 0 ...]
+__global__ __launch_bounds__(NT) void k_feat_write(const float* __restrict__ phi, int n, float inv_2s, float inv_a0,
+                                                   const double* __restrict__ sumsq, double* rms_out,
                                                    bf16* __restrict__ x) {
+  const int N = 2 * n;
   const int64_t nvox = (int64_t)n * n * n;
   const double rms = sqrt(*sumsq / (double)nvox);
   const float scale = rms > 0.0 ? (float)(1.0 / rms) : 0.0f;
   if (blockIdx.x == 0 && threadIdx.x == 0) *rms_out = rms;
-  const int lo = N / 2 - n / 2;
   for (int64_t v = blockIdx.x * (int64_t)NT + threadIdx.x; v < nvox; v += (int64_t)gridDim.x * NT) {
-    const int xx = (int)(v % n), y = (int)((v / n) % n), z = (int)(v / ((int64_t)n * n));
-    float d[3];
-    dphi(phi, xx + lo, y + lo, z + lo, N, inv_2s, d);
-    const float mag = sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    int X, Y, Z;
+    coarse_xyz(v, n, X, Y, Z);
+    float g[3];
+    coarse_gN(phi, X, Y, Z, N, inv_2s, g);
+    const float mag = sqrtf(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
     uint4 o0 = make_uint4(0u, 0u, 0u, 0u), o1 = make_uint4(0u, 0u, 0u, 0u);
     bf16* e = reinterpret_cast<bf16*>(&o0);
-    e[0] = (bf16)(-d[0] * scale);
-    e[1] = (bf16)(-d[1] * scale);
-    e[2] = (bf16)(-d[2] * scale);
+    e[0] = (bf16)(g[0] * scale);
+    e[1] = (bf16)(g[1] * scale);
+    e[2] = (bf16)(g[2] * scale);
     e[3] = (bf16)log10f(mag * inv_a0 + 1e-30f);
     *reinterpret_cast<uint4*>(x + v * 16) = o0;
     *reinterpret_cast<uint4*>(x + v * 16 + 8) = o1;
   }
 }
 
-// target[c][v] = (F[c] - g_N[c]) / rms = (F[c] + D_c phi_N) / rms on the region
+// target[c][v] = block mean of (F[c] - g_N[c]) = (F[c] + D_c phi_N), over rms
 __global__ __launch_bounds__(NT) void k_target(const float* __restrict__ phi, const float* __restrict__ F, int n,
-                                               int N, float inv_2s, const double* __restrict__ rms,
-                                               float* __restrict__ t) {
+                                               float inv_2s, const double* __restrict__ rms, float* __restrict__ t) {
+  const int N = 2 * n;
   const int64_t nvox = (int64_t)n * n * n, cs = (int64_t)N * N * N;
   const double r = *rms;
-  const float inv = r > 0.0 ? (float)(1.0 / r) : 0.0f;
-  const int lo = N / 2 - n / 2;
+  const float inv = r > 0.0 ? (float)(0.125 / r) : 0.0f;
   for (int64_t v = blockIdx.x * (int64_t)NT + threadIdx.x; v < nvox; v += (int64_t)gridDim.x * NT) {
-    const int x = (int)(v % n), y = (int)((v / n) % n), z = (int)(v / ((int64_t)n * n));
-    float d[3];
-    dphi(phi, x + lo, y + lo, z + lo, N, inv_2s, d);
-    const int64_t j = box_index(x, y, z, n, N);
+    int X, Y, Z;
+    coarse_xyz(v, n, X, Y, Z);
+    float h[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int c = 0; c < 3; ++c) t[c * nvox + v] = (F[c * cs + j] + d[c]) * inv;
+    for (int k = 0; k < 8; ++k) {
+      const int x = 2 * X + (k & 1), y = 2 * Y + ((k >> 1) & 1), z = 2 * Z + (k >> 2);
+      float d[3];
+      dphi(phi, x, y, z, N, inv_2s, d);
+      const int64_t j = ((int64_t)z * N + y) * N + x;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) h[c] += F[c * cs + j] + d[c];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) t[c * nvox + v] = h[c] * inv;
   }
 }
 
-// H0[c][box(v)] = rms * yhat[c][v]
+// H0[c][j] = rms * yhat[c][parent(j)] for every cell j of the N^3 box
 __global__ __launch_bounds__(NT) void k_start(const float* __restrict__ yhat, const double* __restrict__ rms, int n,
-                                              int N, float* __restrict__ H0) {
+                                              float* __restrict__ H0) {
+  const int N = 2 * n;
   const int64_t nvox = (int64_t)n * n * n, cs = (int64_t)N * N * N;
   const float r = (float)*rms;
-  for (int64_t v = blockIdx.x * (int64_t)NT + threadIdx.x; v < nvox; v += (int64_t)gridDim.x * NT) {
-    const int x = (int)(v % n), y = (int)((v / n) % n), z = (int)(v / ((int64_t)n * n));
-    const int64_t j = box_index(x, y, z, n, N);
+  for (int64_t j = blockIdx.x * (int64_t)NT + threadIdx.x; j < cs; j += (int64_t)gridDim.x * NT) {
+    const int x = (int)(j % N), y = (int)((j / N) % N), z = (int)(j / ((int64_t)N * N));
+    const int64_t v = ((int64_t)(z >> 1) * n + (y >> 1)) * n + (x >> 1);
 #pragma unroll
     for (int c = 0; c < 3; ++c) H0[c * cs + j] = r * yhat[c * nvox + v];
   }
@@ -847,32 +876,31 @@ hipError_t adam(const Buffers& b, float lr, float beta1, float beta2, float eps,
   return pack_weights(b, st);
 }
 
-hipError_t features(const Buffers& b, int slot, const float* phiN, int n_pad, double inv_2s, double a0,
-                    hipStream_t st) {
+hipError_t features(const Buffers& b, int slot, const float* phiN, double inv_2s, double a0, hipStream_t st) {
   const int n = b.n;
   const int64_t nvox = level_voxels(n, 0);
   const int nb = grid_for(nvox);
   if (nb > b.dpartial_count) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_feat_sumsq, dim3(nb), dim3(NT), 0, st, phiN, n, n_pad, (float)inv_2s, b.dpartial);
+  hipLaunchKernelGGL(k_feat_sumsq, dim3(nb), dim3(NT), 0, st, phiN, n, (float)inv_2s, b.dpartial);
   NETCHK(launched("k_feat_sumsq"));
   hipLaunchKernelGGL(k_reduce_d, dim3(1), dim3(NT), 0, st, b.dpartial, nb, 1, b.sums + slot);
   NETCHK(launched("k_reduce_d"));
-  hipLaunchKernelGGL(k_feat_write, dim3(nb), dim3(NT), 0, st, phiN, n, n_pad, (float)inv_2s, (float)(1.0 / a0),
+  hipLaunchKernelGGL(k_feat_write, dim3(nb), dim3(NT), 0, st, phiN, n, (float)inv_2s, (float)(1.0 / a0),
                      b.sums + slot, b.rms + slot, b.x + (int64_t)slot * nvox * 16);
   return launched("k_feat_write");
 }
 
-hipError_t target_from_field(const Buffers& b, int slot, const float* phiN, const float* F, int n_pad, double inv_2s,
+hipError_t target_from_field(const Buffers& b, int slot, const float* phiN, const float* F, double inv_2s,
                              hipStream_t st) {
   const int64_t nvox = level_voxels(b.n, 0);
-  hipLaunchKernelGGL(k_target, dim3(grid_for(nvox)), dim3(NT), 0, st, phiN, F, b.n, n_pad, (float)inv_2s,
-                     b.rms + slot, b.target + (int64_t)slot * 3 * nvox);
+  hipLaunchKernelGGL(k_target, dim3(grid_for(nvox)), dim3(NT), 0, st, phiN, F, b.n, (float)inv_2s, b.rms + slot,
+                     b.target + (int64_t)slot * 3 * nvox);
   return launched("k_target");
 }
 
-hipError_t start_field(const Buffers& b, float* H0, int n_pad, hipStream_t st) {
-  const int64_t nvox = level_voxels(b.n, 0);
-  hipLaunchKernelGGL(k_start, dim3(grid_for(nvox)), dim3(NT), 0, st, b.yhat, b.rms, b.n, n_pad, H0);
+hipError_t start_field(const Buffers& b, float* H0, hipStream_t st) {
+  const int64_t cells = level_voxels(b.n, 0) * 8;
+  hipLaunchKernelGGL(k_start, dim3(grid_for(cells)), dim3(NT), 0, st, b.yhat, b.rms, b.n, H0);
   return launched("k_start");
 }
 

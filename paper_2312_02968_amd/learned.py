@@ -1,0 +1,301 @@
+"""Training and evaluation of the learned starting guess, through the C ABI.
+
+    python -m paper_2312_02968_amd.learned train [--pairs 256] [--epochs 40]
+    python -m paper_2312_02968_amd.learned eval  [--weights PATH]
+
+Training pairs come from the solver itself: random Plummer mixtures on a
+128^3 region (256^3 FFT box) are deposited, the Newton potential gives the
+network input, and a long solve (K iterations with its last F returned) gives
+the target H = F - g_N.  Every step runs in the HIP library; this module only
+draws the seeded particle sets, keeps the pairs in device tensors and orders
+the calls.  The evaluation compares the learned start with the zero start on
+held-out inputs: iterations and wall time to the accuracy of the plain K = 4
+solve, and iterations in tolerance mode.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+from paper_2312_02968_amd import mondpm as M  # noqa: E402
+import workloads as W  # noqa: E402
+
+WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "learned_start.npy")
+TRAIN_N = 128
+TARGET_ITERS = 12          # the long solve that defines the training target
+
+
+def init_params(seed=0):
+    """He-normal weights, zero biases, in the C ABI's parameter layout."""
+    rng = np.random.default_rng(seed)
+    shapes = [(4, 16, 3), (16, 16, 3), (16, 32, 3), (32, 32, 3), (32, 64, 3), (64, 64, 3),
+              (96, 32, 3), (32, 32, 3), (48, 16, 3), (16, 16, 3), (16, 3, 1)]
+    out = []
+    for ci, co, k in shapes:
+        taps = k ** 3
+        std = np.sqrt(2.0 / (taps * ci)) * (0.1 if k == 1 else 1.0)
+        out.append(rng.standard_normal(taps * ci * co) * std)
+        out.append(np.zeros(co))
+    v = np.concatenate(out).astype(np.float32)
+    assert v.size == M.pm_net_param_count()
+    return v
+
+
+class PairMaker:
+    """Builds (input, target) pairs for one region size on the GPU."""
+
+    def __init__(self, n, max_particles, a0_ref=None):
+        self.n = n
+        self.N = 2 * n
+        base = W.params(n, mu=W.MU_STANDARD, iters=TARGET_ITERS, flags=M.PM_F_RESIDUAL)
+        self.base = base
+        self.max_particles = max_particles
+        self.ctx = None
+        self.key = None
+
+    def _ctx(self, p):
+        key = (p["a0"], p["G"])
+        if self.ctx is None or self.key != key:
+            if self.ctx is not None:
+                self.ctx.close()
+            self.ctx = M.pm_create(p, self.max_particles)
+            self.key = key
+        return self.ctx
+
+    def rho_of(self, ctx, w):
+        rho = torch.empty(self.N ** 3, device="cuda")
+        pos = torch.from_numpy(np.ascontiguousarray(w["pos"])).cuda()
+        mass = torch.from_numpy(np.ascontiguousarray(w["mass"])).cuda()
+        M.pm_deposit(ctx, pos, mass, rho)
+        return rho
+
+    def pair(self, net, slot, w):
+        p = dict(self.base, a0=w["params"]["a0"], G=w["params"]["G"])
+        ctx = self._ctx(p)
+        rho = self.rho_of(ctx, w)
+        phiN = torch.empty(self.N ** 3, device="cuda")
+        M.pm_newton_potential(ctx, rho, phiN)
+        M.pm_net_input(ctx, net, phiN, slot)
+        phi = torch.empty(self.N ** 3, device="cuda")
+        F = torch.empty(3 * self.N ** 3, device="cuda")
+        info = M.aqual_solve_field(ctx, rho, phi, F)
+        M.pm_net_target(ctx, net, phiN, F, slot)
+        return info
+
+    def close(self):
+        if self.ctx is not None:
+            self.ctx.close()
+            self.ctx = None
+
+
+def training_sample(seed, n=TRAIN_N):
+    return W.mixture_training_sample(seed, n=n)
+
+
+def make_dataset(net, count, seed0=0, log=print):
+    """count pairs as device tensors X [count, 4 n^3], Y [count, 3 n^3]."""
+    n = net.n
+    X = torch.empty(count, 4 * n ** 3, device="cuda")
+    Y = torch.empty(count, 3 * n ** 3, device="cuda")
+    maker = PairMaker(n, 1 << 18)
+    t0 = time.time()
+    for i in range(count):
+        w = training_sample(seed0 + i, n)
+        maker.pair(net, 0, w)
+        M.pm_net_get_input(net, 0, X[i])
+        M.pm_net_get_target(net, 0, Y[i])
+        if (i + 1) % 32 == 0 or i + 1 == count:
+            torch.cuda.synchronize()
+            log(f"pairs {i + 1}/{count}  {time.time() - t0:.1f} s")
+    maker.close()
+    return X, Y
+
+
+def train(net, X, Y, epochs, batch=4, lr=3e-4, lr_final=None, seed=0, log=print):
+    """Adam over shuffled mini-batches with a cosine learning-rate decay to
+    lr_final (default lr / 10)."""
+    if lr_final is None:
+        lr_final = lr / 10.0
+    rng = np.random.default_rng(seed)
+    count = X.shape[0]
+    steps_per_epoch = count // batch
+    total = epochs * steps_per_epoch
+    hist = []
+    step = 0
+    t0 = time.time()
+    for ep in range(epochs):
+        order = rng.permutation(count)
+        acc = 0.0
+        for s in range(steps_per_epoch):
+            for b in range(batch):
+                k = int(order[s * batch + b])
+                M.pm_net_set_input(net, b, X[k])
+                M.pm_net_set_target(net, b, Y[k])
+            frac = step / max(total - 1, 1)
+            cur = lr_final + 0.5 * (lr - lr_final) * (1.0 + np.cos(np.pi * frac))
+            acc += M.pm_net_train_step(net, batch, float(cur))
+            step += 1
+        hist.append(acc / steps_per_epoch)
+        log(f"epoch {ep + 1}/{epochs}  loss {hist[-1]:.4e}  {time.time() - t0:.1f} s")
+    return hist
+
+
+def save_params(path, v):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    np.save(path, np.asarray(v, dtype=np.float32), allow_pickle=False)
+
+
+def load_params(path=WEIGHTS):
+    v = np.load(path, allow_pickle=False)
+    if v.dtype != np.float32 or v.size != M.pm_net_param_count():
+        raise ValueError(f"{path}: expected {M.pm_net_param_count()} float32 parameters")
+    return v
+
+
+# ---------------------------------------------------------------------------
+# learned vs plain
+# ---------------------------------------------------------------------------
+
+def _timed(fn):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3, r
+
+
+def compare_starts(w, net, K_plain=4, K_ref=30, tol=1e-4, max_iters=30, reps=3):
+    """Learned vs zero start on one input (dict with params, pos, mass).
+
+    Returns the potential error of the plain K_plain solve against a K_ref
+    reference, the error of the learned start after K = 1..K_plain, the
+    smallest K reaching the plain error, wall times (ms, best of reps) of the
+    plain solve and of the learned path (Newton potential + network + solve
+    with K iterations), and the iterations of both in tolerance mode."""
+    p0 = dict(w["params"])
+    n, N = p0["n"], p0["n_pad"]
+    pos = torch.from_numpy(np.ascontiguousarray(w["pos"])).cuda()
+    mass = torch.from_numpy(np.ascontiguousarray(w["mass"])).cuda()
+    out = {"workload": w.get("workload", ""), "n": n, "particles": int(pos.shape[0])}
+
+    def ctx_for(**kw):
+        return M.pm_create(dict(p0, **kw), pos.shape[0])
+
+    c_ref = ctx_for(iters=K_ref)
+    rho = torch.empty(N ** 3, device="cuda")
+    M.pm_deposit(c_ref, pos, mass, rho)
+    phi_ref = torch.empty_like(rho)
+    M.aqual_solve(c_ref, rho, phi_ref)
+    nref = float(torch.linalg.vector_norm(phi_ref))
+    c_ref.close()
+
+    phiN = torch.empty_like(rho)
+    H0 = torch.empty(3 * N ** 3, device="cuda")
+    phi = torch.empty_like(rho)
+    c1 = ctx_for(iters=1)
+    M.pm_newton_potential(c1, rho, phiN)
+    M.pm_net_forward(c1, net, phiN, H0)
+
+    def err(ph):
+        return float(torch.linalg.vector_norm(ph - phi_ref)) / nref
+
+    plain_err, learned_err = {}, {}
+    for K in range(1, K_plain + 1):
+        c = ctx_for(iters=K)
+        M.aqual_solve(c, rho, phi)
+        plain_err[K] = err(phi)
+        M.aqual_solve(c, rho, phi, H0=H0)
+        learned_err[K] = err(phi)
+        c.close()
+    target = plain_err[K_plain]
+    K_star = next((K for K in range(1, K_plain + 1) if learned_err[K] <= target), None)
+    out.update(plain_err=plain_err, learned_err=learned_err, K_plain=K_plain, K_learned=K_star)
+
+    cp = ctx_for(iters=K_plain)
+    t_plain = min(_timed(lambda: M.aqual_solve(cp, rho, phi, want_info=False))[0] for _ in range(reps))
+    cp.close()
+    if K_star is not None:
+        cl = ctx_for(iters=K_star)
+
+        def learned_path():
+            M.pm_newton_potential(cl, rho, phiN)
+            M.pm_net_forward(cl, net, phiN, H0)
+            M.aqual_solve(cl, rho, phi, H0=H0, want_info=False)
+        t_learned = min(_timed(learned_path)[0] for _ in range(reps))
+        t_net = min(_timed(lambda: (M.pm_newton_potential(cl, rho, phiN),
+                                    M.pm_net_forward(cl, net, phiN, H0)))[0] for _ in range(reps))
+        cl.close()
+    else:
+        t_learned = t_net = None
+    out.update(t_plain_ms=t_plain, t_learned_ms=t_learned, t_start_ms=t_net)
+
+    ct = ctx_for(iters=max_iters, tol=tol)
+    ip = M.aqual_solve(ct, rho, phi)
+    il = M.aqual_solve(ct, rho, phi, H0=H0)
+    ct.close()
+    c1.close()
+    out.update(tol=tol, tol_iters_plain=ip["iterations"], tol_iters_learned=il["iterations"],
+               tol_status_plain=ip["status"], tol_status_learned=il["status"],
+               resid_plain=ip["residuals"], resid_learned=il["residuals"])
+    return out
+
+
+def held_out_inputs(n=256, count=4):
+    """Held-out Plummer mixtures at n (radii twice the training range) and the
+    isothermal sphere of the throughput workload."""
+    f = n / TRAIN_N
+    ws = [W.mixture_training_sample(100000 + i, n=n, a_range=(2.0 * f, 8.0 * f)) for i in range(count)]
+    if n == 256:
+        s = W.isothermal_sphere(seed=0)
+        ws.append(dict(params=s["params"], pos=s["pos"], mass=s["mass"], workload=s.get("workload", "isothermal")))
+    return ws
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("cmd", choices=["train", "eval"])
+    ap.add_argument("--pairs", type=int, default=256)
+    ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--batch", type=int, default=4)
+    ap.add_argument("--lr", type=float, default=3e-4)
+    ap.add_argument("--weights", default=WEIGHTS)
+    ap.add_argument("--eval-n", type=int, default=256)
+    ap.add_argument("--eval-count", type=int, default=4)
+    ap.add_argument("--out", default=None, help="JSON file for the results")
+    a = ap.parse_args(argv)
+    log = lambda s: print(s, flush=True)  # noqa: E731
+    torch.cuda.init()
+    if a.cmd == "train":
+        net = M.Net(TRAIN_N, a.batch)
+        M.pm_net_set_params(net, init_params(0))
+        X, Y = make_dataset(net, a.pairs, log=log)
+        hist = train(net, X, Y, a.epochs, batch=a.batch, lr=a.lr, log=log)
+        save_params(a.weights, M.pm_net_get_params(net))
+        res = {"pairs": a.pairs, "epochs": a.epochs, "loss": hist}
+    else:
+        v = load_params(a.weights)
+        net = M.Net(a.eval_n, 1)
+        M.pm_net_set_params(net, v)
+        res = {"results": []}
+        for w in held_out_inputs(a.eval_n, a.eval_count):
+            r = compare_starts(w, net)
+            log(json.dumps(r))
+            res["results"].append(r)
+    if a.out:
+        with open(a.out, "w") as f:
+            json.dump(res, f)
+    return res
+
+
+if __name__ == "__main__":
+    main()

@@ -38,6 +38,28 @@ def test_conv3d_brute_force():
                     assert abs(got[o, z, y, xx] - s) < 1e-12
 
 
+def test_periodic_conv3d_brute_force():
+    rng = np.random.default_rng(10)
+    x = rng.standard_normal((2, 4, 3, 5))
+    w = rng.standard_normal((27, 2, 3))
+    b = rng.standard_normal(3)
+    got = cn.conv3d(x, w, b, periodic=True)
+    C, D, H, W = x.shape
+    for o in range(3):
+        for z in range(D):
+            for y in range(H):
+                for xx in range(W):
+                    s = b[o]
+                    t = 0
+                    for dz in (-1, 0, 1):
+                        for dy in (-1, 0, 1):
+                            for dx in (-1, 0, 1):
+                                for c in range(C):
+                                    s += x[c, (z + dz) % D, (y + dy) % H, (xx + dx) % W] * w[t, c, o]
+                                t += 1
+                    assert abs(got[o, z, y, xx] - s) < 1e-12
+
+
 def test_conv3d_delta_response_fixes_tap_orientation():
     # a unit impulse at v0 in channel c gives out[o, v0 - tap_t] = w[t, c, o]
     rng = np.random.default_rng(1)
@@ -53,14 +75,14 @@ def test_conv3d_delta_response_fixes_tap_orientation():
                 t += 1
 
 
-@pytest.mark.parametrize("taps", [27, 1])
-def test_conv_backward_is_the_adjoint(taps):
+@pytest.mark.parametrize("taps,periodic", [(27, False), (1, False), (27, True)])
+def test_conv_backward_is_the_adjoint(taps, periodic):
     rng = np.random.default_rng(2)
     x = rng.standard_normal((3, 4, 4, 6))
     w = rng.standard_normal((taps, 3, 5))
     g = rng.standard_normal((5, 4, 4, 6))
-    y = cn.conv3d(x, w, np.zeros(5))
-    gx, gw, gb = cn.conv3d_backward(x, w, g)
+    y = cn.conv3d(x, w, np.zeros(5), periodic)
+    gx, gw, gb = cn.conv3d_backward(x, w, g, periodic)
     ip = float((y * g).sum())
     assert abs(ip - float((gx * x).sum())) < 1e-10 * abs(ip)
     assert abs(ip - float((gw * w).sum())) < 1e-10 * abs(ip)
@@ -84,12 +106,13 @@ def test_parameter_count():
     assert 3.0e5 < n < 4.0e5
 
 
-def _loss(p, x, t):
-    y, _ = cn.forward(p, x)
+def _loss(p, x, t, periodic=False):
+    y, _ = cn.forward(p, x, periodic=periodic)
     return cn.mse(y, t)[0]
 
 
-def test_network_gradient_matches_finite_differences():
+@pytest.mark.parametrize("periodic", [False, True])
+def test_network_gradient_matches_finite_differences(periodic):
     rng = np.random.default_rng(4)
     p = cn.init_params(1)
     for k in p:
@@ -97,7 +120,7 @@ def test_network_gradient_matches_finite_differences():
             p[k] = 0.1 * rng.standard_normal(p[k].shape)
     x = rng.standard_normal((4, 8, 8, 8))
     t = rng.standard_normal((3, 8, 8, 8))
-    y, cache = cn.forward(p, x)
+    y, cache = cn.forward(p, x, periodic=periodic)
     _, gy = cn.mse(y, t)
     g = cn.backward(p, cache, gy)
     eps = 1e-6
@@ -106,9 +129,9 @@ def test_network_gradient_matches_finite_differences():
         for i in rng.choice(flat.size, size=min(3, flat.size), replace=False):
             old = flat[i]
             flat[i] = old + eps
-            lp = _loss(p, x, t)
+            lp = _loss(p, x, t, periodic)
             flat[i] = old - eps
-            lm = _loss(p, x, t)
+            lm = _loss(p, x, t, periodic)
             flat[i] = old
             fd = (lp - lm) / (2 * eps)
             an = g[k].reshape(-1)[i]
@@ -161,19 +184,22 @@ def test_training_reduces_loss_on_a_fixed_pair():
 
 
 def test_net_input_and_start_field():
+    # the network sees the whole box averaged over 2 x 2 x 2 blocks
     p = pm.Params(n=8, n_pad=16, box=8.0, a0=2.0)
     rng = np.random.default_rng(8)
     gN = rng.standard_normal((3, 16, 16, 16))
     x, rms = ol.net_input(p, gN)
-    r = slice(4, 12)
-    g = gN[:, r, r, r]
     assert x.shape == (4, 8, 8, 8)
-    assert rms == pytest.approx(math.sqrt((g ** 2).sum() / 8 ** 3))
-    assert ((x[:3] ** 2).sum(axis=0).mean()) == pytest.approx(1.0)
-    assert np.allclose(10.0 ** x[3], np.sqrt((g ** 2).sum(axis=0)) / 2.0 + 1e-30)
+    gc = np.zeros((3, 8, 8, 8))
+    for dz in (0, 1):
+        for dy in (0, 1):
+            for dx in (0, 1):
+                gc += gN[:, dz::2, dy::2, dx::2] / 8.0
+    assert rms == pytest.approx(math.sqrt((gc ** 2).sum() / 8 ** 3))
+    assert np.allclose(x[:3], gc / rms)
+    assert np.allclose(10.0 ** x[3], np.sqrt((gc ** 2).sum(axis=0)) / 2.0 + 1e-30)
     y = rng.standard_normal((3, 8, 8, 8))
     H0 = ol.start_field(p, y, rms)
-    assert np.allclose(H0[:, r, r, r], rms * y)
-    H0[:, r, r, r] = 0.0
-    assert not H0.any()
-    assert np.allclose(ol.target(p, ol.start_field(p, y, rms), rms), y)
+    assert H0.shape == (3, 16, 16, 16)
+    assert np.allclose(H0[:, 5, 9, 14], rms * y[:, 2, 4, 7])
+    assert np.allclose(ol.target(p, H0, rms), y)
