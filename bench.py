@@ -108,6 +108,29 @@ def fft_compare(n_pad=512, reps=20):
     print(json.dumps({k: (round(v, 4) if isinstance(v, float) else v) for k, v in res.items()}), flush=True)
 
 
+def start_comparison(w):
+    """Learned start (committed weights) and warm start against the zero start
+    on the same workload, outside the timed region: potential error against a
+    30-iteration reference, iterations to the accuracy of the plain 4-iteration
+    solve, wall times, and the warm start's error and step time along a
+    10-step trajectory."""
+    from paper_2312_02968_amd import learned as L
+    from paper_2312_02968_amd import mondpm as M
+    res = {}
+    if os.path.exists(L.WEIGHTS):
+        net = M.Net(w["params"]["n_pad"] // 2, 1)
+        M.pm_net_set_params(net, L.load_params(L.WEIGHTS))
+        r = L.compare_starts(w, net)
+        net.close()
+        keep = ("K_plain", "K_learned", "plain_err", "learned_err", "t_plain_ms", "t_learned_ms", "t_start_ms",
+                "tol", "tol_iters_plain", "tol_iters_learned")
+        res["learned_start"] = {k: r[k] for k in keep}
+    t = L.warm_start_trajectory(w, steps=10, Ks=(2,))
+    last = {k: v[-1] for k, v in t["err_box_region"].items()}
+    res["warm_start"] = {"steps": t["steps"], "err_box_region_last_step": last, "step_ms": t["step_ms"]}
+    return res
+
+
 def make_workload(name):
     import workloads as W
     if name == "isothermal":
@@ -226,6 +249,10 @@ def main():
     ap.add_argument("--copy-probe", action="store_true", help="only run the counter-calibration copy")
     ap.add_argument("--fft-compare", action="store_true",
                     help="only time this library's 512^3 real transforms beside rocFFT's")
+    ap.add_argument("--warm", type=int, default=0, metavar="K",
+                    help="time pm_step with the warm start (previous step's F) and K iterations")
+    ap.add_argument("--no-starts", action="store_true",
+                    help="skip the learned-start and warm-start comparisons")
     a = ap.parse_args()
     if a.copy_probe:
         copy_probe()
@@ -243,6 +270,8 @@ def main():
     from paper_2312_02968_amd import mondpm as M
 
     w = make_workload(a.workload)
+    if a.warm:
+        w["params"] = dict(w["params"], iters=a.warm, flags=w["params"].get("flags", 0) | M.PM_F_WARM_START)
     p = w["params"]
     N_part = len(w["mass"])
     dt = float(w["dt"])
@@ -300,14 +329,16 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": w["workload"], "grid": p["n"], "fft_box": Npad, "particles": N_part,
-                   "iterations": K, "sigma_cells": p["sigma"], "mu": "standard" if p["mu"] == 0 else
-                   ("deep" if p["mu"] == 1 else "newton"), "dt": dt},
+                   "iterations": K, "start": "warm" if a.warm else "zero", "sigma_cells": p["sigma"],
+                   "mu": "standard" if p["mu"] == 0 else ("deep" if p["mu"] == 1 else "newton"), "dt": dt},
         "particle_updates_per_s": round(N_part * 1e3 / ms_step, 1),
         "roofline": roof,
     }
+    ctx.close()
+    if not a.no_starts and not a.warm:
+        out.update(start_comparison(w))
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
-    ctx.close()
     print(json.dumps(out), flush=True)
 
 

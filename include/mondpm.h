@@ -62,6 +62,15 @@ typedef enum {
                                    FP64 sum of the weights over the ball      */
 #define PM_F_RESIDUAL      0x2u /* compute r_k every iteration in fixed-K mode
                                    (always on when tol > 0)                   */
+#define PM_F_WARM_START    0x4u /* start each solve on the context from the last
+                                   F of the previous one (the paper's remark
+                                   that the previous step's H is a good start,
+                                   Sect. 2.1): F0 = P_L g_N + P_T F_prev, i.e.
+                                   H0 = divergence-free part of F_prev - g_N.
+                                   The first solve starts from zero; keeps one
+                                   more 3-component real field.  Needs
+                                   iters >= 2: F is updated only between two
+                                   evaluations of nu.                         */
 
 /* Statement of the problem (Sect. 2, Sect. 3 and the table of symbols). */
 typedef struct {

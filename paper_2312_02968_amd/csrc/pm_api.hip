@@ -39,7 +39,8 @@ struct pm_ctx {
   float2* phiN = nullptr;     // Newton potential spectrum
   float* rho = nullptr;       // internal real grids of pm_step
   float* phi = nullptr;
-  float* fprev = nullptr;     // previous F for the residual (optional)
+  float* fprev = nullptr;     // previous F for the residual and the warm start (optional)
+  bool have_F = false;        // fprev holds the last F of a solve
   double* partials = nullptr;
   double* dacc = nullptr;     // [0] |g_N|^2 sum, [1..64] residual sums, [80..89] diagnostics
   double* hacc = nullptr;     // pinned host copy of dacc
@@ -127,6 +128,8 @@ static pm_status check_params(const pm_params* p) {
   const double R = p->cutoff * p->sigma;
   if (R > 10.0) return inval("cutoff * sigma must be <= 10 cells");
   if (p->iters < 1 || p->iters > 64) return inval("iters must be in [1, 64]");
+  if ((p->flags & PM_F_WARM_START) && p->iters < 2)
+    return inval("PM_F_WARM_START needs iters >= 2 (with one iteration F is never updated)");
   if (!(p->tol >= 0.0)) return inval("tol must be >= 0");
   return PM_OK;
 }
@@ -151,7 +154,7 @@ size_t pm_workspace_bytes(const pm_params* p, int64_t max_particles) {
   const size_t N = p->n_pad, P = pm_spectrum_pitch(p->n_pad);
   const size_t C = N * N * P * sizeof(float2), R = N * N * N * sizeof(float);
   size_t b = 4 * C + 2 * R;
-  if (need_residual(*p)) b += 3 * R;
+  if (need_residual(*p) || (p->flags & PM_F_WARM_START)) b += 3 * R;
   const size_t ntiles = (N / 8) * (N / 8) * (N / 8);
   b += (size_t)max_particles * 4 * sizeof(int) + (2 * (ntiles + 1) + 4096 + 16) * sizeof(int);
   return b;
@@ -224,7 +227,7 @@ pm_status pm_create(const pm_params* p, int64_t max_particles, void* stream, pm_
   ALLOC(c->phiN, C);
   ALLOC(c->rho, R);
   ALLOC(c->phi, R);
-  if (need_residual(*p)) ALLOC(c->fprev, 3 * R);
+  if (need_residual(*p) || (p->flags & PM_F_WARM_START)) ALLOC(c->fprev, 3 * R);
   ALLOC(c->partials, (size_t)c->npartials);
   ALLOC(c->dacc, 128);
   ALLOC(c->tw, (size_t)N);
@@ -348,9 +351,13 @@ static pm_status run_solve(pm_ctx* c, const float* rho, const float* H0, float* 
     HIPCHK(pass(c, d));
     HIPCHK(pass(c, pdesc(PASS_Y_FWD, c->phiN, 1)));
   }
-  if (H0) {
+  // warm start: F0 = P_L g_N + P_T F_prev from the last F of the previous solve
+  const bool keep_F = (p.flags & PM_F_WARM_START) != 0;
+  const bool warm = keep_F && c->have_F && !H0;
+  const float* start = H0 ? H0 : (warm ? c->fprev : nullptr);
+  if (start) {
     PassDesc d = pdesc(PASS_X_FWD_REAL3, c->spec);
-    d.real = const_cast<float*>(H0);
+    d.real = const_cast<float*>(start);
     d.real_cs = R;
     HIPCHK(pass(c, d));
     HIPCHK(pass(c, pdesc(PASS_Y_FWD, c->spec, 3)));
@@ -358,7 +365,7 @@ static pm_status run_solve(pm_ctx* c, const float* rho, const float* H0, float* 
   {
     PassDesc d = pdesc(PASS_Z_NEWTON, c->spec);
     d.z = zargs(c);
-    d.z.with_h0 = H0 ? 1 : 0;
+    d.z.with_h0 = warm ? 2 : (H0 ? 1 : 0);
     HIPCHK(pass(c, d));
     HIPCHK(reduce_partials(c->partials, z_blocks(N), c->dacc, c->st));
     HIPCHK(pass(c, pdesc(PASS_Y_INV, c->spec, 3)));
@@ -369,7 +376,8 @@ static pm_status run_solve(pm_ctx* c, const float* rho, const float* H0, float* 
       PassDesc d = pdesc(PASS_X_NU, c->spec, 3);
       d.mu_mode = p.mu;
       d.inv_a0 = inv_a0;
-      d.fprev = resid ? c->fprev : nullptr;
+      // F is kept every iteration for the residual; for the warm start only the last one
+      d.fprev = (resid || (keep_F && k == K)) ? c->fprev : nullptr;
       d.partials = c->partials;
       HIPCHK(pass(c, d));
     }
@@ -417,6 +425,7 @@ static pm_status run_solve(pm_ctx* c, const float* rho, const float* H0, float* 
     }
     HIPCHK(pass(c, pdesc(PASS_Y_INV, c->spec, 3)));
   }
+  if (resid || keep_F) c->have_F = true;
   HIPCHK(pass(c, pdesc(PASS_Y_INV, c->spec, 1)));
   {
     PassDesc d = pdesc(PASS_X_INV_REAL, c->spec);

@@ -440,13 +440,15 @@ __global__ __launch_bounds__(NT) void k_ypass(float2* spec, long long comp_strid
   store_cols<L, T, NT, Last::R, 2>(v, E, ptr, nv, P);
 }
 
-enum { Z_FWD = 0, Z_INV = 1, Z_NEWTON = 2, Z_CURL = 3, Z_CURL_FINAL = 4, Z_DIV = 5, Z_NEWTON_H0 = 6, Z_POISSON = 7 };
+enum { Z_FWD = 0, Z_INV = 1, Z_NEWTON = 2, Z_CURL = 3, Z_CURL_FINAL = 4, Z_DIV = 5, Z_NEWTON_H0 = 6, Z_POISSON = 7,
+       Z_NEWTON_WARM = 8 };
 
 template <int ZOP> struct ZComp;
 template <> struct ZComp<Z_FWD>        { static constexpr int IN = 1, OUT = 1; };
 template <> struct ZComp<Z_INV>        { static constexpr int IN = 1, OUT = 1; };
 template <> struct ZComp<Z_NEWTON>     { static constexpr int IN = 1, OUT = 3; };
 template <> struct ZComp<Z_NEWTON_H0>  { static constexpr int IN = 4, OUT = 3; };
+template <> struct ZComp<Z_NEWTON_WARM> { static constexpr int IN = 4, OUT = 3; };
 template <> struct ZComp<Z_CURL>       { static constexpr int IN = 3, OUT = 3; };
 template <> struct ZComp<Z_CURL_FINAL> { static constexpr int IN = 3, OUT = 1; };
 template <> struct ZComp<Z_DIV>        { static constexpr int IN = 3, OUT = 3; };
@@ -467,6 +469,9 @@ template <> struct ZComp<Z_POISSON>    { static constexpr int IN = 1, OUT = 1; }
 //   Z_CURL_FINAL: phi_hat = i At (kt . g) / N^3 (one output component)
 //   Z_DIV       : F = F' + kt At kt . (g_N - F'), g_N = -i kappa phi_N (/N^3)
 //   Z_POISSON   : phi_N_hat = -4 pi G A rho_hat / N^3 (one component, in place)
+//   Z_NEWTON_WARM: as Z_NEWTON_H0 with the previous F in place of H0, whose
+//                 divergence-free part minus that of g_N starts H:
+//                 F = P_L g_N + P_T F_prev
 template <int L, int T, int NT, int HZ, int ZOP>
 __global__ __launch_bounds__(NT) void k_zpass(ZArgs a, const float2* __restrict__ tw) {
   constexpr int E = ColCfg<L, T, NT>::E;
@@ -495,7 +500,7 @@ __global__ __launch_bounds__(NT) void k_zpass(ZArgs a, const float2* __restrict_
     for (int h = 0; h < HZ; ++h) nvs[HZ * c + h] = nvh[h];
 #pragma unroll
   for (int c = 0; c < NIN; ++c) {
-    const float2* p = (ZOP == Z_NEWTON || ZOP == Z_NEWTON_H0)
+    const float2* p = (ZOP == Z_NEWTON || ZOP == Z_NEWTON_H0 || ZOP == Z_NEWTON_WARM)
                           ? (c == 0 ? a.phiN + off : a.spec + (c - 1) * a.comp_stride + off)
                           : a.spec + c * a.comp_stride + off;
 #pragma unroll
@@ -550,7 +555,7 @@ __global__ __launch_bounds__(NT) void k_zpass(ZArgs a, const float2* __restrict_
         float2* v0 = v + (0 * HZ + h) * E + e;
         float2* v1 = v + (1 * HZ + h) * E + e;
         float2* v2 = v + (2 * HZ + h) * E + e;
-        if (ZOP == Z_NEWTON || ZOP == Z_NEWTON_H0) {
+        if (ZOP == Z_NEWTON || ZOP == Z_NEWTON_H0 || ZOP == Z_NEWTON_WARM) {
           const float kzz = a.kv[kz];
           const float k2 = kx * kx + ky * ky + kzz * kzz;
           const float A = (k2 > 0.0f) ? 1.0f / k2 : 0.0f;
@@ -559,13 +564,21 @@ __global__ __launch_bounds__(NT) void k_zpass(ZArgs a, const float2* __restrict_
           const float kpz = a.kap[kz];
           const float2 g = cscale(mul_mi<false>(ph), a.scale);
           float2 o0 = cscale(g, kpx), o1 = cscale(g, kapy), o2 = cscale(g, kpz);
-          if (ZOP == Z_NEWTON_H0) {
-            // H0 components arrived in input slots 1..3 (component c at slot HZ c + h);
-            // H starts at their divergence-free part h - kt At (kt . h)
+          if (ZOP == Z_NEWTON_H0 || ZOP == Z_NEWTON_WARM) {
+            // H0 (or F_prev) components arrived in input slots 1..3 (component c
+            // at slot HZ c + h); H starts at the divergence-free part of H0, or
+            // of F_prev - g_N: h - kt At (kt . h)
             const float tz = a.kt[kz];
             const float t2 = tx * tx + ty * ty + tz * tz;
             const float At = (t2 > 0.0f) ? 1.0f / t2 : 0.0f;
-            const float2 h0 = v[(1 * HZ + h) * E + e], h1 = v[(2 * HZ + h) * E + e], h2 = v[(3 * HZ + h) * E + e];
+            float2 h0 = v[(1 * HZ + h) * E + e], h1 = v[(2 * HZ + h) * E + e], h2 = v[(3 * HZ + h) * E + e];
+            if (ZOP == Z_NEWTON_WARM) {
+              // o_c = g_N hat (already divided by N^3); bring F_prev to the same units
+              const float rs = 1.0f / a.scale;
+              h0 = csub(h0, cscale(o0, rs));
+              h1 = csub(h1, cscale(o1, rs));
+              h2 = csub(h2, cscale(o2, rs));
+            }
             const float2 dd = cscale(cadd(cadd(cscale(h0, tx), cscale(h1, ty)), cscale(h2, tz)), At);
             o0 = cadd(o0, cscale(csub(h0, cscale(dd, tx)), a.scale));
             o1 = cadd(o1, cscale(csub(h1, cscale(dd, ty)), a.scale));
@@ -609,7 +622,7 @@ __global__ __launch_bounds__(NT) void k_zpass(ZArgs a, const float2* __restrict_
       }
     }
   }
-  if (ZOP == Z_NEWTON || ZOP == Z_NEWTON_H0) {
+  if (ZOP == Z_NEWTON || ZOP == Z_NEWTON_H0 || ZOP == Z_NEWTON_WARM) {
     __shared__ double red[NT / 64];
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
@@ -719,6 +732,7 @@ hipError_t run_pass(const FftGeom& g, const PassDesc& d, hipStream_t st) {
     case PASS_Z_FWD: return launch_z<N, Z_FWD>(g, d.z, st);
     case PASS_Z_INV: return launch_z<N, Z_INV>(g, d.z, st);
     case PASS_Z_NEWTON:
+      if (d.z.with_h0 == 2) return launch_z<N, Z_NEWTON_WARM>(g, d.z, st);
       return d.z.with_h0 ? launch_z<N, Z_NEWTON_H0>(g, d.z, st) : launch_z<N, Z_NEWTON>(g, d.z, st);
     case PASS_Z_CURL: return launch_z<N, Z_CURL>(g, d.z, st);
     case PASS_Z_CURL_FINAL: return launch_z<N, Z_CURL_FINAL>(g, d.z, st);

@@ -24,7 +24,7 @@ struct ZArgs {
   const float* kap;
   float newton_coef;
   float scale;
-  int with_h0;
+  int with_h0;     // 0: H = 0; 1: H0 given; 2: warm start from the previous F
   double* partials;
   int nc;
 };

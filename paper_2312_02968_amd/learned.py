@@ -99,7 +99,9 @@ class PairMaker:
 
 
 def training_sample(seed, n=TRAIN_N):
-    return W.mixture_training_sample(seed, n=n)
+    """Training mixture for an n^3 region; clump radii scale with n."""
+    f = n / TRAIN_N
+    return W.mixture_training_sample(seed, n=n, a_range=(2.0 * f, 8.0 * f))
 
 
 def make_dataset(net, count, seed0=0, log=print):
@@ -250,6 +252,61 @@ def compare_starts(w, net, K_plain=4, K_ref=30, tol=1e-4, max_iters=30, reps=3):
     return out
 
 
+def warm_start_trajectory(w, steps=10, Ks=(2, 3), K_cold=4, K_ref=30, reps=5):
+    """The paper's own start (Sect. 2.1): each solve begins from the previous
+    step's field (PM_F_WARM_START).  A cold K_cold trajectory of pm_step moves
+    the particles; along it, solves with the warm start and K iterations are
+    compared with a cold K_ref reference at every step (potential error over
+    the box and over the physical region), and pm_step is timed with each
+    setting."""
+    p0 = dict(w["params"])
+    N, n = p0["n_pad"], p0["n"]
+    lo = N // 2 - n // 2
+    pos = torch.from_numpy(np.ascontiguousarray(w["pos"])).cuda()
+    vel = torch.from_numpy(np.ascontiguousarray(w["vel"])).cuda()
+    mass = torch.from_numpy(np.ascontiguousarray(w["mass"])).cuda()
+    dt = float(w["dt"])
+    Np = int(pos.shape[0])
+    step_ctx = M.pm_create(dict(p0, iters=K_cold), Np)
+    ref_ctx = M.pm_create(dict(p0, iters=K_ref), Np)
+    cold_ctx = M.pm_create(dict(p0, iters=K_cold), Np)
+    warm_ctx = {K: M.pm_create(dict(p0, iters=K, flags=M.PM_F_WARM_START), Np) for K in Ks}
+    rho = torch.empty(N ** 3, device="cuda")
+    phi_ref, phi = torch.empty_like(rho), torch.empty_like(rho)
+
+    def errs(a, b):
+        box = float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+        a3, b3 = a.view(N, N, N)[lo:lo + n, lo:lo + n, lo:lo + n], b.view(N, N, N)[lo:lo + n, lo:lo + n, lo:lo + n]
+        reg = float(torch.linalg.vector_norm(a3 - b3) / torch.linalg.vector_norm(b3))
+        return box, reg
+
+    hist = {"cold": [], **{f"warm{K}": [] for K in Ks}}
+    for s in range(steps):
+        M.pm_deposit(ref_ctx, pos, mass, rho)
+        M.aqual_solve(ref_ctx, rho, phi_ref, want_info=False)
+        M.aqual_solve(cold_ctx, rho, phi, want_info=False)
+        hist["cold"].append(errs(phi, phi_ref))
+        for K in Ks:
+            M.aqual_solve(warm_ctx[K], rho, phi, want_info=False)
+            hist[f"warm{K}"].append(errs(phi, phi_ref))
+        M.pm_step(step_ctx, pos, vel, mass, dt, want_info=False)
+    for c in (step_ctx, ref_ctx, cold_ctx, *warm_ctx.values()):
+        c.close()
+
+    # pm_step throughput, cold K_cold and warm K (fresh copies of the particles)
+    timing = {}
+    for name, K, flags in [("cold", K_cold, 0)] + [(f"warm{K}", K, M.PM_F_WARM_START) for K in Ks]:
+        c = M.pm_create(dict(p0, iters=K, flags=flags), Np)
+        pp, vv = pos.clone(), vel.clone()
+        for _ in range(2):
+            M.pm_step(c, pp, vv, mass, dt, want_info=False)
+        ms = min(_timed(lambda: M.pm_step(c, pp, vv, mass, dt, want_info=False))[0] for _ in range(reps))
+        timing[name] = ms
+        c.close()
+    return {"workload": w.get("workload", ""), "steps": steps, "dt": dt, "err_box_region": hist,
+            "step_ms": timing}
+
+
 def held_out_inputs(n=256, count=4):
     """Held-out Plummer mixtures at n (radii twice the training range) and the
     isothermal sphere of the throughput workload."""
@@ -263,7 +320,7 @@ def held_out_inputs(n=256, count=4):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("cmd", choices=["train", "eval"])
+    ap.add_argument("cmd", choices=["train", "eval", "warm"])
     ap.add_argument("--pairs", type=int, default=256)
     ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--batch", type=int, default=4)
@@ -272,16 +329,22 @@ def main(argv=None):
     ap.add_argument("--eval-n", type=int, default=256)
     ap.add_argument("--eval-count", type=int, default=4)
     ap.add_argument("--out", default=None, help="JSON file for the results")
+    ap.add_argument("--train-n", type=int, default=TRAIN_N, help="network size (half the FFT box) for training")
+    ap.add_argument("--init", default=None, help="start training from these parameters")
+    ap.add_argument("--seed0", type=int, default=0, help="first training seed")
     a = ap.parse_args(argv)
     log = lambda s: print(s, flush=True)  # noqa: E731
     torch.cuda.init()
     if a.cmd == "train":
-        net = M.Net(TRAIN_N, a.batch)
-        M.pm_net_set_params(net, init_params(0))
-        X, Y = make_dataset(net, a.pairs, log=log)
+        net = M.Net(a.train_n, a.batch)
+        M.pm_net_set_params(net, load_params(a.init) if a.init else init_params(0))
+        X, Y = make_dataset(net, a.pairs, seed0=a.seed0, log=log)
         hist = train(net, X, Y, a.epochs, batch=a.batch, lr=a.lr, log=log)
         save_params(a.weights, M.pm_net_get_params(net))
-        res = {"pairs": a.pairs, "epochs": a.epochs, "loss": hist}
+        res = {"pairs": a.pairs, "epochs": a.epochs, "n": a.train_n, "loss": hist}
+    elif a.cmd == "warm":
+        res = warm_start_trajectory(W.isothermal_sphere(seed=0))
+        log(json.dumps(res))
     else:
         v = load_params(a.weights)
         net = M.Net(a.eval_n, 1)

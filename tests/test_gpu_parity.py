@@ -179,6 +179,37 @@ def test_solve_in_place_and_h0(M):
     ctx.close()
 
 
+@pytest.mark.parametrize("K,extra", [(2, 0), (3, "residual")])
+def test_warm_start_from_previous_solve(M, K, extra):
+    # With PM_F_WARM_START the second solve starts from H0 = F_prev - g_N
+    # (projected divergence-free), F_prev the last F of the first solve; the
+    # oracle takes that start from its own first solve.
+    _log("warm start", K, extra)
+    w = W.random_cloud(31, 16, 60, mu=0, iters=K)
+    p = w["params"]
+    op = oparams(p)
+    N = p["n_pad"]
+    pos1 = w["pos"].astype(np.float64)
+    pos2 = pos1 + 0.4 * w["vel"].astype(np.float64) / np.abs(w["vel"]).max()
+    m = w["mass"].astype(np.float64)
+    rho1 = orc.deposit(op, pos1, m).astype(np.float32)
+    rho2 = orc.deposit(op, pos2, m).astype(np.float32)
+    _, i1 = orc.aqual_solve(op, rho1.astype(np.float64), keep_fields=True)
+    F1 = i1.gN + i1.H
+    _, gN2 = orc.newton_potential(op, rho2.astype(np.float64))
+    phi2_ref, _ = orc.aqual_solve(op, rho2.astype(np.float64), H0=F1 - gN2)
+    phi2_cold, _ = orc.aqual_solve(op, rho2.astype(np.float64))
+    flags = M.PM_F_WARM_START | (M.PM_F_RESIDUAL if extra == "residual" else 0)
+    ctx = M.pm_create(dict(p, flags=flags), 0)
+    phi = grid(N)
+    M.aqual_solve(ctx, dev(rho1), phi)
+    M.aqual_solve(ctx, dev(rho2), phi)
+    got = host(phi).reshape(N, N, N)
+    assert rel_l2(got, phi2_ref) < 1e-5
+    assert rel_l2(phi2_cold, phi2_ref) > 1e-4          # the start made a difference
+    ctx.close()
+
+
 def test_tolerance_mode(M):
     w = W.random_cloud(4, 16, 50, mu=0, iters=12)
     p = w["params"]
