@@ -516,6 +516,28 @@ __global__ __launch_bounds__(NT) void k_zpass(ZArgs a, const float2* __restrict_
     store_cols<L, T, NT, Last::R, HZ>(v, E, dst1, nvs, row);
     return;
   }
+  // Z_DIV also needs phi_N hat at the operator's elements (kz = j + r L / RL of
+  // the last stage); those loads are issued here, with the column loads, so
+  // their latency overlaps the forward transform.
+  constexpr int RLP = Last::R;
+  using BLP = Bfly<L, T, NT, RLP>;
+  float2 php[(ZOP == Z_DIV) ? HZ * BLP::BPT * RLP : 1];
+  if constexpr (ZOP == Z_DIV) {
+#pragma unroll
+    for (int u = 0; u < BLP::BPT; ++u) {
+      const int b = threadIdx.x + u * NT;
+      const int q = b % T, j = b / T;
+#pragma unroll
+      for (int h = 0; h < HZ; ++h)
+#pragma unroll
+        for (int r = 0; r < RLP; ++r) {
+          const int kz = j + r * (L / RLP);
+          const bool ok = BLP::valid(b) && q < nvh[h];
+          php[(h * BLP::BPT + u) * RLP + r] =
+              ok ? a.phiN[(long long)kz * row + off + h * T + q] : make_float2(0.0f, 0.0f);
+        }
+    }
+  }
   load_cols<L, T, NT, First::R, HZ * NIN>(v, E, src, nvs, row);
   __syncthreads();
   col_fft<L, T, NT, HZ * NIN, false, false>(v, lds, tw_s, 1);
@@ -597,8 +619,8 @@ __global__ __launch_bounds__(NT) void k_zpass(ZArgs a, const float2* __restrict_
           const float t2 = tx * tx + ty * ty + tz * tz;
           const float At = (t2 > 0.0f) ? 1.0f / t2 : 0.0f;
           const float2 g0 = *v0, g1 = *v1, g2 = *v2;
-          if (ZOP == Z_DIV) {
-            const float2 ph = inb ? a.phiN[(long long)kz * row + off + h * T + q] : make_float2(0.0f, 0.0f);
+          if constexpr (ZOP == Z_DIV) {
+            const float2 ph = php[(h * BLP::BPT + u) * RLP + r];
             const float2 mph = mul_mi<false>(ph);
             const float2 d0 = csub(cscale(mph, kpx), g0);
             const float2 d1 = csub(cscale(mph, kapy), g1);
