@@ -133,7 +133,9 @@ pm_status pm_deposit(pm_ctx* ctx, const float* pos, const float* mass, int64_t N
  * projection.  rho: device float [n_pad^3] (read); H0: device float
  * [3][n_pad^3] or NULL; phi: device float [n_pad^3] (written).  rho and phi
  * may be the same buffer.  info (host) may be NULL; when given, or when
- * tol > 0, the call synchronises and fills it. */
+ * tol > 0, the call synchronises and fills it.  With iters = 1, no H0 and no
+ * warm start the result is quasi-linear MOND (the equivalent system for
+ * QuMOND in Sect. 2): g_M = curl-free part of nu(|g_N|/a0) g_N. */
 pm_status aqual_solve(pm_ctx* ctx, const float* rho, const float* H0, float* phi,
                       pm_solve_info* info);
 

@@ -347,6 +347,17 @@ def aqual_solve(p: Params, rho: np.ndarray, H0: np.ndarray | None = None,
     return phi, info
 
 
+def qumond_potential(p: Params, rho: np.ndarray) -> np.ndarray:
+    """Potential of quasi-linear MOND (Sect. 2, the equivalent system for
+    QuMOND): g_M + H = nu(|g_N|/a0) g_N with g_M curl-free and H divergence
+    free, so g_M is the curl-free part of nu(|g_N|/a0) g_N and phi its
+    potential.  No iteration is involved."""
+    _, gN = newton_potential(p, rho)
+    rhs = apply_nu(p, gN)
+    _, phih = project_curl_free(p, np.stack([fft3(rhs[c]) for c in range(3)]))
+    return ifft3_real(phih)
+
+
 # ---------------------------------------------------------------------------
 # Forces and time integration (Eq. gi, Eq. motion; flow scheme steps 10-11)
 # ---------------------------------------------------------------------------

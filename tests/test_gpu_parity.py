@@ -210,6 +210,22 @@ def test_warm_start_from_previous_solve(M, K, extra):
     ctx.close()
 
 
+@pytest.mark.parametrize("mu", [0, 1])
+def test_qumond(M, mu):
+    # QuMOND (the equivalent system of Sect. 2) is the solve with one
+    # evaluation of nu from the zero start.
+    w = W.random_cloud(41, 32, 400, mu=mu, iters=1)
+    p = w["params"]
+    N = p["n_pad"]
+    rho32 = orc.deposit(oparams(p), w["pos"].astype(np.float64), w["mass"].astype(np.float64)).astype(np.float32)
+    phi_ref = orc.qumond_potential(oparams(p), rho32.astype(np.float64))
+    ctx = M.pm_create(p, 0)
+    phi = grid(N)
+    M.aqual_solve(ctx, dev(rho32), phi)
+    assert rel_l2(host(phi).reshape(N, N, N), phi_ref) < 1e-5
+    ctx.close()
+
+
 def test_tolerance_mode(M):
     w = W.random_cloud(4, 16, 50, mu=0, iters=12)
     p = w["params"]

@@ -277,3 +277,31 @@ def test_start_value_is_taken_divergence_free():
     _, rest = pm.aqual_solve(q3, rho, H0=mid.H)
     # mid made residuals r_1..r_3; the restart's r_1, r_2 are the long run's r_4, r_5
     assert np.allclose(rest.residuals, long.residuals[3:5], rtol=1e-7)
+
+
+def test_qumond_is_the_first_iteration_and_differs_from_aqual():
+    # QuMOND's g_M is the curl-free part of nu(|g_N|/a0) g_N: the solve with one
+    # evaluation of nu and a zero start computes exactly that.  The two
+    # theories agree for a point mass (the field is radial) and differ for a
+    # clumpy cloud.
+    p, pos, mass, rho = _cloud(5, 16, 40, W.MU_STANDARD, iters=1)
+    phi1, _ = pm.aqual_solve(p, rho)
+    phiq = pm.qumond_potential(p, rho)
+    assert np.max(np.abs(phi1 - phiq)) < 1e-12 * np.max(np.abs(phiq))
+    q = pm.Params.from_dict({**p.__dict__, "iters": 12})
+    phia, _ = pm.aqual_solve(q, rho)
+    d = np.linalg.norm(phia - phiq) / np.linalg.norm(phia)
+    assert 1e-4 < d < 5e-2
+
+
+def test_qumond_point_mass_deep_field():
+    # deep MOND: |g_M| = sqrt(G M a0) / r for a point mass in QuMOND as in AQUAL
+    p = pm.Params(n=64, n_pad=128, box=64.0, G=1.0, a0=1e3, mu=W.MU_DEEP, sigma=1.0)
+    M = 2.0
+    rho = pm.deposit(p, np.array([[0.0, 0.0, 0.0]]), np.array([M]))
+    phi = pm.qumond_potential(p, rho)
+    g = -pm.fd_gradient(p, phi)
+    c = p.n_pad // 2
+    for r in (4, 6, 8):
+        got = abs(g[0, c, c, c + r])
+        assert got == pytest.approx(math.sqrt(p.G * M * p.a0) / r, rel=0.03)
