@@ -314,27 +314,42 @@ __global__ __launch_bounds__(NT) void k_reduce_wgrad(const float* __restrict__ p
   }
 }
 
-// partial[block][c] = sum over this block's voxels of g[v][c] (C divides 256)
+// partial[block][c] = sum over this block's voxels of g[v][c]; a thread reads
+// 8 channels (16 bytes) at a time (C a multiple of 8 dividing 256)
 __global__ __launch_bounds__(NT) void k_colsum(const bf16* __restrict__ g, int64_t nvox, int C, float* partial) {
+  __shared__ float red[NT * 8];
+  const int groups = C / 8, cg = threadIdx.x % groups, lanes = NT / groups, l = threadIdx.x / groups;
+  float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int64_t v = blockIdx.x * (int64_t)lanes + l; v < nvox; v += (int64_t)gridDim.x * lanes) {
+    const uint4 u = *reinterpret_cast<const uint4*>(g + v * C + cg * 8);
+    const bf16* e = reinterpret_cast<const bf16*>(&u);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) s[i] += bf(e[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < 8; ++i) red[threadIdx.x * 8 + i] = s[i];
+  __syncthreads();
+  if (threadIdx.x < C) {
+    const int c = threadIdx.x, g8 = c / 8, i = c % 8;
+    float t = 0.0f;
+    for (int k = 0; k < lanes; ++k) t += red[(k * groups + g8) * 8 + i];
+    partial[blockIdx.x * C + c] = t;
+  }
+}
+
+// out[c] = sum over k of partial[k * C + c]; one block, C divides 256
+__global__ __launch_bounds__(NT) void k_reduce_cols(const float* __restrict__ partial, int nblk, int C, float* out) {
   __shared__ float red[NT];
-  const int c = threadIdx.x % C, lanes = NT / C, l = threadIdx.x / C;
+  const int c = threadIdx.x % C, lanes = NT / C;
   float s = 0.0f;
-  for (int64_t v = blockIdx.x * (int64_t)lanes + l; v < nvox; v += (int64_t)gridDim.x * lanes) s += bf(g[v * C + c]);
+  for (int k = threadIdx.x / C; k < nblk; k += lanes) s += partial[k * C + c];
   red[threadIdx.x] = s;
   __syncthreads();
   if (threadIdx.x < C) {
     float t = 0.0f;
-    for (int k = 0; k < lanes; ++k) t += red[k * C + threadIdx.x];
-    partial[blockIdx.x * C + threadIdx.x] = t;
+    for (int l = 0; l < lanes; ++l) t += red[l * C + threadIdx.x];
+    out[threadIdx.x] = t;
   }
-}
-
-__global__ __launch_bounds__(NT) void k_reduce_cols(const float* __restrict__ partial, int nblk, int C, float* out) {
-  const int c = threadIdx.x;
-  if (c >= C) return;
-  float s = 0.0f;
-  for (int k = 0; k < nblk; ++k) s += partial[k * C + c];
-  out[c] = s;
 }
 
 // 2 x 2 x 2 average pooling: out at level size nh = n / 2
@@ -457,12 +472,23 @@ __device__ void block_reduce_store(double (&v)[NV], double* part) {
   }
 }
 
-// out[k] = sum over blocks of part[b * nv + k] (FP64)
+// out[k] = sum over blocks of part[b * nv + k] (FP64); one block, all threads
+// share every k
 __global__ __launch_bounds__(NT) void k_reduce_d(const double* __restrict__ part, int nblk, int nv, double* out) {
-  for (int k = threadIdx.x; k < nv; k += NT) {
+  __shared__ double red[NT / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int k = 0; k < nv; ++k) {
     double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += part[b * nv + k];
-    out[k] = s;
+    for (int b = threadIdx.x; b < nblk; b += NT) s += part[b * nv + k];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) red[wave] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int w = 0; w < NT / 64; ++w) t += red[w];
+      out[k] = t;
+    }
+    __syncthreads();
   }
 }
 
@@ -754,7 +780,7 @@ hipError_t wgrad(const Buffers& B, int layer, const bf16* s0, const bf16* s1, co
                      B.grads + weight_offset(layer));
   NETCHK(launched("k_reduce_wgrad"));
   const int64_t nvox = level_voxels(n, 0) * batch;
-  const int nb = grid_for(nvox / (NT / COUT) + 1);
+  const int nb = grid_for(nvox / (NT / (COUT / 8)) + 1);
   hipLaunchKernelGGL(k_colsum, dim3(nb), dim3(NT), 0, st, gz, nvox, COUT, B.partial);
   NETCHK(launched("k_colsum"));
   hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(NT), 0, st, B.partial, nb, COUT, B.grads + bias_offset(layer));

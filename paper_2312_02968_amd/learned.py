@@ -307,6 +307,35 @@ def warm_start_trajectory(w, steps=10, Ks=(2, 3), K_cold=4, K_ref=30, reps=5):
             "step_ms": timing}
 
 
+def time_network(n, batch, reps=5, weights=None):
+    """Forward and training-step times (ms, mean of reps after two warm-up
+    calls) of the network at size n with random inputs and targets, and the
+    rates against the forward pass's 115 872 flop per voxel (training: 3x)."""
+    net = M.Net(n, batch)
+    M.pm_net_set_params(net, load_params(weights) if weights else init_params(0))
+    g = torch.Generator(device="cpu").manual_seed(0)
+    for b in range(batch):
+        M.pm_net_set_input(net, b, torch.randn(4 * n ** 3, generator=g).cuda())
+        M.pm_net_set_target(net, b, 0.1 * torch.randn(3 * n ** 3, generator=g).cuda())
+
+    def mean_ms(fn):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / reps
+
+    fwd = mean_ms(lambda: M.pm_net_run(net, batch))
+    trn = mean_ms(lambda: M.pm_net_train_step(net, batch, 1e-5, want_loss=False))
+    net.close()
+    flop = 115872.0 * n ** 3 * batch      # 54 cin cout per 3x3x3 layer over its level, 2 cin cout for the head
+    return {"n": n, "batch": batch, "forward_ms": fwd, "train_step_ms": trn,
+            "forward_tflops": flop / fwd * 1e-9, "train_tflops": 3 * flop / trn * 1e-9}
+
+
 def held_out_inputs(n=256, count=4):
     """Held-out Plummer mixtures at n (radii twice the training range) and the
     isothermal sphere of the throughput workload."""
@@ -320,7 +349,7 @@ def held_out_inputs(n=256, count=4):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("cmd", choices=["train", "eval", "warm"])
+    ap.add_argument("cmd", choices=["train", "eval", "warm", "time"])
     ap.add_argument("--pairs", type=int, default=256)
     ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--batch", type=int, default=4)
@@ -342,6 +371,9 @@ def main(argv=None):
         hist = train(net, X, Y, a.epochs, batch=a.batch, lr=a.lr, log=log)
         save_params(a.weights, M.pm_net_get_params(net))
         res = {"pairs": a.pairs, "epochs": a.epochs, "n": a.train_n, "loss": hist}
+    elif a.cmd == "time":
+        res = {"timings": [time_network(a.eval_n, 1), time_network(TRAIN_N, a.batch)]}
+        log(json.dumps(res))
     elif a.cmd == "warm":
         res = warm_start_trajectory(W.isothermal_sphere(seed=0))
         log(json.dumps(res))

@@ -240,3 +240,25 @@ def test_learned_start_field_and_solve():
     assert rel_l2(host(phi).reshape(N, N, N), phio) < 2e-3
     net.close()
     ctx.close()
+
+
+def test_net_forward_shift_equivariance_at_full_size():
+    # 256^3 (the network of a 512^3 box).  Periodic convolutions, pooling and
+    # upsampling commute with shifts by multiples of 4 voxels, and every output
+    # voxel is accumulated in the same order wherever it sits, so shifting the
+    # input shifts the output exactly.
+    n = 256
+    rng = np.random.default_rng(21)
+    v32, _ = gpu_params(6)
+    net = M.Net(n, 2)
+    M.pm_net_set_params(net, v32)
+    x = torch.from_numpy(net_inputs(rng, n)).cuda().view(4, n, n, n)
+    xs = torch.roll(x, shifts=(4, -8, 12), dims=(1, 2, 3)).contiguous()
+    M.pm_net_set_input(net, 0, x.reshape(-1).contiguous())
+    M.pm_net_set_input(net, 1, xs.reshape(-1))
+    M.pm_net_run(net, 2)
+    y0 = M.pm_net_output(net, 0, torch.empty(3 * n ** 3, device="cuda")).view(3, n, n, n)
+    y1 = M.pm_net_output(net, 1, torch.empty(3 * n ** 3, device="cuda")).view(3, n, n, n)
+    assert torch.equal(torch.roll(y0, shifts=(4, -8, 12), dims=(1, 2, 3)), y1)
+    assert float(y0.abs().max()) > 0.0
+    net.close()
