@@ -717,14 +717,16 @@ pm_status pm_net_create(int32_t n, int32_t max_batch, void* stream, pm_net** out
   NALLOC(b.target, 3 * V1);
   NALLOC(b.rms, (size_t)max_batch);
   NALLOC(b.sums, (size_t)max_batch + 64);
-  // weight-gradient partials: brick groups x 27 taps x the largest cin x cout (b3b: 64 x 64)
-  int64_t cc_max = 0;
-  for (int l = 0; l < net::NLAYER; ++l) {
-    const int64_t cc = (int64_t)net::kLayers[l].cin_p * net::kLayers[l].cout;
-    cc_max = cc > cc_max ? cc : cc_max;
-  }
-  b.partial_floats = (int64_t)net::kWgradGroups * 27 * cc_max;
+  // weight-gradient partial sums (the launch picks its number of brick groups
+  // to fit; the largest layer, b3b at 64 x 64, still gets 606)
+  b.partial_floats = net::kWgradPartialFloats;
   NALLOC(b.partial, (size_t)b.partial_floats);
+  size_t wmax = 0;   // largest weight tensor (b3b: 27 x 64 x 64)
+  for (int l = 0; l < net::NLAYER; ++l) {
+    const size_t cnt = (size_t)net::kLayers[l].taps * net::kLayers[l].cin * net::kLayers[l].cout;
+    wmax = cnt > wmax ? cnt : wmax;
+  }
+  NALLOC(b.partial2, (size_t)net::kWgradSlices * wmax);
   b.dpartial_count = 1024 * 52;
   NALLOC(b.dpartial, (size_t)b.dpartial_count);
 #undef NALLOC

@@ -9,8 +9,11 @@ namespace net {
 
 typedef __bf16 bf16;
 
-// brick groups of a weight-gradient launch (each writes one partial sum)
-constexpr int kWgradGroups = 256;
+// brick groups of a weight-gradient launch (each writes one partial sum): at
+// most kWgradGroups, and no more than kWgradPartialFloats / (27 cin cout)
+constexpr int kWgradGroups = 2048;
+constexpr int64_t kWgradPartialFloats = 64LL << 20;   // 256 MB of FP32 partial sums
+constexpr int kWgradSlices = 64;                       // first-stage slices of their reduction
 
 // Layers in parameter order; weights [taps][cin][cout] FP32 then bias [cout].
 enum Layer { E1A, E1B, E2A, E2B, B3A, B3B, D2A, D2B, D1A, D1B, OUT, NLAYER };
@@ -46,6 +49,7 @@ struct Buffers {
   double* rms = nullptr;     // [max_batch] scale of each slot
   double* sums = nullptr;    // [max_batch + 4] FP64 reduction results
   float* partial = nullptr;  // weight-gradient partial sums
+  float* partial2 = nullptr; // [kWgradSlices][27 cin cout] first-stage sums
   int64_t partial_floats = 0;
   double* dpartial = nullptr;  // FP64 block partials
   int64_t dpartial_count = 0;

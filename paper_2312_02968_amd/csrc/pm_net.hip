@@ -298,20 +298,34 @@ __global__ __launch_bounds__(NT) void k_wgrad(WgradArgs a) {
   }
 }
 
-// grads[(t cin_real + c) COUT + o] = sum over g of partial[g][t][c][o], c < cin_real
-__global__ __launch_bounds__(NT) void k_reduce_wgrad(const float* __restrict__ partial, int G, int CIN, int COUT,
-                                                     int cin_real, float* out) {
+// Two-stage sum over the brick groups.  Stage 1: part2[s][i] = sum over the
+// groups of slice s (blockIdx.y) of partial[g][t][c][o], with
+// i = (t cin_real + c) COUT + o and c < cin_real.
+__global__ __launch_bounds__(NT) void k_reduce_wgrad1(const float* __restrict__ partial, int G, int S, int CIN,
+                                                      int COUT, int cin_real, float* __restrict__ part2) {
   const int64_t count = 27LL * cin_real * COUT;
   const int64_t stride = 27LL * CIN * COUT;
-  for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < count; i += (int64_t)gridDim.x * NT) {
-    const int o = (int)(i % COUT);
-    const int64_t tc = i / COUT;
-    const int c = (int)(tc % cin_real), t = (int)(tc / cin_real);
-    const int64_t src = ((int64_t)t * CIN + c) * COUT + o;
-    float s = 0.0f;
-    for (int gi = 0; gi < G; ++gi) s += partial[gi * stride + src];
-    out[i] = s;
-  }
+  const int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x;
+  if (i >= count) return;
+  const int o = (int)(i % COUT);
+  const int64_t tc = i / COUT;
+  const int c = (int)(tc % cin_real), t = (int)(tc / cin_real);
+  const int64_t src = ((int64_t)t * CIN + c) * COUT + o;
+  const int s = blockIdx.y;
+  const int g0 = (int)((int64_t)G * s / S), g1 = (int)((int64_t)G * (s + 1) / S);
+  float acc = 0.0f;
+  for (int gi = g0; gi < g1; ++gi) acc += partial[gi * stride + src];
+  part2[s * count + i] = acc;
+}
+
+// Stage 2: out[i] = sum over slices of part2[s][i].
+__global__ __launch_bounds__(NT) void k_reduce_wgrad2(const float* __restrict__ part2, int S, int64_t count,
+                                                      float* __restrict__ out) {
+  const int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x;
+  if (i >= count) return;
+  float acc = 0.0f;
+  for (int s = 0; s < S; ++s) acc += part2[s * count + i];
+  out[i] = acc;
 }
 
 // partial[block][c] = sum over this block's voxels of g[v][c]; a thread reads
@@ -765,9 +779,13 @@ hipError_t conv(const bf16* s0, const bf16* s1, const bf16* w, const float* bias
 template <int CIN, int COUT, int C0>
 hipError_t wgrad(const Buffers& B, int layer, const bf16* s0, const bf16* s1, const bf16* gz, int n, int batch,
                  hipStream_t st) {
+  // as many brick groups as the partial-sum buffer holds (up to 2048), so that
+  // even the 16-channel layers put several blocks on every CU
   const int nbricks = ((n + WBX - 1) / WBX) * ((n + WBY - 1) / WBY) * ((n + WBZ - 1) / WBZ) * batch;
-  const int G = nbricks < WGROUPS ? nbricks : WGROUPS;
-  if ((int64_t)G * 27 * CIN * COUT > B.partial_floats) {
+  int64_t gmax = B.partial_floats / (27LL * CIN * COUT);
+  if (gmax > WGROUPS) gmax = WGROUPS;
+  const int G = nbricks < gmax ? nbricks : (int)gmax;
+  if (G < 1 || (int64_t)G * 27 * CIN * COUT > B.partial_floats) {
     g_where = "weight-gradient partial buffer too small";
     return hipErrorInvalidValue;
   }
@@ -776,9 +794,14 @@ hipError_t wgrad(const Buffers& B, int layer, const bf16* s0, const bf16* s1, co
   NETCHK(launched("k_wgrad"));
   const int cin_real = kLayers[layer].cin;
   const int64_t cnt = 27LL * cin_real * COUT;
-  hipLaunchKernelGGL(k_reduce_wgrad, dim3(grid_for(cnt)), dim3(NT), 0, st, B.partial, G, CIN, COUT, cin_real,
+  const int S = G < kWgradSlices ? G : kWgradSlices;
+  const int nbx = (int)((cnt + NT - 1) / NT);
+  hipLaunchKernelGGL(k_reduce_wgrad1, dim3(nbx, S), dim3(NT), 0, st, B.partial, G, S, CIN, COUT, cin_real,
+                     B.partial2);
+  NETCHK(launched("k_reduce_wgrad1"));
+  hipLaunchKernelGGL(k_reduce_wgrad2, dim3(nbx), dim3(NT), 0, st, B.partial2, S, cnt,
                      B.grads + weight_offset(layer));
-  NETCHK(launched("k_reduce_wgrad"));
+  NETCHK(launched("k_reduce_wgrad2"));
   const int64_t nvox = level_voxels(n, 0) * batch;
   const int nb = grid_for(nvox / (NT / (COUT / 8)) + 1);
   hipLaunchKernelGGL(k_colsum, dim3(nb), dim3(NT), 0, st, gz, nvox, COUT, B.partial);
