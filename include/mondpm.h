@@ -192,6 +192,15 @@ pm_status pm_read_timing(pm_ctx* ctx, double* total_ms, int64_t* launches);
  * [n_pad^3]; they may not overlap.  Used to form the learned start's input. */
 pm_status pm_newton_potential(pm_ctx* ctx, const float* rho, float* phiN);
 
+/* Apparent density of Eq. apparentdensity, rho_A = -div(g)/(4 pi G) with
+ * g = -grad phi, in the discretisation of the solve's projections
+ * (g_M_hat = -i kt phi_hat): rho_A_hat = -|kt|^2 phi_hat / (4 pi G).  From the
+ * MOND potential it gives baryonic plus phantom density, from the Newton
+ * potential the baryonic density; both without their mean (a periodic
+ * potential does not carry it).  phi, rho_a: device float [n_pad^3], may be
+ * the same buffer. */
+pm_status pm_apparent_density(pm_ctx* ctx, const float* phi, float* rho_a);
+
 /* aqual_solve that also returns F = g_N + H of its last iteration (the field
  * whose nu gave phi) in F: device float [3][n_pad^3].  Requires a context
  * created with PM_F_RESIDUAL or tol > 0 (it keeps F); otherwise PM_E_INVAL.

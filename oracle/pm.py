@@ -358,6 +358,20 @@ def qumond_potential(p: Params, rho: np.ndarray) -> np.ndarray:
     return ifft3_real(phih)
 
 
+def apparent_density(p: Params, phi: np.ndarray) -> np.ndarray:
+    """Apparent density of Eq. apparentdensity, rho_A = -div(g)/(4 pi G) with
+    g = -grad phi, written with the same discrete wavevector kt as the
+    projections (the field g_M of the solve is -i kt phi_hat):
+    rho_A_hat = -|kt|^2 phi_hat / (4 pi G).  The k = 0 mode is zero: a
+    potential on the periodic box does not fix the mean density.  Applied to
+    the Newton potential it gives the baryonic density the same way, and
+    the difference of the two is the phantom density."""
+    _, kt = wavevectors(p)
+    kx, ky, kz = _grids(kt)
+    k2 = kx * kx + ky * ky + kz * kz
+    return ifft3_real(-k2 * fft3(phi) / (4.0 * math.pi * p.G))
+
+
 # ---------------------------------------------------------------------------
 # Forces and time integration (Eq. gi, Eq. motion; flow scheme steps 10-11)
 # ---------------------------------------------------------------------------

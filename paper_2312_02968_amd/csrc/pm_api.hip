@@ -105,6 +105,7 @@ static int timer_of(PassKind k) {
     case PASS_Z_CURL_FINAL: return PM_T_Z_CURL_FINAL;
     case PASS_Z_DIV: return PM_T_Z_DIV;
     case PASS_Z_POISSON: return PM_T_Z_NEWTON;
+    case PASS_Z_APPARENT: return PM_T_Z_FWD;
   }
   return PM_T_REDUCE;
 }
@@ -610,6 +611,23 @@ pm_status pm_newton_potential(pm_ctx* c, const float* rho, float* phiN) {
   HIPCHK(pass(c, pdesc(PASS_Y_INV, c->spec, 1)));
   PassDesc x = pdesc(PASS_X_INV_REAL, c->spec);
   x.real = phiN;
+  HIPCHK(pass(c, x));
+  return PM_OK;
+}
+
+pm_status pm_apparent_density(pm_ctx* c, const float* phi, float* rho_a) {
+  if (!c) return inval("ctx is NULL");
+  if (!phi || !rho_a) return inval("phi and rho_a are required");
+  PassDesc d = pdesc(PASS_X_FWD_REAL, c->spec);
+  d.real = const_cast<float*>(phi);
+  HIPCHK(pass(c, d));
+  HIPCHK(pass(c, pdesc(PASS_Y_FWD, c->spec, 1)));
+  PassDesc z = pdesc(PASS_Z_APPARENT, c->spec);
+  z.z = zargs(c);
+  HIPCHK(pass(c, z));
+  HIPCHK(pass(c, pdesc(PASS_Y_INV, c->spec, 1)));
+  PassDesc x = pdesc(PASS_X_INV_REAL, c->spec);
+  x.real = rho_a;
   HIPCHK(pass(c, x));
   return PM_OK;
 }

@@ -441,7 +441,7 @@ __global__ __launch_bounds__(NT) void k_ypass(float2* spec, long long comp_strid
 }
 
 enum { Z_FWD = 0, Z_INV = 1, Z_NEWTON = 2, Z_CURL = 3, Z_CURL_FINAL = 4, Z_DIV = 5, Z_NEWTON_H0 = 6, Z_POISSON = 7,
-       Z_NEWTON_WARM = 8 };
+       Z_NEWTON_WARM = 8, Z_APPARENT = 9 };
 
 template <int ZOP> struct ZComp;
 template <> struct ZComp<Z_FWD>        { static constexpr int IN = 1, OUT = 1; };
@@ -453,6 +453,7 @@ template <> struct ZComp<Z_CURL>       { static constexpr int IN = 3, OUT = 3; }
 template <> struct ZComp<Z_CURL_FINAL> { static constexpr int IN = 3, OUT = 1; };
 template <> struct ZComp<Z_DIV>        { static constexpr int IN = 3, OUT = 3; };
 template <> struct ZComp<Z_POISSON>    { static constexpr int IN = 1, OUT = 1; };
+template <> struct ZComp<Z_APPARENT>   { static constexpr int IN = 1, OUT = 1; };
 
 // z pass: forward z transform of the input components, the spectral operator
 // at every (kx, ky, kz) in registers, inverse z transform, store.  A block
@@ -469,6 +470,8 @@ template <> struct ZComp<Z_POISSON>    { static constexpr int IN = 1, OUT = 1; }
 //   Z_CURL_FINAL: phi_hat = i At (kt . g) / N^3 (one output component)
 //   Z_DIV       : F = F' + kt At kt . (g_N - F'), g_N = -i kappa phi_N (/N^3)
 //   Z_POISSON   : phi_N_hat = -4 pi G A rho_hat / N^3 (one component, in place)
+//   Z_APPARENT  : rho_A_hat = -|kt|^2 phi_hat / (4 pi G N^3), the apparent density
+//                 of Eq. apparentdensity (one component, in place)
 //   Z_NEWTON_WARM: as Z_NEWTON_H0 with the previous F in place of H0, whose
 //                 divergence-free part minus that of g_N starts H:
 //                 F = P_L g_N + P_T F_prev
@@ -572,6 +575,12 @@ __global__ __launch_bounds__(NT) void k_zpass(ZArgs a, const float2* __restrict_
           const float k2 = kx * kx + ky * ky + kzz * kzz;
           const float A = (k2 > 0.0f) ? 1.0f / k2 : 0.0f;
           v[h * E + e] = cscale(v[h * E + e], a.newton_coef * A * a.scale);
+          continue;
+        }
+        if constexpr (ZOP == Z_APPARENT) {
+          const float tz = a.kt[kz];
+          const float t2 = tx * tx + ty * ty + tz * tz;
+          v[h * E + e] = cscale(v[h * E + e], t2 / a.newton_coef * a.scale);
           continue;
         }
         float2* v0 = v + (0 * HZ + h) * E + e;
@@ -760,6 +769,7 @@ hipError_t run_pass(const FftGeom& g, const PassDesc& d, hipStream_t st) {
     case PASS_Z_CURL_FINAL: return launch_z<N, Z_CURL_FINAL>(g, d.z, st);
     case PASS_Z_DIV: return launch_z<N, Z_DIV>(g, d.z, st);
     case PASS_Z_POISSON: return launch_z<N, Z_POISSON>(g, d.z, st);
+    case PASS_Z_APPARENT: return launch_z<N, Z_APPARENT>(g, d.z, st);
   }
   return hipErrorInvalidValue;
 }

@@ -32,7 +32,7 @@ struct ZArgs {
 enum PassKind {
   PASS_X_FWD_REAL, PASS_X_FWD_REAL3, PASS_X_INV_REAL, PASS_X_NU, PASS_X_MU,
   PASS_Y_FWD, PASS_Y_INV,
-  PASS_Z_FWD, PASS_Z_INV, PASS_Z_NEWTON, PASS_Z_CURL, PASS_Z_CURL_FINAL, PASS_Z_DIV, PASS_Z_POISSON
+  PASS_Z_FWD, PASS_Z_INV, PASS_Z_NEWTON, PASS_Z_CURL, PASS_Z_CURL_FINAL, PASS_Z_DIV, PASS_Z_POISSON, PASS_Z_APPARENT
 };
 
 struct PassDesc {

@@ -226,6 +226,27 @@ def test_qumond(M, mu):
     ctx.close()
 
 
+@pytest.mark.parametrize("mu", [0, 1])
+def test_apparent_density(M, mu):
+    # Eq. apparentdensity on the oracle's potential (the same FP32 values on
+    # both sides).  The operator weights a mode by |kt|^2, up to 3 (pi/s)^2,
+    # so FP32 transform rounding is amplified at high k.
+    w = W.random_cloud(51, 32, 300, mu=mu, iters=3)
+    p = w["params"]
+    N = p["n_pad"]
+    rho = orc.deposit(oparams(p), w["pos"].astype(np.float64), w["mass"].astype(np.float64))
+    phi, _ = orc.aqual_solve(oparams(p), rho)
+    phi32 = phi.astype(np.float32)
+    ref = orc.apparent_density(oparams(p), phi32.astype(np.float64))
+    ctx = M.pm_create(p, 0)
+    buf = dev(phi32)
+    M.pm_apparent_density(ctx, buf, buf)          # in place
+    got = host(buf).reshape(N, N, N)
+    assert rel_l2(got, ref) < 1e-4
+    assert rel_max(got, ref) < 1e-4
+    ctx.close()
+
+
 def test_tolerance_mode(M):
     w = W.random_cloud(4, 16, 50, mu=0, iters=12)
     p = w["params"]

@@ -305,3 +305,38 @@ def test_qumond_point_mass_deep_field():
     for r in (4, 6, 8):
         got = abs(g[0, c, c, c + r])
         assert got == pytest.approx(math.sqrt(p.G * M * p.a0) / r, rel=0.03)
+
+
+def test_apparent_mass_of_a_point_mass_from_gauss_law():
+    # Eq. totalmass: the apparent mass inside a sphere is the flux of g_M,
+    # R^2 g(R) / G; for a deep-MOND point mass g = sqrt(G M a0)/R, so
+    # M_A(<R) = sqrt(G M a0) R / G (the baryonic mass M is a small part of it).
+    p = pm.Params(n=64, n_pad=128, box=64.0, G=1.0, a0=1e3, mu=W.MU_DEEP, sigma=1.0, iters=4)
+    M = 2.0
+    rho = pm.deposit(p, np.array([[0.0, 0.0, 0.0]]), np.array([M]))
+    phi, _ = pm.aqual_solve(p, rho)
+    rho_a = pm.apparent_density(p, phi)
+    N = p.n_pad
+    ax = np.arange(N) - N // 2
+    z, y, x = np.meshgrid(ax, ax, ax, indexing="ij")
+    r = np.sqrt(x * x + y * y + z * z)
+    for R in (6, 10, 16):
+        assert rho_a[r < R].sum() * p.s ** 3 == pytest.approx(math.sqrt(p.G * M * p.a0) * R / p.G, rel=0.02)
+
+
+def test_apparent_density_of_the_newton_potential_is_rho():
+    # applied to phi_N the operator returns rho (up to the mean, which the
+    # periodic potential does not carry) wherever |kt| = |k|, i.e. off the
+    # Nyquist planes; the 4-sigma truncation of the kernel leaves content of
+    # order 1e-4 there
+    p = pm.Params(n=16, n_pad=32, box=16.0, G=0.7, sigma=2.0)
+    rho = pm.deposit(p, np.array([[0.3, -0.2, 0.1]]), np.array([1.5]))
+    phiN, _ = pm.newton_potential(p, rho)
+    rb = pm.apparent_density(p, phiN)
+    assert np.max(np.abs(rb - (rho - rho.mean()))) < 2e-4 * np.max(rho)
+    # and exactly, mode by mode, off the Nyquist planes
+    d = np.fft.fftn(rb - (rho - rho.mean()))
+    m = np.fft.fftfreq(32, 1.0 / 32)
+    off = (m != -16)
+    mask = off[:, None, None] & off[None, :, None] & off[None, None, :]
+    assert np.max(np.abs(d[mask])) < 1e-12 * np.max(np.abs(np.fft.fftn(rho)))
