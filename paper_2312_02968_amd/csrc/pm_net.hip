@@ -50,8 +50,14 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int NT = 256;
+#ifndef PM_CONV_PAD
+#define PM_CONV_PAD 0
+#endif
+#ifndef PM_CONV_BY
+#define PM_CONV_BY 4
+#endif
 // forward / backward-data brick: 16 x 4 x 4 voxels, one z plane per wave
-constexpr int BX = 16, BY = 4, BZ = 4;
+constexpr int BX = 16, BY = PM_CONV_BY, BZ = 4;
 constexpr int HX = BX + 2, HY = BY + 2, HZ = BZ + 2;
 constexpr int HSLOTS = HX * HY * HZ;
 // weight-gradient brick: 16 x 4 x 2 voxels
@@ -109,7 +115,7 @@ struct ConvArgs {
 template <int CIN, int COUT, int C0, bool RELU>
 __global__ __launch_bounds__(NT) void k_conv(ConvArgs a) {
   constexpr int CC = (CIN % 32 == 0) ? 32 : 16;
-  constexpr int CS = CC + 8;   // voxel slot stride in LDS (bf16), keeps 16 lanes on distinct banks
+  constexpr int CS = CC + PM_CONV_PAD;   // voxel slot stride in LDS (bf16); padding measured no faster
   constexpr int NCH = CIN / CC;
   constexpr int KS = (27 * CC + 31) / 32;
   constexpr int NTL = COUT / 16;
