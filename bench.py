@@ -9,11 +9,13 @@ self-consistent isothermal sphere of 2^20 equal masses on a 256^3 grid in a
 512^3 periodic FFT box (standard interpolation, sigma = 1 cell).  Inputs are
 resident in HBM before the timed region.  Prints one JSON line.
 
-The line carries a roofline record for the kernel with the largest share of
-the step (its launch durations come from HIP events recorded around every
-launch on the library's stream during the timed steps) and a CPU baseline:
-the FP64 oracle timed on a bounded sample of the same workload on the host
-cores.
+The timed region is K replays of the step recorded once as a HIP graph
+(pm_step_capture / pm_step_replay; --launch eager times K pm_step calls
+instead).  K eager steps follow with a HIP event pair around every launch on
+the library's stream: they give the per-kernel durations of the roofline
+record, for the kernel with the largest share of the step, and their own
+ms/step.  The line also carries a CPU baseline: the FP64 oracle timed on a
+bounded sample of the same workload on the host cores.
 """
 from __future__ import annotations
 
@@ -253,6 +255,8 @@ def main():
                     help="time pm_step with the warm start (previous step's F) and K iterations")
     ap.add_argument("--no-starts", action="store_true",
                     help="skip the learned-start and warm-start comparisons")
+    ap.add_argument("--launch", choices=("graph", "eager"), default="graph",
+                    help="time replays of the step recorded as a HIP graph (default) or eager pm_step calls")
     a = ap.parse_args()
     if a.copy_probe:
         copy_probe()
@@ -276,13 +280,30 @@ def main():
     N_part = len(w["mass"])
     dt = float(w["dt"])
     torch.cuda.init()
-    ctx = M.pm_create(p, N_part)
+    stream = torch.cuda.Stream()
+    ctx = M.pm_create(p, N_part, stream=stream)
     pos = torch.from_numpy(w["pos"]).cuda()
     vel = torch.from_numpy(w["vel"]).cuda()
     mass = torch.from_numpy(w["mass"]).cuda()
+    torch.cuda.synchronize()
     for _ in range(a.warmup):
         M.pm_step(ctx, pos, vel, mass, dt)
+    if a.warm and a.warmup == 0:
+        M.pm_step(ctx, pos, vel, mass, dt)        # the warm start needs a previous solve
     torch.cuda.synchronize()
+    ms_graph = None
+    if a.launch == "graph":
+        # The timed region: K replays of the whole step recorded as one HIP graph.
+        M.pm_step_capture(ctx, pos, vel, mass, dt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        M.pm_step_replay(ctx, a.steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ms_graph = (t1 - t0) * 1e3 / a.steps
+    # Eager steps with a HIP event pair around every launch on the library's
+    # stream: the per-kernel durations of the roofline record (and the timed
+    # region itself with --launch eager).
     M.pm_read_timing(ctx)
     M.pm_set_timing(ctx, True)
     torch.cuda.synchronize()
@@ -293,7 +314,8 @@ def main():
     t1 = time.perf_counter()
     timing = M.pm_read_timing(ctx)
     M.pm_set_timing(ctx, False)
-    ms_step = (t1 - t0) * 1e3 / a.steps
+    ms_eager = (t1 - t0) * 1e3 / a.steps
+    ms_step = ms_graph if ms_graph is not None else ms_eager
 
     Npad = p["n_pad"]
     K = p["iters"]
@@ -331,6 +353,8 @@ def main():
         "config": {"workload": w["workload"], "grid": p["n"], "fft_box": Npad, "particles": N_part,
                    "iterations": K, "start": "warm" if a.warm else "zero", "sigma_cells": p["sigma"],
                    "mu": "standard" if p["mu"] == 0 else ("deep" if p["mu"] == 1 else "newton"), "dt": dt},
+        "launch": a.launch,
+        "ms_per_step_eager": round(ms_eager, 3),
         "particle_updates_per_s": round(N_part * 1e3 / ms_step, 1),
         "roofline": roof,
     }

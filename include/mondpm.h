@@ -156,6 +156,21 @@ pm_status interp_push(pm_ctx* ctx, const float* phi, float* pos, float* vel, int
 pm_status pm_step(pm_ctx* ctx, float* pos, float* vel, const float* mass, int64_t N,
                   double dt, pm_solve_info* info);
 
+/* One pm_step (info = NULL) recorded as a HIP graph and replayed: the whole
+ * step of the flow scheme's main loop, every kernel of deposit, solve and
+ * push, with one launch call per step.  pm_step_capture records the step on
+ * the context's stream with these buffers and this dt, without running it,
+ * and keeps the graph in the context (replacing an earlier one; pm_destroy
+ * frees it).  pm_step_replay launches it count times on the stream; each
+ * replay is one pm_step on the captured buffers, which the caller keeps alive
+ * and in place.  PM_E_INVAL if the context was created on the null stream,
+ * has tol > 0 (that mode synchronises), has event timing on, or has
+ * PM_F_WARM_START before its first solve (capture after one pm_step so the
+ * recorded solve starts warm); on a capture error no graph is kept. */
+pm_status pm_step_capture(pm_ctx* ctx, float* pos, float* vel, const float* mass, int64_t N,
+                          double dt);
+pm_status pm_step_replay(pm_ctx* ctx, int32_t count);
+
 /* FP64 diagnostics (constants of motion of Sect. 4.1): out (host) receives
  * 10 doubles: P (3), L (3), E_kin, total mass, and, if phi is not NULL,
  * sum_i m_i phi_i with phi smoothed by the particle kernel (else 0), and the

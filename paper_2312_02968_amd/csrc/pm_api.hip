@@ -56,6 +56,7 @@ struct pm_ctx {
   KernelGeom kg{};
   SortBufs sb{};
   int npartials = 0;
+  hipGraphExec_t step_graph = nullptr;  // one captured pm_step (pm_step_capture)
   // event timing
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -181,6 +182,7 @@ pm_status pm_destroy(pm_ctx* c) {
   if (!c) return PM_OK;
   (void)(c->st ? hipStreamSynchronize(c->st) : hipDeviceSynchronize());
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  if (c->step_graph) (void)hipGraphExecDestroy(c->step_graph);
   for (void* v : c->allocs) (void)hipFree(v);
   if (c->hacc) (void)hipHostFree(c->hacc);
   delete c;
@@ -522,6 +524,45 @@ pm_status pm_step(pm_ctx* c, float* pos, float* vel, const float* mass, int64_t 
     HIPCHK(hipStreamSynchronize(c->st));
     info->bounds_flag = flag > 0 ? 1 : 0;
   }
+  return PM_OK;
+}
+
+pm_status pm_step_capture(pm_ctx* c, float* pos, float* vel, const float* mass, int64_t n, double dt) {
+  pm_status s = check_ctx(c, n);
+  if (s != PM_OK) return s;
+  if (n > 0 && (!pos || !vel || !mass)) return inval("NULL buffer");
+  if (!c->st) return inval("capture needs the context to run on a created stream, not the null stream");
+  if (c->p.tol > 0.0) return inval("tolerance mode reads the residual on the host and cannot be captured");
+  if (c->timing) return inval("switch event timing off before capturing");
+  if ((c->p.flags & PM_F_WARM_START) && !c->have_F)
+    return inval("warm start: run one pm_step before capturing, so the captured solve starts warm");
+  if (c->step_graph) {
+    (void)hipGraphExecDestroy(c->step_graph);
+    c->step_graph = nullptr;
+  }
+  HIPCHK(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
+  s = pm_step(c, pos, vel, mass, n, dt, nullptr);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(c->st, &g);
+  if (s != PM_OK) {
+    if (e == hipSuccess && g) (void)hipGraphDestroy(g);
+    return s;
+  }
+  if (e != hipSuccess) return dev_fail(e, "hipStreamEndCapture");
+  const hipError_t ei = hipGraphInstantiate(&c->step_graph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ei != hipSuccess) {
+    c->step_graph = nullptr;
+    return dev_fail(ei, "hipGraphInstantiate");
+  }
+  return PM_OK;
+}
+
+pm_status pm_step_replay(pm_ctx* c, int32_t count) {
+  if (!c) return inval("ctx is NULL");
+  if (!c->step_graph) return inval("no captured step on this context");
+  if (count < 0) return inval("count must be >= 0");
+  for (int32_t i = 0; i < count; ++i) HIPCHK(hipGraphLaunch(c->step_graph, c->st));
   return PM_OK;
 }
 

@@ -483,7 +483,14 @@ __global__ __launch_bounds__(NT) void k_zpass(ZArgs a, const float2* __restrict_
   extern __shared__ float2 lds[];
   float2* tw_s = lds + ColBuf<L, T>::elems;
   const int ntile = (a.ncols + HZ * T - 1) / (HZ * T);
-  const int tile = blockIdx.x % ntile, y = blockIdx.x / ntile;
+  // Workgroups go to the 8 XCDs round robin (block b to XCD b % 8), each XCD
+  // with its own L2.  A tile of T = 8 complex columns is half a 128-byte line,
+  // so tiles 2j and 2j+1 read the same lines; numbering the tiles so that
+  // blocks b and b + 8 (same XCD, dispatched one after the other) take
+  // neighbouring tiles lets the second read hit in that XCD's L2.
+  const int nb = gridDim.x;
+  const int lb = (nb % 8 == 0) ? (blockIdx.x % 8) * (nb / 8) + blockIdx.x / 8 : blockIdx.x;
+  const int tile = lb % ntile, y = lb / ntile;
   const int x0 = tile * HZ * T;
   const long long row = (long long)L * a.P;
   const long long off = (long long)y * a.P + x0;

@@ -64,6 +64,8 @@ def lib():
         L.smooth_accel.argtypes = [VP, VP, VP, I64, VP]
         L.interp_push.argtypes = [VP, VP, VP, VP, I64, D, D]
         L.pm_step.argtypes = [VP, VP, VP, VP, I64, D, P(PmSolveInfo)]
+        L.pm_step_capture.argtypes = [VP, VP, VP, VP, I64, D]
+        L.pm_step_replay.argtypes = [VP, ctypes.c_int32]
         L.pm_diagnostics.argtypes = [VP, VP, VP, VP, I64, VP, P(ctypes.c_double)]
         L.pm_spectrum_pitch.argtypes = [ctypes.c_int32]
         L.pm_spectrum_pitch.restype = ctypes.c_int32
@@ -97,7 +99,7 @@ def lib():
         L.pm_net_train_step.argtypes = [VP, I32, F32, P(D)]
         L.pm_net_forward.argtypes = [VP, VP, VP, VP]
         for f in ("pm_create", "pm_destroy", "pm_deposit", "aqual_solve", "smooth_accel", "interp_push",
-                  "pm_step", "pm_diagnostics", "pm_fft_r2c", "pm_fft_c2r", "pm_set_timing",
+                  "pm_step", "pm_step_capture", "pm_step_replay", "pm_diagnostics", "pm_fft_r2c", "pm_fft_c2r", "pm_set_timing",
                   "pm_read_timing", "pm_newton_potential", "pm_apparent_density", "aqual_solve_field", "pm_net_create",
                   "pm_net_destroy", "pm_net_set_params", "pm_net_get_params", "pm_net_get_grads",
                   "pm_net_input", "pm_net_target", "pm_net_set_input", "pm_net_get_input",
@@ -221,6 +223,19 @@ def pm_step(ctx: Ctx, pos, vel, mass, dt, want_info=False):
                          _ptr(mass, name="mass"), n, float(dt),
                          ctypes.byref(info) if want_info else None), "pm_step")
     return info.to_dict() if want_info else None
+
+
+def pm_step_capture(ctx: Ctx, pos, vel, mass, dt):
+    """Records one pm_step on these buffers as a graph kept by the context
+    (nothing runs); the context must live on a created stream."""
+    n = mass.numel()
+    _check(lib().pm_step_capture(ctx.handle, _ptr(pos, numel=3 * n, name="pos"),
+                                 _ptr(vel, numel=3 * n, name="vel"), _ptr(mass, name="mass"), n, float(dt)),
+           "pm_step_capture")
+
+
+def pm_step_replay(ctx: Ctx, count=1):
+    _check(lib().pm_step_replay(ctx.handle, int(count)), "pm_step_replay")
 
 
 def pm_diagnostics(ctx: Ctx, pos, vel, mass, phi=None):
