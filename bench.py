@@ -46,16 +46,18 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, workload):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (FETCH_SIZE x fetch_scale + WRITE_SIZE x write_scale), or None when the
-    summary is missing or was taken on different kernel sources."""
+    summary is missing, was taken on different kernel sources or on another
+    workload."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("source_hash") != source_hash() or kernel not in t.get("kernels", {}):
+    if (t.get("source_hash") != source_hash() or t.get("workload") != workload
+            or kernel not in t.get("kernels", {})):
         return None
     return t["kernels"][kernel]["bytes_per_launch"]
 
@@ -335,7 +337,7 @@ def main():
             print(f"{k:14s} {t / a.steps:8.3f} ms/step  {c // a.steps:3d} launches/step  "
                   f"{t / c:8.4f} ms/launch{extra}", file=sys.stderr)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom), "kernel": dom,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom, w["workload"]), "kernel": dom,
             "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": int(bytes_launch)}
     out = {
         "metric": METRIC,

@@ -212,15 +212,16 @@ __global__ __launch_bounds__(NT) void k_xpass(float2* spec, long long comp_strid
 }
 
 // ----------------------------------------------------------------------------
-// x pass for n_pad = 512 (rows of H = 256 complex): one 16-lane group per
-// row, four rows per wave, four waves per block.  Lane j of a group holds the
-// elements k = j + 16 r (r < 16) of its row for every component, so
-//  - the 256-point FFT is 16 x 16: a radix-16 DFT in registers, one exchange
-//    through a wave-private LDS buffer, twiddles, a radix-16 DFT, and the
-//    output is again at k = j + 16 r;
+// x pass for n_pad = 512 and 1024 (rows of H = 256 or 512 complex): a group of
+// LANES lanes per row (16 for H = 256, four rows per wave; 64 for H = 512, one
+// row per wave), four waves per block.  Lane j of a group holds the elements
+// k = j + LANES r (r < RG = H / LANES) of its row for every component, so
+//  - the FFT runs in registers with wave-private LDS exchanges: 16 x 16 for
+//    H = 256, 8 x 8 x 8 for H = 512, and the output is again at
+//    k = j + LANES r;
 //  - the partner H - k of element k (even/odd split of the real transform)
-//    sits in lane 16 - j, register 15 - r (lane 0 pairs within itself), so the
-//    split and merge are cross-lane shuffles;
+//    sits in lane LANES - j, register RG - 1 - r (lane 0 pairs within
+//    itself), so the split and merge are cross-lane shuffles;
 //  - nu / mu act on the registers.
 // No block-wide barrier is needed after the twiddle table is loaded.
 // ----------------------------------------------------------------------------
@@ -252,62 +253,119 @@ __device__ __forceinline__ void fft256_group(float2* v, float2* xb, int j, const
   Dft<16, INV>::run(v);                                  // outputs y[j + 16 r]
 }
 
-template <int XMODE, int NC>
-__global__ __launch_bounds__(256) void k_xpass256(float2* spec, long long comp_stride, int P, float* real,
-                                                  long long real_comp_stride, const float2* __restrict__ tw,
-                                                  int mu_mode, float inv_a0, float* fprev, double* partials) {
-  constexpr int H = 256, N = 512;
+// 512-point FFT of the wave's row held as v[r] = x[j + 64 r], j = lane; result
+// in the same layout.  x = j + 64 r and k = s + 8 a + 64 b: a radix-8 DFT over
+// r (giving s), twiddles w_512^(j s), then for each s a 64-point DFT over
+// j = j1 + 8 j2 as a radix-8 DFT over j2 (giving a), twiddles w_64^(j1 a) and a
+// radix-8 DFT over j1 (giving b).  After the first exchange lane s + 8 j1
+// holds the 8 values j2; after the second, lane s + 8 a = k mod 64 holds the 8
+// values j1, so the last DFT leaves X[lane + 64 b] in v[b].  xb: the wave's
+// 544-entry LDS row; tw_s: the 1024-entry table w_1024^t.
+template <bool INV>
+__device__ __forceinline__ void fft512_wave(float2* v, float2* xb, int j, const float2* tw_s) {
+  Dft<8, INV>::run(v);
+#pragma unroll
+  for (int r = 1; r < 8; ++r) {
+    float2 w = tw_s[2 * j * r];                          // w_512^(j s)
+    if (INV) w.y = -w.y;
+    v[r] = cmul(v[r], w);
+  }
+#pragma unroll
+  for (int r = 0; r < 8; ++r) xb[xpad(64 * r + j)] = v[r];
+  wave_sync();
+  const int s = j & 7, j1 = j >> 3;
+#pragma unroll
+  for (int r = 0; r < 8; ++r) v[r] = xb[xpad(64 * s + j1 + 8 * r)];
+  wave_sync();
+  Dft<8, INV>::run(v);
+#pragma unroll
+  for (int r = 1; r < 8; ++r) {
+    float2 w = tw_s[16 * j1 * r];                        // w_64^(j1 a)
+    if (INV) w.y = -w.y;
+    v[r] = cmul(v[r], w);
+  }
+#pragma unroll
+  for (int r = 0; r < 8; ++r) xb[xpad(64 * s + 8 * r + j1)] = v[r];
+  wave_sync();
+  const int a = j >> 3;
+#pragma unroll
+  for (int r = 0; r < 8; ++r) v[r] = xb[xpad(64 * s + 8 * a + r)];
+  wave_sync();
+  Dft<8, INV>::run(v);
+}
+
+template <int H>
+struct XWave {
+  static constexpr int N = 2 * H;
+  static constexpr int LANES = (H == 256) ? 16 : 64;
+  static constexpr int RG = H / LANES;              // elements per lane and component
+  static constexpr int G = 64 / LANES;              // rows per wave
+  static constexpr int ROWS = 4 * G;                // rows per block (4 waves)
+  static constexpr int XB = H + H / 16;             // padded LDS row (xpad)
+  template <bool INV>
+  __device__ __forceinline__ static void fft(float2* v, float2* xb, int j, const float2* tw_s) {
+    if constexpr (H == 256) fft256_group<INV>(v, xb, j, tw_s);
+    else fft512_wave<INV>(v, xb, j, tw_s);
+  }
+};
+
+template <int H, int XMODE, int NC>
+__global__ __launch_bounds__(256) void k_xpass_wave(float2* spec, long long comp_stride, int P, float* real,
+                                                    long long real_comp_stride, const float2* __restrict__ tw,
+                                                    int mu_mode, float inv_a0, float* fprev, double* partials) {
+  using X = XWave<H>;
+  constexpr int N = X::N, LANES = X::LANES, RG = X::RG;
   extern __shared__ float2 lds[];
   float2* tw_s = lds;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int g = lane >> 4, j = lane & 15;
-  float2* xb = lds + N + (wave * 4 + g) * 272;
-  const long long row = (long long)blockIdx.x * 16 + wave * 4 + g;
+  const int g = lane / LANES, j = lane % LANES;
+  float2* xb = lds + N + (wave * X::G + g) * X::XB;
+  const long long row = (long long)blockIdx.x * X::ROWS + wave * X::G + g;
   for (int t = threadIdx.x; t < N; t += 256) tw_s[t] = tw[t];
   __syncthreads();
 
-  float2 v[NC][16];
-  const int pl = (lane & ~15) | ((16 - j) & 15);          // lane of the partner elements
+  float2 v[NC][RG];
+  const int pl = (lane & ~(LANES - 1)) | ((LANES - j) & (LANES - 1));   // lane of the partner elements
 
   if (XMODE == X_FWD_REAL) {
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       const float2* src = reinterpret_cast<const float2*>(real + c * real_comp_stride + row * N);
 #pragma unroll
-      for (int r = 0; r < 16; ++r) v[c][r] = src[j + 16 * r];
+      for (int r = 0; r < RG; ++r) v[c][r] = src[j + LANES * r];
     }
   } else {
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       const float2* src = spec + c * comp_stride + row * P;
-      float2 x[16];
+      float2 x[RG];
 #pragma unroll
-      for (int r = 0; r < 16; ++r) x[r] = src[j + 16 * r];
+      for (int r = 0; r < RG; ++r) x[r] = src[j + LANES * r];
       const float2 nyq = src[H];
       // merge: Z[k] = (Xk + conj Xm) + i (Xk - conj Xm) conj(W^k), Xm = X[H - k]
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
+      for (int r = 0; r < RG; ++r) {
         float2 xm;
-        xm.x = __shfl(x[15 - r].x, pl, 64);
-        xm.y = __shfl(x[15 - r].y, pl, 64);
-        if (j == 0) xm = (r == 0) ? nyq : x[(16 - r) & 15];
-        const int k = j + 16 * r;
+        xm.x = __shfl(x[RG - 1 - r].x, pl, 64);
+        xm.y = __shfl(x[RG - 1 - r].y, pl, 64);
+        if (j == 0) xm = (r == 0) ? nyq : x[(RG - r) & (RG - 1)];
+        const int k = j + LANES * r;
         const float2 a = cadd(x[r], cconj(xm));
         const float2 d = cmul(csub(x[r], cconj(xm)), cconj(tw_s[k]));
         v[c][r] = cadd(a, mul_mi<true>(d));
       }
     }
 #pragma unroll
-    for (int c = 0; c < NC; ++c) fft256_group<true>(v[c], xb, j, tw_s);
+    for (int c = 0; c < NC; ++c) X::template fft<true>(v[c], xb, j, tw_s);
   }
 
   if constexpr (XMODE == X_FUSED_NU || XMODE == X_FUSED_MU) {
     double acc = 0.0;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
+    for (int r = 0; r < RG; ++r) {
       float2 a0 = v[0][r], a1 = v[1][r], a2 = v[2][r];
       if (XMODE == X_FUSED_NU && fprev != nullptr) {
-        const long long e = row * N + 2 * (j + 16 * r);
+        const long long e = row * N + 2 * (j + LANES * r);
         const long long cs = (long long)N * N * N;
         float2* f0 = reinterpret_cast<float2*>(fprev + e);
         float2* f1 = reinterpret_cast<float2*>(fprev + cs + e);
@@ -338,23 +396,23 @@ __global__ __launch_bounds__(256) void k_xpass256(float2* spec, long long comp_s
   if (XMODE == X_INV_REAL) {
     float2* dst = reinterpret_cast<float2*>(real + row * N);
 #pragma unroll
-    for (int r = 0; r < 16; ++r) dst[j + 16 * r] = v[0][r];
+    for (int r = 0; r < RG; ++r) dst[j + LANES * r] = v[0][r];
     return;
   }
 
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
-    fft256_group<false>(v[c], xb, j, tw_s);
+    X::template fft<false>(v[c], xb, j, tw_s);
     float2* dst = spec + c * comp_stride + row * P;
     // split: X[k] = E + W^k O, E = (Zk + conj Zm)/2, O = -i (Zk - conj Zm)/2
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
+    for (int r = 0; r < RG; ++r) {
       float2 zm;
-      zm.x = __shfl(v[c][15 - r].x, pl, 64);
-      zm.y = __shfl(v[c][15 - r].y, pl, 64);
-      if (j == 0) zm = v[c][(16 - r) & 15];
+      zm.x = __shfl(v[c][RG - 1 - r].x, pl, 64);
+      zm.y = __shfl(v[c][RG - 1 - r].y, pl, 64);
+      if (j == 0) zm = v[c][(RG - r) & (RG - 1)];
       const float2 zk = v[c][r];
-      const int k = j + 16 * r;
+      const int k = j + LANES * r;
       const float2 e = cscale(cadd(zk, cconj(zm)), 0.5f);
       const float2 o = cscale(mul_mi<false>(csub(zk, cconj(zm))), 0.5f);
       if (k == 0) {
@@ -718,17 +776,19 @@ template <int N, int XMODE, int NC>
 hipError_t launch_x(const FftGeom& g, float2* spec, float* real, long long real_cs, int mu_mode,
                     float inv_a0, float* fprev, double* partials, hipStream_t st) {
   using C = Cfg<N>;
-  if (N == 512) {
-    const size_t sh = sizeof(float2) * (512 + 16 * 272);
-    hipLaunchKernelGGL((k_xpass256<XMODE, NC>), dim3(N * N / 16), dim3(256), sh, st, spec, g.comp_stride, g.P,
-                       real, real_cs, g.tw, mu_mode, inv_a0, fprev, partials);
+  if constexpr (N == 512 || N == 1024) {
+    using X = XWave<N / 2>;
+    const size_t sh = sizeof(float2) * (N + (size_t)X::ROWS * X::XB);
+    hipLaunchKernelGGL((k_xpass_wave<N / 2, XMODE, NC>), dim3(N * N / X::ROWS), dim3(256), sh, st, spec,
+                       g.comp_stride, g.P, real, real_cs, g.tw, mu_mode, inv_a0, fprev, partials);
+    return hipGetLastError();
+  } else {
+    const int blocks = N * N / C::ROWS;
+    const size_t sh = sizeof(float2) * ((size_t)(C::H + 1) * (NC * C::ROWS + 1) + N);
+    hipLaunchKernelGGL((k_xpass<C::H, C::ROWS, NC, kNT, XMODE>), dim3(blocks), dim3(kNT), sh, st, spec,
+                       g.comp_stride, g.P, real, real_cs, g.tw, mu_mode, inv_a0, fprev, partials);
     return hipGetLastError();
   }
-  const int blocks = N * N / C::ROWS;
-  const size_t sh = sizeof(float2) * ((size_t)(C::H + 1) * (NC * C::ROWS + 1) + N);
-  hipLaunchKernelGGL((k_xpass<C::H, C::ROWS, NC, kNT, XMODE>), dim3(blocks), dim3(kNT), sh, st, spec,
-                     g.comp_stride, g.P, real, real_cs, g.tw, mu_mode, inv_a0, fprev, partials);
-  return hipGetLastError();
 }
 
 template <int N, bool INV>
@@ -783,7 +843,8 @@ hipError_t run_pass(const FftGeom& g, const PassDesc& d, hipStream_t st) {
 }  // namespace
 
 int x_blocks(int N) {
-  if (N == 512) return N * N / 16;
+  if (N == 512) return N * N / XWave<256>::ROWS;
+  if (N == 1024) return N * N / XWave<512>::ROWS;
   const int H = N / 2;
   int rows = 1024 / H;
   rows = rows < 1 ? 1 : (rows > 64 ? 64 : rows);

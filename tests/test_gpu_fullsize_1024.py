@@ -1,0 +1,184 @@
+"""Parity at the precision workload's full size: 512^3 grid in a 1024^3 FFT
+box, 2^24 particles in a mixture of eight Plummer spheres, in the launch
+configuration the benchmark times for it.
+
+The FP64 oracle cannot solve a 1024^3 box in seconds, so the solve and the
+gather are checked through an exact embedding.  A field of period 512 on the
+1024^3 box has only even modes, and on those modes everything the solve uses
+equals its value on the 512^3 box:
+- the wavevectors;
+- the Nyquist-zeroed k~ of the projections (the 1024 Nyquist plane is the
+  doubled 512 Nyquist plane);
+- the finite-difference symbol.
+nu and mu act cell by cell.  So the 1024^3 solve of a 512^3 density tiled
+2 x 2 x 2 is the 512^3 solve tiled, and the oracle solves the 512^3 box.
+
+A 512-periodic potential on the 1024^3 box, shifted so that its cell j holds
+the 512^3 potential's cell (j - 256) mod 512, gives every particle the force
+the oracle computes on the 512^3 box, whose ball indices wrap mod 512.
+
+The density is checked on sampled cells against the particles whose ball
+covers them.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import pm as orc  # noqa: E402
+import workloads as W  # noqa: E402
+from tests.gpu_util import oparams, rel_l2, rel_max  # noqa: E402
+
+N = 1024
+H = N // 2
+
+
+def _log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _host32(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def M():
+    from paper_2312_02968_amd import mondpm
+    mondpm.lib()
+    return mondpm
+
+
+@pytest.fixture(scope="module")
+def mix():
+    return W.plummer_mixture(seed=0)
+
+
+@pytest.fixture(scope="module")
+def half(mix):
+    """The 512^3 box: params with the mixture's physics, a density from a
+    2^16-particle mixture that fits it, and its oracle potential (K = 2)."""
+    _log("oracle: 512^3 density and solve")
+    p512 = dict(mix["params"], n=256, n_pad=512, box=256.0, iters=2, flags=0)
+    small = W.plummer_mixture(seed=1, N=1 << 16, n=256, a_range=(4.0, 16.0), a0=mix["params"]["a0"])
+    rho = orc.deposit(oparams(p512), small["pos"].astype(np.float64),
+                      small["mass"].astype(np.float64)).astype(np.float32)
+    phi, info = orc.aqual_solve(oparams(p512), rho.astype(np.float64))
+    return p512, rho, phi, info
+
+
+@pytest.mark.timeout(600)
+def test_solve_1024_periodic_embedding(M, mix, half):
+    p512, rho, phi_ref, info_ref = half
+    _log("solve 1024 (tiled 512 density), K =", p512["iters"])
+    p = dict(mix["params"], iters=p512["iters"], flags=M.PM_F_RESIDUAL)
+    ctx = M.pm_create(p, 0)
+    rho_t = _dev(np.tile(rho, (2, 2, 2)))
+    phi = torch.zeros(N ** 3, dtype=torch.float32, device="cuda")
+    info = M.aqual_solve(ctx, rho_t, phi)
+    del rho_t
+    got = _host32(phi).reshape(N, N, N)
+    ctx.close()
+    del phi
+    for a in (0, 1):
+        for b in (0, 1):
+            for c in (0, 1):
+                tile = got[a * H:(a + 1) * H, b * H:(b + 1) * H, c * H:(c + 1) * H].astype(np.float64)
+                assert rel_l2(tile, phi_ref) < 1e-5
+                assert rel_max(tile, phi_ref) < 1e-5
+    for x, y in zip(info["residuals"], info_ref.residuals):
+        assert x == pytest.approx(y, rel=1e-3)
+
+
+@pytest.mark.timeout(600)
+def test_gather_1024_sampled(M, mix, half):
+    _log("gather 1024 sampled, 2^24 particles")
+    p512, _, phi_ref, _ = half
+    p = dict(mix["params"], iters=1)
+    n = len(mix["mass"])
+    phi1024 = np.roll(np.tile(phi_ref.astype(np.float32), (2, 2, 2)), H // 2, axis=(0, 1, 2))
+    ctx = M.pm_create(p, n)
+    acc = torch.zeros(3 * n, dtype=torch.float32, device="cuda")
+    M.smooth_accel(ctx, _dev(phi1024), _dev(mix["pos"]), acc)
+    del phi1024
+    got = _host32(acc).reshape(-1, 3).astype(np.float64)
+    ctx.close()
+    idx = np.random.default_rng(5).choice(n, 4096, replace=False)
+    ref = orc.smooth_accel(oparams(p512), phi_ref.astype(np.float32).astype(np.float64),
+                           mix["pos"][idx].astype(np.float64))
+    assert rel_l2(got[idx], ref) < 1e-5
+    assert rel_max(got[idx], ref) < 1e-5
+
+
+def _oracle_rho_at(p, pos, mass, cells):
+    """rho at grid cells (z, y, x) from the particles whose ball covers them;
+    the particles are pre-sorted by the z index of their central pixel so each
+    cell scans only the slab of particles within the ball's z extent."""
+    x = pos / p.s
+    c = np.floor(x + 0.5).astype(np.int64) + p.n_pad // 2
+    order = np.argsort(c[:, 2], kind="stable")
+    cz_sorted = c[order, 2]
+    reach = int(np.ceil(p.cutoff * p.sigma))
+    R2 = (p.cutoff * p.sigma) ** 2
+    out = np.zeros(len(cells))
+    for t, (gz, gy, gx) in enumerate(cells):
+        lo, hi = np.searchsorted(cz_sorted, [gz - reach, gz + reach + 1])
+        cand = order[lo:hi]
+        d = np.stack([gx - c[cand, 0], gy - c[cand, 1], gz - c[cand, 2]], axis=1)
+        sel = cand[(d * d).sum(1) < R2]
+        if len(sel) == 0:
+            continue
+        idx, w = orc.kernel_weights(p, pos[sel])
+        hit = (idx[..., 0] == gx) & (idx[..., 1] == gy) & (idx[..., 2] == gz)
+        out[t] = (mass[sel][:, None] * w * hit).sum() / p.s ** 3
+    return out
+
+
+@pytest.mark.timeout(600)
+def test_deposit_1024_sampled(M, mix):
+    _log("deposit 1024 sampled, 2^24 particles")
+    p = mix["params"]
+    n = len(mix["mass"])
+    ctx = M.pm_create(p, n)
+    rho = torch.zeros(N ** 3, dtype=torch.float32, device="cuda")
+    M.pm_deposit(ctx, _dev(mix["pos"]), _dev(mix["mass"]), rho)
+    total = float(rho.sum(dtype=torch.float64).item())
+    # 64 cells of the densest region, 64 random cells of the physical region,
+    # 16 random cells of the margin
+    top = torch.topk(rho, 4000).indices.cpu().numpy()
+    rng = np.random.default_rng(9)
+    dense = np.array(np.unravel_index(rng.choice(top, 64, replace=False), (N, N, N))).T
+    inner = rng.integers(H - 256, H + 256, (64, 3))
+    outer = rng.integers(0, N, (16, 3))
+    cells = np.concatenate([dense, inner, outer])
+    flat = torch.from_numpy((cells[:, 0] * N + cells[:, 1]) * N + cells[:, 2]).cuda()
+    val = rho[flat].double().cpu().numpy()
+    scale = float(rho.max().item())
+    ctx.close()
+    del rho
+    assert abs(total - mix["mass"].astype(np.float64).sum()) < 1e-5 * mix["mass"].sum()
+    ref = _oracle_rho_at(oparams(p), mix["pos"].astype(np.float64), mix["mass"].astype(np.float64), cells)
+    assert np.max(np.abs(val - ref)) < 1e-6 * scale
+
+
+@pytest.mark.timeout(300)
+def test_step_1024_runs_in_region(M, mix):
+    _log("pm_step 1024, 2^24 particles")
+    p = mix["params"]
+    n = len(mix["mass"])
+    ctx = M.pm_create(p, n)
+    pos, vel, mass = _dev(mix["pos"]), _dev(mix["vel"]), _dev(mix["mass"])
+    info = M.pm_step(ctx, pos, vel, mass, float(mix["dt"]), want_info=True)
+    assert info["iterations"] == p["iters"] and info["bounds_flag"] == 0
+    dv = (vel.double() - _dev(mix["vel"]).double()).abs().max().item()
+    assert np.isfinite(dv) and dv > 0.0
+    ctx.close()

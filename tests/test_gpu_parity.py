@@ -319,6 +319,8 @@ STEP_CASES = [
     ("cloud_deep", lambda: W.random_cloud(32, 32, 400, mu=1, radius_frac=0.2)),
     ("two_body", lambda: W.two_body()),
     ("iso_small", lambda: W.isothermal_sphere(seed=1, N=4096, n=32, b=3.0, r_max=11.0)),
+    # the Plummer-mixture precision workload scaled down: 64^3 grid, radii / 8, 2^15 particles
+    ("plummer_mix_64", lambda: W.plummer_mixture(seed=0, N=1 << 15, n=64, a_range=(1.0, 4.0))),
 ]
 
 
