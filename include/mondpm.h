@@ -207,6 +207,22 @@ pm_status pm_read_timing(pm_ctx* ctx, double* total_ms, int64_t* launches);
  * [n_pad^3]; they may not overlap.  Used to form the learned start's input. */
 pm_status pm_newton_potential(pm_ctx* ctx, const float* rho, float* phiN);
 
+/* External field (Sect. 5): a uniform Newtonian field (gx, gy, gz) added
+ * to every later Newton solve on the context (aqual_solve, pm_step,
+ * pm_newton_potential and the learned start's input), made as the paper
+ * suggests by a permanent dipole sheet on the planes farthest from the
+ * matter.  For each axis, the cell plane n_pad - 1 gets +rho_c and the cell
+ * plane 0 gets -rho_c in every cell, with rho_c = g L / (4 pi G s^2),
+ * L = n_pad s.  On the periodic box this gives the bulk the Newtonian field
+ * g along that axis, up to a lattice ripple from the sharp sheets that decays
+ * with the distance from them (below 1e-4 of g at 16 cells, less further in).
+ * The MOND solve then acts on g_N including this field, which gives the
+ * external-field effect.  The sheets' own cells carry large fields; matter
+ * must stay away from them (the physical region already does).  (0, 0, 0)
+ * removes the field.  PM_E_INVAL for non-finite values.  Host only, no
+ * synchronisation; a captured pm_step graph keeps the value at capture. */
+pm_status pm_set_external_field(pm_ctx* ctx, double gx, double gy, double gz);
+
 /* Apparent density of Eq. apparentdensity, rho_A = -div(g)/(4 pi G) with
  * g = -grad phi, in the discretisation of the solve's projections
  * (g_M_hat = -i kt phi_hat): rho_A_hat = -|kt|^2 phi_hat / (4 pi G).  From the

@@ -347,6 +347,35 @@ def aqual_solve(p: Params, rho: np.ndarray, H0: np.ndarray | None = None,
     return phi, info
 
 
+def external_field_density(p: Params, g_ext) -> np.ndarray:
+    """Density of the external-field sheets (Sect. 5: a permanent dipolar mass
+    layer on the plane farthest from the particles, a pixel layer of mass M
+    beside one of mass -M).
+
+    Reading: one sheet pair per axis d, +rho_d in every cell of plane
+    n_pad - 1 and -rho_d in every cell of plane 0 (the two planes straddle the
+    periodic boundary, the farthest from matter at the centre), with
+    rho_d = g_d L / (4 pi G s^2), L = n_pad s.  The Newton field of a periodic
+    sheet pair has zero mean over the period and jumps by 4 pi G rho_d s
+    across the pair, so in the bulk it is uniform, g_d, pointing from the
+    positive to the negative sheet.
+    """
+    N = p.n_pad
+    L = N * p.s
+    out = np.zeros((N, N, N))
+    for d, axis in ((0, 2), (1, 1), (2, 0)):          # x, y, z components; arrays are [z][y][x]
+        rd = float(g_ext[d]) * L / (4.0 * math.pi * p.G * p.s * p.s)
+        if rd == 0.0:
+            continue
+        hi = [slice(None)] * 3
+        lo = [slice(None)] * 3
+        hi[axis] = N - 1
+        lo[axis] = 0
+        out[tuple(hi)] += rd
+        out[tuple(lo)] -= rd
+    return out
+
+
 def qumond_potential(p: Params, rho: np.ndarray) -> np.ndarray:
     """Potential of quasi-linear MOND (Sect. 2, the equivalent system for
     QuMOND): g_M + H = nu(|g_N|/a0) g_N with g_M curl-free and H divergence
@@ -401,14 +430,18 @@ def interp_push(p: Params, phi, pos, vel, dt_kick: float, dt_drift: float):
     return pos, vel
 
 
-def pm_step(p: Params, pos, vel, mass, dt: float, H0=None):
+def pm_step(p: Params, pos, vel, mass, dt: float, H0=None, g_ext=None):
     """One PM step: deposit(r) -> solve -> kick(dt) -> drift(dt).
 
     Reading: positions and velocities are half a step apart (Sect. 3); one step
     evaluates the force at the current positions, kicks by dt and drifts by dt,
-    which is the alternation of the flow scheme with one fixed phase.
+    which is the alternation of the flow scheme with one fixed phase.  g_ext:
+    optional uniform external Newtonian field, added as the sheets of
+    external_field_density.
     """
     rho = deposit(p, pos, mass)
+    if g_ext is not None:
+        rho = rho + external_field_density(p, g_ext)
     phi, info = aqual_solve(p, rho, H0)
     pos, vel = interp_push(p, phi, pos, vel, dt, dt)
     return pos, vel, info

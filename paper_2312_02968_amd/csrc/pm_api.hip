@@ -57,6 +57,7 @@ struct pm_ctx {
   SortBufs sb{};
   int npartials = 0;
   hipGraphExec_t step_graph = nullptr;  // one captured pm_step (pm_step_capture)
+  Dipole dip{};               // external-field sheets added to every Newton solve's density
   // event timing
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -351,6 +352,7 @@ static pm_status run_solve(pm_ctx* c, const float* rho, const float* H0, float* 
   {
     PassDesc d = pdesc(PASS_X_FWD_REAL, c->phiN);
     d.real = const_cast<float*>(rho);
+    d.dip = c->dip;
     HIPCHK(pass(c, d));
     HIPCHK(pass(c, pdesc(PASS_Y_FWD, c->phiN, 1)));
   }
@@ -644,6 +646,7 @@ pm_status pm_newton_potential(pm_ctx* c, const float* rho, float* phiN) {
   if (!rho || !phiN) return inval("rho and phiN are required");
   PassDesc d = pdesc(PASS_X_FWD_REAL, c->spec);
   d.real = const_cast<float*>(rho);
+  d.dip = c->dip;
   HIPCHK(pass(c, d));
   HIPCHK(pass(c, pdesc(PASS_Y_FWD, c->spec, 1)));
   PassDesc z = pdesc(PASS_Z_POISSON, c->spec);
@@ -653,6 +656,21 @@ pm_status pm_newton_potential(pm_ctx* c, const float* rho, float* phiN) {
   PassDesc x = pdesc(PASS_X_INV_REAL, c->spec);
   x.real = phiN;
   HIPCHK(pass(c, x));
+  return PM_OK;
+}
+
+pm_status pm_set_external_field(pm_ctx* c, double gx, double gy, double gz) {
+  if (!c) return inval("ctx is NULL");
+  if (!isfinite(gx) || !isfinite(gy) || !isfinite(gz)) return inval("external field must be finite");
+  // A sheet pair of +-rho_c per cell on adjacent planes gives the periodic box
+  // a uniform Newtonian field 4 pi G rho_c s^2 / L in its bulk (the field has
+  // zero mean over the period, and the sheets carry a potential jump of
+  // 4 pi G rho_c s^2), pointing from the +rho_c plane to the -rho_c plane.
+  const double s = c->p.box / c->p.n, L = c->N * s;
+  const double k = L / (4.0 * M_PI * c->p.G * s * s);
+  c->dip.x = (float)(gx * k);
+  c->dip.y = (float)(gy * k);
+  c->dip.z = (float)(gz * k);
   return PM_OK;
 }
 

@@ -96,6 +96,17 @@ __device__ __forceinline__ void c2r_merge(float2* buf, int IS, const float2* __r
   __syncthreads();
 }
 
+// The external-field sheets at grid points (2m, 2m + 1) of row `row`
+// (row = z * N + y) of an N^3 density.
+__device__ __forceinline__ void add_dipole(float2& x, const Dipole& dip, long long row, int m, int N) {
+  if (dip.x == 0.f && dip.y == 0.f && dip.z == 0.f) return;
+  const int y = (int)(row % N), z = (int)(row / N);
+  const float a = (y == N - 1 ? dip.y : 0.f) - (y == 0 ? dip.y : 0.f) + (z == N - 1 ? dip.z : 0.f) -
+                  (z == 0 ? dip.z : 0.f);
+  x.x += a - (m == 0 ? dip.x : 0.f);
+  x.y += a + (2 * m + 1 == N - 1 ? dip.x : 0.f);
+}
+
 // One block: ROWS rows of NC components.  Sequence q = c * ROWS + r.
 //   X_FWD_REAL : real rows (float, row pitch 2H) -> spectrum rows
 //   X_INV_REAL : spectrum rows -> real rows
@@ -107,7 +118,7 @@ template <int H, int ROWS, int NC, int NT, int XMODE>
 __global__ __launch_bounds__(NT) void k_xpass(float2* spec, long long comp_stride, int P,
                                               float* real, long long real_comp_stride,
                                               const float2* __restrict__ tw, int mu_mode, float inv_a0,
-                                              float* fprev, double* partials) {
+                                              float* fprev, double* partials, Dipole dip) {
   constexpr int S = NC * ROWS;
   constexpr int IS = S + 1;
   extern __shared__ float2 lds[];
@@ -122,7 +133,9 @@ __global__ __launch_bounds__(NT) void k_xpass(float2* spec, long long comp_strid
       const int q = b / H, m = b % H;
       const int c = q / ROWS, r = q % ROWS;
       const float2* src = reinterpret_cast<const float2*>(real + c * real_comp_stride + (long long)(row0 + r) * N);
-      lds[m * IS + q] = src[m];
+      float2 x = src[m];
+      if (NC == 1) add_dipole(x, dip, row0 + r, m, N);
+      lds[m * IS + q] = x;
     }
   } else {
     for (int b = threadIdx.x; b < S * H; b += NT) {
@@ -312,7 +325,8 @@ struct XWave {
 template <int H, int XMODE, int NC>
 __global__ __launch_bounds__(256) void k_xpass_wave(float2* spec, long long comp_stride, int P, float* real,
                                                     long long real_comp_stride, const float2* __restrict__ tw,
-                                                    int mu_mode, float inv_a0, float* fprev, double* partials) {
+                                                    int mu_mode, float inv_a0, float* fprev, double* partials,
+                                                    Dipole dip) {
   using X = XWave<H>;
   constexpr int N = X::N, LANES = X::LANES, RG = X::RG;
   extern __shared__ float2 lds[];
@@ -333,6 +347,10 @@ __global__ __launch_bounds__(256) void k_xpass_wave(float2* spec, long long comp
       const float2* src = reinterpret_cast<const float2*>(real + c * real_comp_stride + row * N);
 #pragma unroll
       for (int r = 0; r < RG; ++r) v[c][r] = src[j + LANES * r];
+    }
+    if constexpr (NC == 1) {
+#pragma unroll
+      for (int r = 0; r < RG; ++r) add_dipole(v[0][r], dip, row, j + LANES * r, N);
     }
   } else {
 #pragma unroll
@@ -774,19 +792,19 @@ struct Cfg {
 
 template <int N, int XMODE, int NC>
 hipError_t launch_x(const FftGeom& g, float2* spec, float* real, long long real_cs, int mu_mode,
-                    float inv_a0, float* fprev, double* partials, hipStream_t st) {
+                    float inv_a0, float* fprev, double* partials, hipStream_t st, Dipole dip = Dipole{}) {
   using C = Cfg<N>;
   if constexpr (N == 512 || N == 1024) {
     using X = XWave<N / 2>;
     const size_t sh = sizeof(float2) * (N + (size_t)X::ROWS * X::XB);
     hipLaunchKernelGGL((k_xpass_wave<N / 2, XMODE, NC>), dim3(N * N / X::ROWS), dim3(256), sh, st, spec,
-                       g.comp_stride, g.P, real, real_cs, g.tw, mu_mode, inv_a0, fprev, partials);
+                       g.comp_stride, g.P, real, real_cs, g.tw, mu_mode, inv_a0, fprev, partials, dip);
     return hipGetLastError();
   } else {
     const int blocks = N * N / C::ROWS;
     const size_t sh = sizeof(float2) * ((size_t)(C::H + 1) * (NC * C::ROWS + 1) + N);
     hipLaunchKernelGGL((k_xpass<C::H, C::ROWS, NC, kNT, XMODE>), dim3(blocks), dim3(kNT), sh, st, spec,
-                       g.comp_stride, g.P, real, real_cs, g.tw, mu_mode, inv_a0, fprev, partials);
+                       g.comp_stride, g.P, real, real_cs, g.tw, mu_mode, inv_a0, fprev, partials, dip);
     return hipGetLastError();
   }
 }
@@ -816,7 +834,7 @@ template <int N>
 hipError_t run_pass(const FftGeom& g, const PassDesc& d, hipStream_t st) {
   switch (d.kind) {
     case PASS_X_FWD_REAL:
-      return launch_x<N, X_FWD_REAL, 1>(g, d.spec, d.real, d.real_cs, 0, 0.f, nullptr, nullptr, st);
+      return launch_x<N, X_FWD_REAL, 1>(g, d.spec, d.real, d.real_cs, 0, 0.f, nullptr, nullptr, st, d.dip);
     case PASS_X_FWD_REAL3:
       return launch_x<N, X_FWD_REAL, 3>(g, d.spec, d.real, d.real_cs, 0, 0.f, nullptr, nullptr, st);
     case PASS_X_INV_REAL:

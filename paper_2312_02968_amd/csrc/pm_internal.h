@@ -35,8 +35,17 @@ enum PassKind {
   PASS_Z_FWD, PASS_Z_INV, PASS_Z_NEWTON, PASS_Z_CURL, PASS_Z_CURL_FINAL, PASS_Z_DIV, PASS_Z_POISSON, PASS_Z_APPARENT
 };
 
+// Density of the external-field sheets per axis (Sect. 5: a pixel layer of
+// mass +M on the plane farthest from the matter and an adjacent layer of
+// mass -M): +d on cell plane n_pad - 1 and -d on cell plane 0 of that axis,
+// added to the density as the forward real x pass loads it.
+struct Dipole {
+  float x = 0.f, y = 0.f, z = 0.f;
+};
+
 struct PassDesc {
   PassKind kind;
+  Dipole dip{};          // PASS_X_FWD_REAL only
   float2* spec = nullptr;
   float* real = nullptr;
   long long real_cs = 0;

@@ -77,6 +77,7 @@ def lib():
         I32, F32 = ctypes.c_int32, ctypes.c_float
         L.pm_newton_potential.argtypes = [VP, VP, VP]
         L.pm_apparent_density.argtypes = [VP, VP, VP]
+        L.pm_set_external_field.argtypes = [VP, D, D, D]
         L.aqual_solve_field.argtypes = [VP, VP, VP, VP, VP, P(PmSolveInfo)]
         L.pm_net_param_count.argtypes = []
         L.pm_net_param_count.restype = I64
@@ -100,7 +101,7 @@ def lib():
         L.pm_net_forward.argtypes = [VP, VP, VP, VP]
         for f in ("pm_create", "pm_destroy", "pm_deposit", "aqual_solve", "smooth_accel", "interp_push",
                   "pm_step", "pm_step_capture", "pm_step_replay", "pm_diagnostics", "pm_fft_r2c", "pm_fft_c2r", "pm_set_timing",
-                  "pm_read_timing", "pm_newton_potential", "pm_apparent_density", "aqual_solve_field", "pm_net_create",
+                  "pm_read_timing", "pm_newton_potential", "pm_apparent_density", "pm_set_external_field", "aqual_solve_field", "pm_net_create",
                   "pm_net_destroy", "pm_net_set_params", "pm_net_get_params", "pm_net_get_grads",
                   "pm_net_input", "pm_net_target", "pm_net_set_input", "pm_net_get_input",
                   "pm_net_set_target", "pm_net_get_target", "pm_net_run", "pm_net_output", "pm_net_get_rms",
@@ -292,6 +293,12 @@ def pm_apparent_density(ctx: Ctx, phi, rho_a):
     _check(lib().pm_apparent_density(ctx.handle, _ptr(phi, numel=R, name="phi"), _ptr(rho_a, numel=R, name="rho_a")),
            "pm_apparent_density")
     return rho_a
+
+
+def pm_set_external_field(ctx: Ctx, g):
+    """Uniform external Newtonian field g = (gx, gy, gz) for later solves on ctx."""
+    gx, gy, gz = (float(v) for v in g)
+    _check(lib().pm_set_external_field(ctx.handle, gx, gy, gz), "pm_set_external_field")
 
 
 def aqual_solve_field(ctx: Ctx, rho, phi, F, H0=None, want_info=True):

@@ -89,6 +89,23 @@ def test_solve_512(M, iso, rho_sub, K):
     ctx.close()
 
 
+@pytest.mark.timeout(600)
+def test_solve_512_external_field(M, iso, rho_sub):
+    _log("solve 512 with an external field, K = 1")
+    p = dict(iso["params"], iters=1)
+    g = (0.0, 0.0, 0.5 * p["a0"])
+    op = oparams(p)
+    phi_ref, _ = orc.aqual_solve(op, rho_sub.astype(np.float64) + orc.external_field_density(op, g))
+    ctx = M.pm_create(p, 0)
+    M.pm_set_external_field(ctx, g)
+    phi = grid(N)
+    M.aqual_solve(ctx, dev(rho_sub), phi)
+    got = host(phi).reshape(N, N, N)
+    assert rel_l2(got, phi_ref) < 1e-5
+    assert rel_max(got, phi_ref) < 1e-5
+    ctx.close()
+
+
 def _oracle_rho_at(p, pos, mass, cells):
     """rho at the given grid cells (z, y, x) from the particles whose ball covers them."""
     out = np.zeros(len(cells))

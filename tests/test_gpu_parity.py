@@ -226,6 +226,57 @@ def test_qumond(M, mu):
     ctx.close()
 
 
+@pytest.mark.parametrize("n,g_a0", [(16, (0.0, 0.0, 0.8)), (32, (0.5, -0.3, 0.2))])
+def test_external_field_solve(M, n, g_a0):
+    # the Newton solve's density includes the external-field sheets; the
+    # field is given in units of a0
+    _log("external field solve", n, g_a0)
+    w = W.random_cloud(41, n, 80, mu=0, radius_frac=0.2)
+    p = w["params"]
+    g = tuple(v * p["a0"] for v in g_a0)
+    op = oparams(p)
+    N = p["n_pad"]
+    rho = orc.deposit(op, w["pos"].astype(np.float64), w["mass"].astype(np.float64)).astype(np.float32)
+    ref, _ = orc.aqual_solve(op, rho.astype(np.float64) + orc.external_field_density(op, g))
+    plain, _ = orc.aqual_solve(op, rho.astype(np.float64))
+    ctx = M.pm_create(p, 0)
+    M.pm_set_external_field(ctx, g)
+    phi = grid(N)
+    M.aqual_solve(ctx, dev(rho), phi)
+    got = host(phi).reshape(N, N, N)
+    assert rel_l2(got, ref) < 1e-5
+    assert rel_max(got, ref) < 1e-5
+    assert rel_l2(plain, ref) > 1e-2                    # the field made a difference
+    M.pm_set_external_field(ctx, (0.0, 0.0, 0.0))
+    M.aqual_solve(ctx, dev(rho), phi)
+    assert rel_l2(host(phi).reshape(N, N, N), plain) < 1e-5
+    with pytest.raises(M.PmError):
+        M.pm_set_external_field(ctx, (float("nan"), 0.0, 0.0))
+    ctx.close()
+
+
+def test_external_field_step(M):
+    _log("external field step")
+    w = W.random_cloud(42, 32, 300, mu=0, radius_frac=0.2)
+    p = w["params"]
+    g = (0.0, 0.4 * p["a0"], -0.3 * p["a0"])
+    dt = float(w["dt"])
+    ctx = M.pm_create(p, len(w["mass"]))
+    M.pm_set_external_field(ctx, g)
+    pos, vel, mass = dev(w["pos"]), dev(w["vel"]), dev(w["mass"])
+    M.pm_step(ctx, pos, vel, mass, dt)
+    pr, vr, _ = orc.pm_step(oparams(p), w["pos"].astype(np.float64), w["vel"].astype(np.float64),
+                            w["mass"].astype(np.float64), dt, g_ext=g)
+    g_ref = (vr - w["vel"]) / dt
+    got = (host(vel).reshape(-1, 3) - w["vel"]) / dt
+    assert rel_l2(got, g_ref) < 1e-5
+    assert rel_max(got, g_ref) < 1e-5
+    _, v0, _ = orc.pm_step(oparams(p), w["pos"].astype(np.float64), w["vel"].astype(np.float64),
+                           w["mass"].astype(np.float64), dt)
+    assert rel_l2((v0 - w["vel"]) / dt, g_ref) > 1e-2        # the field changed the forces
+    ctx.close()
+
+
 @pytest.mark.parametrize("mu", [0, 1])
 def test_apparent_density(M, mu):
     # Eq. apparentdensity on the oracle's potential (the same FP32 values on
