@@ -92,24 +92,48 @@ __device__ __forceinline__ Part particle_setup(const KernelGeom& kg, const int* 
   return particle_setup(kg, ball_lds, pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], lane);
 }
 
+// Tile key of each particle and its rank among the particles of its tile.
+// The ranks come from device-scope atomic counters, which clustered matter
+// turns into long queues on a few addresses, so a wave first groups its lanes
+// by key: one lane per distinct key adds the group size, and each lane takes
+// the base plus the number of lower lanes in its group (any order within a
+// tile is a valid rank order).
 __global__ __launch_bounds__(256) void k_keys(const float* __restrict__ pos, int64_t n, int N, int nphys,
                                               double inv_s, int ext, int* keys, int* rank, int* counts,
                                               int* flags) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  const bool valid = i < n;
+  const int lane = threadIdx.x & 63;
   const int half = N / 2;
-  int c[3];
+  int key = -1;
   bool out = false;
-  for (int a = 0; a < 3; ++a) {
-    const int ci = (int)floor((double)pos[3 * i + a] * inv_s + 0.5) + half;
-    out |= (ci - ext < half - nphys / 2) || (ci + ext > half + nphys / 2 - 1);
-    c[a] = wrapi(ci, N);
+  if (valid) {
+    int c[3];
+    for (int a = 0; a < 3; ++a) {
+      const int ci = (int)floor((double)pos[3 * i + a] * inv_s + 0.5) + half;
+      out |= (ci - ext < half - nphys / 2) || (ci + ext > half + nphys / 2 - 1);
+      c[a] = wrapi(ci, N);
+    }
+    const int nt = N / kTile;
+    key = ((c[2] / kTile) * nt + c[1] / kTile) * nt + c[0] / kTile;
+    keys[i] = key;
   }
-  const int nt = N / kTile;
-  const int key = ((c[2] / kTile) * nt + c[1] / kTile) * nt + c[0] / kTile;
-  keys[i] = key;
-  rank[i] = atomicAdd(&counts[key], 1);
-  if (out) atomicAdd(&flags[0], 1);
+  const unsigned long long below = (1ull << lane) - 1ull;
+  unsigned long long todo = __ballot(valid);
+  int my_rank = 0;
+  while (todo) {
+    const int leader = __ffsll((long long)todo) - 1;
+    const int lk = __shfl(key, leader, 64);
+    const unsigned long long grp = __ballot(valid && key == lk);
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&counts[lk], __popcll(grp));
+    base = __shfl(base, leader, 64);
+    if (valid && key == lk) my_rank = base + __popcll(grp & below);
+    todo &= ~grp;
+  }
+  if (valid) rank[i] = my_rank;
+  const unsigned long long outs = __ballot(valid && out);
+  if (outs && lane == __ffsll((long long)outs) - 1) atomicAdd(&flags[0], __popcll(outs));
 }
 
 // Exclusive scan of counts[0..n) into offsets[0..n]; blocks of 1024 entries.
