@@ -179,10 +179,12 @@ pm_status pm_diagnostics(pm_ctx* ctx, const float* pos, const float* vel, const 
                          int64_t N, const float* phi, double* out);
 
 /* 3D real transforms of the FFT box used inside aqual_solve, exposed for
- * testing.  Spectrum layout: complex (float2) [n_pad][n_pad][pitch] indexed
- * [kz][ky][kx] with kx = 0..n_pad/2 valid and pitch = pm_spectrum_pitch(n_pad)
- * complex entries per row.  Unnormalised in both directions: c2r(r2c(f)) =
- * n_pad^3 f.  in and out must not overlap. */
+ * testing.  Spectrum layout: kx = 0..n_pad/2 valid, in groups of 16:
+ * complex (float2) [pitch / 16][n_pad][n_pad][16] indexed
+ * [kx / 16][kz][ky][kx % 16], pitch = pm_spectrum_pitch(n_pad) =
+ * 16 * ceil((n_pad/2 + 1) / 16) kx slots (n_pad^2 * pitch complex values).
+ * Unnormalised in both directions: c2r(r2c(f)) = n_pad^3 f.  in and out
+ * must not overlap. */
 int32_t   pm_spectrum_pitch(int32_t n_pad);
 pm_status pm_fft_r2c(pm_ctx* ctx, const float* in, void* spectrum_out);
 pm_status pm_fft_c2r(pm_ctx* ctx, const void* spectrum_in, float* out);

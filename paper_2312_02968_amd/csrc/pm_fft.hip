@@ -2,9 +2,13 @@
 // of the fixed-point iteration fused into them.
 //
 // Data layout.  A real grid is float [N][N][N] ([z][y][x], x fastest).  A
-// spectrum is float2 [N][N][P] ([z or kz][y or ky][kx]) with kx = 0..N/2
-// valid (the half spectrum of a real transform along x) and P complex per
-// row.  Three-component fields are three such spectra, comp_stride apart.
+// spectrum holds kx = 0..N/2 (the half spectrum of a real transform along x)
+// in groups of 16: float2 [P / 16][N][N][16] ([kx / 16][z or kz][y or ky]
+// [kx % 16]), P = 16 * ceil((N/2 + 1) / 16).  A y-pass block (one group, one
+// kz) then reads one contiguous N * 128-byte run, an x-pass block (16
+// consecutive rows) 2 KB runs, and a z-pass block (half a group, one ky)
+// 64-byte pieces N * 128 bytes apart.  Three-component fields are three such
+// spectra, comp_stride apart.
 //
 // A 3D transform is three passes, one per axis.  The x pass works on whole
 // rows and does the real<->complex step as a half-length complex FFT plus the
@@ -22,7 +26,7 @@
 // Tile widths (kx columns per block) of the y and z passes and the z pass's
 // block size; compile-time launch shapes, chosen by measurement.
 #ifndef PM_TY
-#define PM_TY 8
+#define PM_TY 16
 #endif
 #ifndef PM_TZ
 #define PM_TZ 8
@@ -37,6 +41,12 @@
 namespace pm {
 
 int z_blocks(int N);
+
+// Offset of element k of spectrum row `row` (row = kz * N + ky) in the
+// grouped layout; NN = N * N.
+__device__ __forceinline__ long long sidx(long long row, int k, long long NN) {
+  return ((long long)(k >> 4) * NN + row) * 16 + (k & 15);
+}
 
 // ----------------------------------------------------------------------------
 // x pass
@@ -115,7 +125,7 @@ __device__ __forceinline__ void add_dipole(float2& x, const Dipole& dip, long lo
 //                the squared change of F against fprev is accumulated in FP64
 //                into partials[blockIdx.x] and F is stored to fprev.
 template <int H, int ROWS, int NC, int NT, int XMODE>
-__global__ __launch_bounds__(NT) void k_xpass(float2* spec, long long comp_stride, int P,
+__global__ __launch_bounds__(NT) void k_xpass(float2* spec, long long comp_stride,
                                               float* real, long long real_comp_stride,
                                               const float2* __restrict__ tw, int mu_mode, float inv_a0,
                                               float* fprev, double* partials, Dipole dip) {
@@ -124,6 +134,7 @@ __global__ __launch_bounds__(NT) void k_xpass(float2* spec, long long comp_strid
   extern __shared__ float2 lds[];
   const int row0 = blockIdx.x * ROWS;
   const int N = 2 * H;
+  const long long NN = (long long)N * N;
   float2* tw_s = lds + (H + 1) * IS;
   for (int t = threadIdx.x; t < N; t += NT) tw_s[t] = tw[t];
 
@@ -141,11 +152,11 @@ __global__ __launch_bounds__(NT) void k_xpass(float2* spec, long long comp_strid
     for (int b = threadIdx.x; b < S * H; b += NT) {
       const int q = b / H, k = b % H;
       const int c = q / ROWS, r = q % ROWS;
-      lds[k * IS + q] = spec[c * comp_stride + (long long)(row0 + r) * P + k];
+      lds[k * IS + q] = spec[c * comp_stride + sidx(row0 + r, k, NN)];
     }
     for (int q = threadIdx.x; q < S; q += NT) {
       const int c = q / ROWS, r = q % ROWS;
-      lds[H * IS + q] = spec[c * comp_stride + (long long)(row0 + r) * P + H];
+      lds[H * IS + q] = spec[c * comp_stride + sidx(row0 + r, H, NN)];
     }
   }
   __syncthreads();
@@ -208,11 +219,11 @@ __global__ __launch_bounds__(NT) void k_xpass(float2* spec, long long comp_strid
     for (int b = threadIdx.x; b < S * H; b += NT) {
       const int q = b / H, k = b % H;
       const int c = q / ROWS, r = q % ROWS;
-      spec[c * comp_stride + (long long)(row0 + r) * P + k] = lds[k * IS + q];
+      spec[c * comp_stride + sidx(row0 + r, k, NN)] = lds[k * IS + q];
     }
     for (int q = threadIdx.x; q < S; q += NT) {
       const int c = q / ROWS, r = q % ROWS;
-      spec[c * comp_stride + (long long)(row0 + r) * P + H] = lds[H * IS + q];
+      spec[c * comp_stride + sidx(row0 + r, H, NN)] = lds[H * IS + q];
     }
   } else {
     for (int b = threadIdx.x; b < S * H; b += NT) {
@@ -323,12 +334,13 @@ struct XWave {
 };
 
 template <int H, int XMODE, int NC>
-__global__ __launch_bounds__(256) void k_xpass_wave(float2* spec, long long comp_stride, int P, float* real,
+__global__ __launch_bounds__(256) void k_xpass_wave(float2* spec, long long comp_stride, float* real,
                                                     long long real_comp_stride, const float2* __restrict__ tw,
                                                     int mu_mode, float inv_a0, float* fprev, double* partials,
                                                     Dipole dip) {
   using X = XWave<H>;
   constexpr int N = X::N, LANES = X::LANES, RG = X::RG;
+  constexpr long long NN = (long long)N * N;
   extern __shared__ float2 lds[];
   float2* tw_s = lds;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -355,11 +367,11 @@ __global__ __launch_bounds__(256) void k_xpass_wave(float2* spec, long long comp
   } else {
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      const float2* src = spec + c * comp_stride + row * P;
+      const float2* src = spec + c * comp_stride;
       float2 x[RG];
 #pragma unroll
-      for (int r = 0; r < RG; ++r) x[r] = src[j + LANES * r];
-      const float2 nyq = src[H];
+      for (int r = 0; r < RG; ++r) x[r] = src[sidx(row, j + LANES * r, NN)];
+      const float2 nyq = src[sidx(row, H, NN)];
       // merge: Z[k] = (Xk + conj Xm) + i (Xk - conj Xm) conj(W^k), Xm = X[H - k]
 #pragma unroll
       for (int r = 0; r < RG; ++r) {
@@ -421,7 +433,7 @@ __global__ __launch_bounds__(256) void k_xpass_wave(float2* spec, long long comp
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     X::template fft<false>(v[c], xb, j, tw_s);
-    float2* dst = spec + c * comp_stride + row * P;
+    float2* dst = spec + c * comp_stride;
     // split: X[k] = E + W^k O, E = (Zk + conj Zm)/2, O = -i (Zk - conj Zm)/2
 #pragma unroll
     for (int r = 0; r < RG; ++r) {
@@ -434,10 +446,10 @@ __global__ __launch_bounds__(256) void k_xpass_wave(float2* spec, long long comp
       const float2 e = cscale(cadd(zk, cconj(zm)), 0.5f);
       const float2 o = cscale(mul_mi<false>(csub(zk, cconj(zm))), 0.5f);
       if (k == 0) {
-        dst[0] = make_float2(zk.x + zk.y, 0.0f);
-        dst[H] = make_float2(zk.x - zk.y, 0.0f);
+        dst[sidx(row, 0, NN)] = make_float2(zk.x + zk.y, 0.0f);
+        dst[sidx(row, H, NN)] = make_float2(zk.x - zk.y, 0.0f);
       } else {
-        dst[k] = cadd(e, cmul(tw_s[k], o));
+        dst[sidx(row, k, NN)] = cadd(e, cmul(tw_s[k], o));
       }
     }
   }
@@ -493,27 +505,35 @@ __device__ __forceinline__ void store_cols(const float2* v, int E, float2* const
   }
 }
 
-// y pass: a tile of 2 T columns of one z plane, handled as two halves of T
-// columns that share the LDS exchange buffer (the halves of one 128-byte line
-// are loaded and stored together, the buffer holds only T columns).
+// y pass: one group of 16 kx columns of one z plane (a contiguous run of L
+// rows of 16 complex values), handled as 16 / T sets of T columns that share
+// the LDS exchange buffer (the buffer holds only T columns).  With T = 16 a
+// load instruction covers whole 128-byte rows of consecutive ky.
 template <int L, int T, int NT, bool INV>
-__global__ __launch_bounds__(NT) void k_ypass(float2* spec, long long comp_stride, int P, int ncols,
+__global__ __launch_bounds__(NT) void k_ypass(float2* spec, long long comp_stride, int ncols,
                                               const float2* __restrict__ tw) {
+  static_assert(16 % T == 0, "a y-pass block owns one group of 16 kx columns");
+  constexpr int NH = 16 / T;
   constexpr int E = ColCfg<L, T, NT>::E;
   extern __shared__ float2 lds[];
   float2* tw_s = lds + ColBuf<L, T>::elems;
-  const int x0 = blockIdx.x * 2 * T;
-  float2* base = spec + blockIdx.z * comp_stride + (long long)blockIdx.y * L * P + x0;
+  const int x0 = blockIdx.x * 16;
+  float2* base = spec + blockIdx.z * comp_stride + ((long long)blockIdx.x * L + blockIdx.y) * L * 16;
   load_twiddles<L>(tw_s, tw, NT);
-  float2 v[2 * E];
+  float2 v[NH * E];
   using First = PlanAt<L, false, 0>;
   using Last = PlanAt<L, false, Plan<L>::S - 1>;
-  const int nv[2] = {min(T, ncols - x0), min(T, ncols - x0 - T)};
-  float2* ptr[2] = {base, base + T};
-  load_cols<L, T, NT, First::R, 2>(v, E, ptr, nv, P);
+  int nv[NH];
+  float2* ptr[NH];
+#pragma unroll
+  for (int h = 0; h < NH; ++h) {
+    nv[h] = min(T, ncols - x0 - h * T);
+    ptr[h] = base + h * T;
+  }
+  load_cols<L, T, NT, First::R, NH>(v, E, ptr, nv, 16);
   __syncthreads();
-  col_fft<L, T, NT, 2, INV, false>(v, lds, tw_s, 1);
-  store_cols<L, T, NT, Last::R, 2>(v, E, ptr, nv, P);
+  col_fft<L, T, NT, NH, INV, false>(v, lds, tw_s, 1);
+  store_cols<L, T, NT, Last::R, NH>(v, E, ptr, nv, 16);
 }
 
 enum { Z_FWD = 0, Z_INV = 1, Z_NEWTON = 2, Z_CURL = 3, Z_CURL_FINAL = 4, Z_DIV = 5, Z_NEWTON_H0 = 6, Z_POISSON = 7,
@@ -558,18 +578,24 @@ __global__ __launch_bounds__(NT) void k_zpass(ZArgs a, const float2* __restrict_
   constexpr int NV = NIN > NOUT ? NIN : NOUT;
   extern __shared__ float2 lds[];
   float2* tw_s = lds + ColBuf<L, T>::elems;
-  const int ntile = (a.ncols + HZ * T - 1) / (HZ * T);
+  static_assert(16 % (HZ * T) == 0, "a z-pass tile lies inside one group of 16 kx");
+  constexpr int NHZ = 16 / (HZ * T);                 // tiles per group of 16 kx
   // Workgroups go to the 8 XCDs round robin (block b to XCD b % 8), each XCD
   // with its own L2.  A tile of T = 8 complex columns is half a 128-byte line,
-  // so tiles 2j and 2j+1 read the same lines; numbering the tiles so that
-  // blocks b and b + 8 (same XCD, dispatched one after the other) take
-  // neighbouring tiles lets the second read hit in that XCD's L2.
+  // so the two tiles of a group read the same lines.  Blocks are numbered so
+  // that b and b + 8 (same XCD, dispatched one after the other) take the two
+  // tiles of one (group, ky), letting the second read hit in that XCD's L2,
+  // and so that the blocks in flight on an XCD cover neighbouring ky rows.
   const int nb = gridDim.x;
   const int lb = (nb % 8 == 0) ? (blockIdx.x % 8) * (nb / 8) + blockIdx.x / 8 : blockIdx.x;
-  const int tile = lb % ntile, y = lb / ntile;
-  const int x0 = tile * HZ * T;
-  const long long row = (long long)L * a.P;
-  const long long off = (long long)y * a.P + x0;
+  const int h0 = lb % NHZ, y = (lb / NHZ) % L, grp = lb / (NHZ * L);
+  const int x0 = 16 * grp + h0 * HZ * T;
+  if (x0 >= a.ncols) {                               // the unused tail of the last group
+    if (a.partials && threadIdx.x == 0) a.partials[blockIdx.x] = 0.0;
+    return;
+  }
+  const long long row = (long long)L * 16;                                  // kz stride
+  const long long off = ((long long)(x0 >> 4) * L * L + y) * 16 + (x0 & 15);
   load_twiddles<L>(tw_s, tw, NT);
   int nvh[HZ];
 #pragma unroll
@@ -798,13 +824,13 @@ hipError_t launch_x(const FftGeom& g, float2* spec, float* real, long long real_
     using X = XWave<N / 2>;
     const size_t sh = sizeof(float2) * (N + (size_t)X::ROWS * X::XB);
     hipLaunchKernelGGL((k_xpass_wave<N / 2, XMODE, NC>), dim3(N * N / X::ROWS), dim3(256), sh, st, spec,
-                       g.comp_stride, g.P, real, real_cs, g.tw, mu_mode, inv_a0, fprev, partials, dip);
+                       g.comp_stride, real, real_cs, g.tw, mu_mode, inv_a0, fprev, partials, dip);
     return hipGetLastError();
   } else {
     const int blocks = N * N / C::ROWS;
     const size_t sh = sizeof(float2) * ((size_t)(C::H + 1) * (NC * C::ROWS + 1) + N);
     hipLaunchKernelGGL((k_xpass<C::H, C::ROWS, NC, kNT, XMODE>), dim3(blocks), dim3(kNT), sh, st, spec,
-                       g.comp_stride, g.P, real, real_cs, g.tw, mu_mode, inv_a0, fprev, partials, dip);
+                       g.comp_stride, real, real_cs, g.tw, mu_mode, inv_a0, fprev, partials, dip);
     return hipGetLastError();
   }
 }
@@ -812,10 +838,10 @@ hipError_t launch_x(const FftGeom& g, float2* spec, float* real, long long real_
 template <int N, bool INV>
 hipError_t launch_y(const FftGeom& g, float2* spec, int ncomp, hipStream_t st) {
   using C = Cfg<N>;
-  const int tiles = (C::H + 1 + 2 * C::TY - 1) / (2 * C::TY);
+  const int tiles = (C::H + 1 + 15) / 16;
   const size_t sh = sizeof(float2) * ((size_t)ColBuf<N, C::TY>::elems + N);
   hipLaunchKernelGGL((k_ypass<N, C::TY, kNT, INV>), dim3(tiles, N, ncomp), dim3(kNT), sh, st, spec,
-                     g.comp_stride, g.P, C::H + 1, g.tw);
+                     g.comp_stride, C::H + 1, g.tw);
   return hipGetLastError();
 }
 
@@ -824,7 +850,6 @@ hipError_t launch_z(const FftGeom& g, ZArgs a, hipStream_t st) {
   using C = Cfg<N>;
   const size_t sh = sizeof(float2) * ((size_t)ColBuf<N, C::TZ>::elems + N);
   a.comp_stride = g.comp_stride;
-  a.P = g.P;
   a.ncols = C::H + 1;
   hipLaunchKernelGGL((k_zpass<N, C::TZ, kNTZ, PM_HZ, ZOP>), dim3(z_blocks(N)), dim3(kNTZ), sh, st, a, g.tw);
   return hipGetLastError();
@@ -870,8 +895,7 @@ int x_blocks(int N) {
 }
 int z_blocks(int N) {
   const int H = N / 2;
-  const int w = PM_TZ * PM_HZ;
-  return ((H + 1 + w - 1) / w) * N;
+  return ((H + 1 + 15) / 16) * (16 / (PM_TZ * PM_HZ)) * N;
 }
 
 hipError_t fft_pass(const FftGeom& g, const PassDesc& d, hipStream_t st) {

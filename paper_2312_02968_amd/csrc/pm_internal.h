@@ -8,7 +8,7 @@ namespace pm {
 // Geometry of the FFT box and its half spectrum.
 struct FftGeom {
   int N;                  // n_pad
-  int P;                  // complex entries per spectrum row (>= N/2 + 1)
+  int P;                  // kx slots of a spectrum: 16 * ceil((N/2 + 1) / 16)
   long long comp_stride;  // complex entries per spectrum component (N * N * P)
   const float2* tw;       // exp(-2 pi i t / N), t < N
 };
@@ -17,7 +17,7 @@ struct FftGeom {
 struct ZArgs {
   float2* spec;
   long long comp_stride;
-  int P, ncols;
+  int ncols;
   float2* phiN;
   const float* kv;
   const float* kt;

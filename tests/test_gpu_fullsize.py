@@ -18,7 +18,7 @@ torch = pytest.importorskip("torch")
 
 from oracle import pm as orc  # noqa: E402
 import workloads as W  # noqa: E402
-from tests.gpu_util import dev, host, oparams, rel_l2, rel_max, grid  # noqa: E402
+from tests.gpu_util import dev, host, oparams, rel_l2, rel_max, grid, spectrum_array  # noqa: E402
 
 N = 512
 
@@ -58,9 +58,7 @@ def test_fft_512(M):
     P = M.pm_spectrum_pitch(N)
     spec = torch.zeros(N * N * P * 2, dtype=torch.float32, device="cuda")
     M.pm_fft_r2c(ctx, dev(x), spec)
-    s = host(spec).reshape(N, N, P, 2)
-    got = s[:, :, : N // 2 + 1, 0] + 1j * s[:, :, : N // 2 + 1, 1]
-    del s
+    got = spectrum_array(spec, N, P)[:, :, : N // 2 + 1]
     import scipy.fft as sfft
     ref = sfft.rfftn(x.astype(np.float64), workers=orc.WORKERS)
     assert rel_l2(got, ref) < 3e-6

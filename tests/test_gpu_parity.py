@@ -19,7 +19,7 @@ torch = pytest.importorskip("torch")
 
 from oracle import pm as orc  # noqa: E402
 import workloads as W  # noqa: E402
-from tests.gpu_util import dev, host, oparams, rel_l2, rel_max, grid  # noqa: E402
+from tests.gpu_util import dev, host, oparams, rel_l2, rel_max, grid, spectrum_array, spectrum_tensor  # noqa: E402
 
 
 def _log(*a):
@@ -47,14 +47,18 @@ def test_fft_r2c_c2r_against_dft(M, N):
     P = M.pm_spectrum_pitch(N)
     spec = torch.zeros(N * N * P * 2, dtype=torch.float32, device="cuda")
     M.pm_fft_r2c(ctx, dev(x), spec)
-    s = host(spec).reshape(N, N, P, 2)
-    got = s[:, :, : N // 2 + 1, 0] + 1j * s[:, :, : N // 2 + 1, 1]
+    got = spectrum_array(spec, N, P)[:, :, : N // 2 + 1]
     ref = orc.fft3(x.astype(np.float64))[:, :, : N // 2 + 1]
     assert rel_l2(got, ref) < 3e-6
     out = grid(N)
     M.pm_fft_c2r(ctx, spec, out)
     back = host(out).reshape(N, N, N) / N ** 3
     assert rel_l2(back, x) < 3e-6
+    # the inverse of the oracle's half spectrum, handed over in the grouped layout
+    half = np.zeros((N, N, P), dtype=np.complex128)
+    half[:, :, : N // 2 + 1] = ref
+    M.pm_fft_c2r(ctx, spectrum_tensor(half, N, P), out)
+    assert rel_l2(host(out).reshape(N, N, N) / N ** 3, x) < 3e-6
     ctx.close()
 
 
@@ -69,8 +73,7 @@ def test_fft_single_mode_exact(M):
     P = M.pm_spectrum_pitch(N)
     spec = torch.zeros(N * N * P * 2, dtype=torch.float32, device="cuda")
     M.pm_fft_r2c(ctx, dev(f), spec)
-    s = host(spec).reshape(N, N, P, 2)
-    mag = np.hypot(s[:, :, : N // 2 + 1, 0], s[:, :, : N // 2 + 1, 1])
+    mag = np.abs(spectrum_array(spec, N, P)[:, :, : N // 2 + 1])
     assert mag[m[2], m[1], m[0]] == pytest.approx(N ** 3 / 2, rel=1e-6)
     mag[m[2], m[1], m[0]] = 0.0
     assert mag.max() < 1e-6 * N ** 3
