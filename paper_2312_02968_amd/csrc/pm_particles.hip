@@ -41,7 +41,7 @@ __device__ __forceinline__ float wave_sum_f(float v) {
 // Per-wave state of the particle being processed.
 struct Part {
   int cx, cy, cz;      // central pixel, wrapped grid index
-  float w1;            // this lane's 1D weight (axis lane / W, offset lane % W - ext)
+  float fx, fy, fz;    // central pixel minus the particle position (cells)
   double S;            // FP64 sum of the weights over the ball
 };
 
@@ -51,11 +51,18 @@ __device__ __forceinline__ void unpack(int e, int& dx, int& dy, int& dz) {
   dz = ((e >> 16) & 255) - 16;
 }
 
-// Central pixel and 1D weights of the particle at (px, py, pz), then S (all
-// lanes take part; the coordinates are wave-uniform).
+// Kernel weight of ball offset (dx, dy, dz): exp(-|c + d - x|^2 / (2 sigma^2))
+// with c + d - x = d + f; every lane evaluates its own cell (no cross-lane
+// traffic).
+__device__ __forceinline__ float ball_weight(const KernelGeom& kg, const Part& p, int dx, int dy, int dz) {
+  const float ex = (float)dx + p.fx, ey = (float)dy + p.fy, ez = (float)dz + p.fz;
+  return expf(-(ex * ex + ey * ey + ez * ez) * kg.inv2sig2);
+}
+
+// Central pixel and sub-pixel offset of the particle at (px, py, pz), then S
+// (all lanes take part; the coordinates are wave-uniform).
 __device__ __forceinline__ Part particle_setup(const KernelGeom& kg, const int* __restrict__ ball_lds, float px,
                                                float py, float pz, int lane, bool with_sum = true) {
-  const int W = 2 * kg.ext + 1;
   Part p;
   const double ux = (double)px * kg.inv_s;
   const double uy = (double)py * kg.inv_s;
@@ -65,23 +72,20 @@ __device__ __forceinline__ Part particle_setup(const KernelGeom& kg, const int* 
   p.cx = wrapi((int)cxd + half, kg.N);
   p.cy = wrapi((int)cyd + half, kg.N);
   p.cz = wrapi((int)czd + half, kg.N);
-  const int axis = lane / W;
-  const int o = lane - axis * W - kg.ext;
-  const double frac = axis == 0 ? cxd - ux : (axis == 1 ? cyd - uy : czd - uz);
-  const float d = (float)o + (float)frac;
-  p.w1 = (axis < 3) ? expf(-d * d * kg.inv2sig2) : 0.0f;
+  p.fx = (float)(cxd - ux);
+  p.fy = (float)(cyd - uy);
+  p.fz = (float)(czd - uz);
   p.S = 0.0;
   if (!with_sum || kg.analytic) return p;
   double acc = 0.0;
   const int nit = (kg.nball + 63) / 64;
   for (int it = 0; it < nit; ++it) {
     const int b = it * 64 + lane;
-    int dx = 0, dy = 0, dz = 0;
-    if (b < kg.nball) unpack(ball_lds[b], dx, dy, dz);
-    const float wx = __shfl(p.w1, dx + kg.ext, 64);
-    const float wy = __shfl(p.w1, W + dy + kg.ext, 64);
-    const float wz = __shfl(p.w1, 2 * W + dz + kg.ext, 64);
-    if (b < kg.nball) acc += (double)wx * (double)wy * (double)wz;
+    if (b < kg.nball) {
+      int dx, dy, dz;
+      unpack(ball_lds[b], dx, dy, dz);
+      acc += (double)ball_weight(kg, p, dx, dy, dz);
+    }
   }
   p.S = wave_sum_d(acc);
   return p;
@@ -251,7 +255,7 @@ template <bool LDS>
 __device__ __forceinline__ void deposit_one(const KernelGeom& kg, const int* __restrict__ ball, float x, float y,
                                             float z, float m, double s3, float* tile, int TE, int ox, int oy,
                                             int oz, float* rho, double* s_out, int lane) {
-  const int W = 2 * kg.ext + 1, N = kg.N;
+  const int N = kg.N;
   const Part p = particle_setup(kg, ball, x, y, z, lane);
   const double norm = kg.analytic ? kg.analytic_norm : p.S;
   if (s_out != nullptr && lane == 0) *s_out = norm;
@@ -259,13 +263,10 @@ __device__ __forceinline__ void deposit_one(const KernelGeom& kg, const int* __r
   const int nit = (kg.nball + 63) / 64;
   for (int it = 0; it < nit; ++it) {
     const int b = it * 64 + lane;
-    int dx = 0, dy = 0, dz = 0;
-    if (b < kg.nball) unpack(ball[b], dx, dy, dz);
-    const float wx = __shfl(p.w1, dx + kg.ext, 64);
-    const float wy = __shfl(p.w1, W + dy + kg.ext, 64);
-    const float wz = __shfl(p.w1, 2 * W + dz + kg.ext, 64);
     if (b < kg.nball) {
-      const float v = wx * wy * wz * scale;
+      int dx, dy, dz;
+      unpack(ball[b], dx, dy, dz);
+      const float v = ball_weight(kg, p, dx, dy, dz) * scale;
       if constexpr (LDS) {
         const int lx = p.cx + dx - ox, ly = p.cy + dy - oy, lz = p.cz + dz - oz;
         if (kg.private_tiles) {
@@ -357,12 +358,13 @@ __global__ __launch_bounds__(kNT) void k_deposit(KernelGeom kg, const int* __res
 // gather + push
 // ---------------------------------------------------------------------------
 // Smoothed acceleration of the wave's particle at (x, y, z) from the LDS
-// tile of phi (origin o*, edge TE) when tile != nullptr, else from phi.
+// tile of phi (origin o*, row pitch RP, plane pitch PP) when LDS, else from
+// phi.
 template <bool LDS>
 __device__ __forceinline__ float3 gather_one(const KernelGeom& kg, const int* __restrict__ ball, float x, float y,
-                                             float z, const float* tile, int TE, int ox, int oy, int oz,
+                                             float z, const float* tile, int RP, int PP, int ox, int oy, int oz,
                                              const float* __restrict__ phi, double s_known, int lane) {
-  const int W = 2 * kg.ext + 1, N = kg.N;
+  const int N = kg.N;
   // with a stored normalisation (s_known > 0) the ball sum is not recomputed
   const Part p = particle_setup(kg, ball, x, y, z, lane, s_known <= 0.0);
   const double norm = s_known > 0.0 ? s_known : (kg.analytic ? kg.analytic_norm : p.S);
@@ -370,20 +372,17 @@ __device__ __forceinline__ float3 gather_one(const KernelGeom& kg, const int* __
   const int nit = (kg.nball + 63) / 64;
   for (int it = 0; it < nit; ++it) {
     const int b = it * 64 + lane;
-    int dx = 0, dy = 0, dz = 0;
-    if (b < kg.nball) unpack(ball[b], dx, dy, dz);
-    const float wx = __shfl(p.w1, dx + kg.ext, 64);
-    const float wy = __shfl(p.w1, W + dy + kg.ext, 64);
-    const float wz = __shfl(p.w1, 2 * W + dz + kg.ext, 64);
     if (b < kg.nball) {
-      const float w = wx * wy * wz;
+      int dx, dy, dz;
+      unpack(ball[b], dx, dy, dz);
+      const float w = ball_weight(kg, p, dx, dy, dz);
       float xp, xm, yp, ym, zp, zm;
       if constexpr (LDS) {
         const int lx = p.cx + dx - ox, ly = p.cy + dy - oy, lz = p.cz + dz - oz;
-        const int c = (lz * TE + ly) * TE + lx;
+        const int c = lz * PP + ly * RP + lx;
         xp = tile[c + 1]; xm = tile[c - 1];
-        yp = tile[c + TE]; ym = tile[c - TE];
-        zp = tile[c + TE * TE]; zm = tile[c - TE * TE];
+        yp = tile[c + RP]; ym = tile[c - RP];
+        zp = tile[c + PP]; zm = tile[c - PP];
       } else {
         const int X = p.cx + dx, Y = p.cy + dy, Z = p.cz + dz;
         const long long zr = (long long)wrapi(Z, N) * N, zrp = (long long)wrapi(Z + 1, N) * N,
@@ -437,6 +436,9 @@ __global__ __launch_bounds__(kNT) void k_gather(KernelGeom kg, const int* __rest
   const int he = kg.ext + 1;                  // halo: ball plus the FD stencil
   const int TE = kTile + 2 * he;
   const int TE3 = TE * TE * TE;
+  // padded pitches: with TE = 16 (sigma = 1) unpadded planes are 256 floats
+  // apart, so the ball's cells in different planes would share LDS banks
+  const int RP = TE + 1, PP = RP * TE + 1;
   const int N = kg.N;
   const int nt = N / kTile;
   const int64_t a0 = (int64_t)blockIdx.x * kChunk;
@@ -455,7 +457,7 @@ __global__ __launch_bounds__(kNT) void k_gather(KernelGeom kg, const int* __rest
     const int nb = min(64, pl.nsparse - jb);
     for (int t = 0; t < nb; ++t) {
       const float3 g = gather_one<false>(kg, ball, __shfl(xl, t, 64), __shfl(yl, t, 64), __shfl(zl, t, 64),
-                                         nullptr, TE, 0, 0, 0, phi, __shfl(sl, t, 64), lane);
+                                         nullptr, RP, PP, 0, 0, 0, phi, __shfl(sl, t, 64), lane);
       if (lane == t) mine = g;
     }
     if (has) gather_store(il, mine, xl, yl, zl, pos, vel, acc, dt_kick, dt_drift, mode);
@@ -468,7 +470,7 @@ __global__ __launch_bounds__(kNT) void k_gather(KernelGeom kg, const int* __rest
     const int ox = tx * kTile - he, oy = ty * kTile - he, oz = tz * kTile - he;
     for (int j = threadIdx.x; j < TE3; j += kNT) {
       const int lx = j % TE, ly = (j / TE) % TE, lz = j / (TE * TE);
-      tile[j] = phi[((long long)wrapi(oz + lz, N) * N + wrapi(oy + ly, N)) * N + wrapi(ox + lx, N)];
+      tile[lz * PP + ly * RP + lx] = phi[((long long)wrapi(oz + lz, N) * N + wrapi(oy + ly, N)) * N + wrapi(ox + lx, N)];
     }
     __syncthreads();
     for (int jb = ps + wave; jb < pe; jb += kWaves * 64) {
@@ -482,7 +484,7 @@ __global__ __launch_bounds__(kNT) void k_gather(KernelGeom kg, const int* __rest
       const int nb = min(64, (pe - jb + kWaves - 1) / kWaves);
       for (int u = 0; u < nb; ++u) {
         const float3 g = gather_one<true>(kg, ball, __shfl(xl, u, 64), __shfl(yl, u, 64), __shfl(zl, u, 64),
-                                          tile, TE, ox, oy, oz, phi, __shfl(sl, u, 64), lane);
+                                          tile, RP, PP, ox, oy, oz, phi, __shfl(sl, u, 64), lane);
         if (lane == u) mine = g;
       }
       if (has) gather_store(il, mine, xl, yl, zl, pos, vel, acc, dt_kick, dt_drift, mode);
@@ -527,7 +529,7 @@ __global__ __launch_bounds__(kNT) void k_diag_phi(KernelGeom kg, const float* __
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int b = threadIdx.x; b < kg.nball; b += kNT) ball[b] = kg.ball[b];
   __syncthreads();
-  const int W = 2 * kg.ext + 1, N = kg.N;
+  const int N = kg.N;
   double tot = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * kWaves + wave; i < n; i += (int64_t)gridDim.x * kWaves) {
     const Part p = particle_setup(kg, ball, pos, (int)i, lane);
@@ -536,14 +538,11 @@ __global__ __launch_bounds__(kNT) void k_diag_phi(KernelGeom kg, const float* __
     const int nit = (kg.nball + 63) / 64;
     for (int it = 0; it < nit; ++it) {
       const int b = it * 64 + lane;
-      int dx = 0, dy = 0, dz = 0;
-      if (b < kg.nball) unpack(ball[b], dx, dy, dz);
-      const float wx = __shfl(p.w1, dx + kg.ext, 64);
-      const float wy = __shfl(p.w1, W + dy + kg.ext, 64);
-      const float wz = __shfl(p.w1, 2 * W + dz + kg.ext, 64);
       if (b < kg.nball) {
+        int dx, dy, dz;
+        unpack(ball[b], dx, dy, dz);
         const long long g = ((long long)wrapi(p.cz + dz, N) * N + wrapi(p.cy + dy, N)) * N + wrapi(p.cx + dx, N);
-        acc += (double)(wx * wy * wz) * (double)phi[g];
+        acc += (double)ball_weight(kg, p, dx, dy, dz) * (double)phi[g];
       }
     }
     acc = wave_sum_d(acc);
@@ -585,9 +584,12 @@ hipError_t sort_particles(const KernelGeom& kg, const SortBufs& sb, const float*
   return hipGetLastError();
 }
 
-static size_t particle_lds(const KernelGeom& kg, int halo) {
-  const int TE = kTile + 2 * halo;
-  return sizeof(float) * (((kg.nball + 3) & ~3) + (size_t)TE * TE * TE);
+// LDS of the gather: ball offsets and the phi tile with padded pitches
+// (row TE + 1, plane (TE + 1) TE + 1).
+static size_t gather_lds(const KernelGeom& kg) {
+  const int TE = kTile + 2 * (kg.ext + 1);
+  const size_t PP = (size_t)(TE + 1) * TE + 1;
+  return sizeof(float) * (((kg.nball + 3) & ~3) + (size_t)TE * PP);
 }
 
 hipError_t deposit_sorted(const KernelGeom& kg, const SortBufs& sb, const float* pos, const float* mass,
@@ -606,7 +608,7 @@ hipError_t gather_sorted(const KernelGeom& kg, const SortBufs& sb, const float* 
                          hipStream_t st) {
   if (n <= 0) return hipSuccess;
   const unsigned blocks = (unsigned)((n + kChunk - 1) / kChunk);
-  hipLaunchKernelGGL(k_gather, dim3(blocks), dim3(kNT), particle_lds(kg, kg.ext + 1), st, kg, sb.perm, sb.skey,
+  hipLaunchKernelGGL(k_gather, dim3(blocks), dim3(kNT), gather_lds(kg), st, kg, sb.perm, sb.skey,
                      sb.offsets, phi, pos, vel, acc, n, dt_kick, dt_drift, mode, s_store);
   return hipGetLastError();
 }

@@ -408,6 +408,34 @@ def test_pm_step_zero_particles(M):
     ctx.close()
 
 
+def test_diagnostics_parity(M):
+    # FP64 constants of motion (Sect. 4.1) and sum_i m_i phi_i of the same FP32
+    # state; phi is the oracle's potential of that state
+    _log("diagnostics")
+    w = W.random_cloud(44, 32, 2000, mu=0, radius_frac=0.25)
+    p = w["params"]
+    op = oparams(p)
+    pos, vel, mass = (w[k].astype(np.float64) for k in ("pos", "vel", "mass"))
+    phi, _ = orc.aqual_solve(op, orc.deposit(op, pos, mass))
+    phi32 = phi.astype(np.float32)
+    ref = orc.diagnostics(op, pos, vel, mass, phi32.astype(np.float64))
+    ctx = M.pm_create(p, len(mass))
+    d = M.pm_diagnostics(ctx, dev(w["pos"]), dev(w["vel"]), dev(w["mass"]), dev(phi32))
+    scale_p = float((mass[:, None] * np.abs(vel)).sum())
+    scale_l = float((mass[:, None] * np.abs(np.cross(pos, vel))).sum())
+    assert np.max(np.abs(np.array(d["P"]) - ref["P"])) < 1e-12 * scale_p
+    assert np.max(np.abs(np.array(d["L"]) - ref["L"])) < 1e-12 * scale_l
+    assert d["Ekin"] == pytest.approx(ref["Ekin"], rel=1e-12)
+    assert d["mass"] == pytest.approx(ref["mass"], rel=1e-12)
+    # phi at the particles is smoothed in FP32 on the GPU
+    assert d["Epot_sum"] == pytest.approx(ref["Epot_sum"], rel=1e-6)
+    assert d["out_of_region"] == 0
+    nophi = M.pm_diagnostics(ctx, dev(w["pos"]), dev(w["vel"]), dev(w["mass"]))
+    # the FP64 sums are atomics in any order: equal to rounding
+    assert nophi["Epot_sum"] == 0.0 and nophi["Ekin"] == pytest.approx(d["Ekin"], rel=1e-14)
+    ctx.close()
+
+
 def test_newton_momentum_conserved_on_gpu(M):
     # Newton mode: sum_i m_i g_i = 0 up to FP32 rounding of the forces.
     w = W.random_cloud(40, 32, 2000, mu=2, radius_frac=0.2)
