@@ -517,8 +517,27 @@ __global__ __launch_bounds__(NT) void k_ypass(float2* spec, long long comp_strid
   constexpr int E = ColCfg<L, T, NT>::E;
   extern __shared__ float2 lds[];
   float2* tw_s = lds + ColBuf<L, T>::elems;
-  const int x0 = blockIdx.x * 16;
-  float2* base = spec + blockIdx.z * comp_stride + ((long long)blockIdx.x * L + blockIdx.y) * L * 16;
+  // Block order.  Each pass reads what the previous one wrote, and the last
+  // ~256 MB written are still in the Infinity Cache, so a pass starts where
+  // its predecessor ended.  The forward y pass follows an x pass, which
+  // writes rows (planes) in ascending order: it takes planes in descending
+  // order as its slowest index.  The inverse y pass follows a z pass, whose
+  // XCD ranges end in the higher kx groups: it takes groups in descending
+  // order as its slowest index.
+  const int nt = gridDim.x, nc = gridDim.z;
+  const long long b = blockIdx.x + (long long)nt * (blockIdx.y + (long long)L * blockIdx.z);
+  int t, kz, comp;
+  if constexpr (!INV) {
+    t = (int)(b % nt);
+    comp = (int)((b / nt) % nc);
+    kz = L - 1 - (int)(b / ((long long)nt * nc));
+  } else {
+    kz = (int)(b % L);
+    comp = (int)((b / L) % nc);
+    t = nt - 1 - (int)(b / ((long long)L * nc));
+  }
+  const int x0 = t * 16;
+  float2* base = spec + comp * comp_stride + ((long long)t * L + kz) * L * 16;
   load_twiddles<L>(tw_s, tw, NT);
   float2 v[NH * E];
   using First = PlanAt<L, false, 0>;
