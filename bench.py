@@ -127,7 +127,8 @@ def start_comparison(w):
         r = L.compare_starts(w, net)
         net.close()
         keep = ("K_plain", "K_learned", "plain_err", "learned_err", "t_plain_ms", "t_learned_ms", "t_start_ms",
-                "tol", "tol_iters_plain", "tol_iters_learned")
+                "tol", "tol_iters_plain", "tol_iters_learned", "t_tol_plain_ms", "t_tol_learned_ms",
+                "tol_fixed_point_diff", "tol_fallback")
         res["learned_start"] = {k: r[k] for k in keep}
     t = L.warm_start_trajectory(w, steps=10, Ks=(2,))
     last = {k: v[-1] for k, v in t["err_box_region"].items()}

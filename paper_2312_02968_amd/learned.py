@@ -241,15 +241,46 @@ def compare_starts(w, net, K_plain=4, K_ref=30, tol=1e-4, max_iters=30, reps=3):
         t_learned = t_net = None
     out.update(t_plain_ms=t_plain, t_learned_ms=t_learned, t_start_ms=t_net)
 
+    # tolerance mode: both starts iterate until r_k <= tol.  The fixed points
+    # must agree; the learned start falls back to zero when its first
+    # residual (the change of H in the first iteration) exceeds the zero
+    # start's; wall times include the learned path's Newton potential and
+    # network.
     ct = ctx_for(iters=max_iters, tol=tol)
+    phi_l = torch.empty_like(rho)
     ip = M.aqual_solve(ct, rho, phi)
-    il = M.aqual_solve(ct, rho, phi, H0=H0)
+    il = M.aqual_solve(ct, rho, phi_l, H0=H0)
+    fp_diff = float(torch.linalg.vector_norm(phi_l - phi)) / float(torch.linalg.vector_norm(phi))
+    fallback = bool(il["residuals"] and ip["residuals"] and il["residuals"][0] > ip["residuals"][0])
+    t_tol_plain = min(_timed(lambda: M.aqual_solve(ct, rho, phi, want_info=False))[0] for _ in range(reps))
+
+    def learned_tol():
+        M.pm_newton_potential(ct, rho, phiN)
+        M.pm_net_forward(ct, net, phiN, H0)
+        M.aqual_solve(ct, rho, phi_l, H0=H0, want_info=False)
+    t_tol_learned = min(_timed(learned_tol)[0] for _ in range(reps))
     ct.close()
     c1.close()
     out.update(tol=tol, tol_iters_plain=ip["iterations"], tol_iters_learned=il["iterations"],
                tol_status_plain=ip["status"], tol_status_learned=il["status"],
-               resid_plain=ip["residuals"], resid_learned=il["residuals"])
+               resid_plain=ip["residuals"], resid_learned=il["residuals"],
+               tol_fixed_point_diff=fp_diff, tol_fallback=fallback,
+               t_tol_plain_ms=t_tol_plain, t_tol_learned_ms=t_tol_learned)
     return out
+
+
+def summarize(results):
+    """Learned-vs-plain summary over inputs: median wall-time ratio in
+    tolerance mode, largest fixed-point difference, fallback rate, and the
+    iteration counts."""
+    ratios = sorted(r["t_tol_learned_ms"] / r["t_tol_plain_ms"] for r in results)
+    m = len(ratios)
+    med = ratios[m // 2] if m % 2 else 0.5 * (ratios[m // 2 - 1] + ratios[m // 2])
+    return {"inputs": m, "tol": results[0]["tol"], "median_time_ratio": med,
+            "max_fixed_point_diff": max(r["tol_fixed_point_diff"] for r in results),
+            "fallback_rate": sum(r["tol_fallback"] for r in results) / m,
+            "iters_plain": [r["tol_iters_plain"] for r in results],
+            "iters_learned": [r["tol_iters_learned"] for r in results]}
 
 
 def warm_start_trajectory(w, steps=10, Ks=(2, 3), K_cold=4, K_ref=30, reps=5):
@@ -356,7 +387,7 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=3e-4)
     ap.add_argument("--weights", default=WEIGHTS)
     ap.add_argument("--eval-n", type=int, default=256)
-    ap.add_argument("--eval-count", type=int, default=4)
+    ap.add_argument("--eval-count", type=int, default=16)
     ap.add_argument("--out", default=None, help="JSON file for the results")
     ap.add_argument("--train-n", type=int, default=TRAIN_N, help="network size (half the FFT box) for training")
     ap.add_argument("--init", default=None, help="start training from these parameters")
@@ -386,6 +417,8 @@ def main(argv=None):
             r = compare_starts(w, net)
             log(json.dumps(r))
             res["results"].append(r)
+        res["summary"] = summarize(res["results"])
+        log(json.dumps({"summary": res["summary"]}))
     if a.out:
         with open(a.out, "w") as f:
             json.dump(res, f)
