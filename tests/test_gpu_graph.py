@@ -145,3 +145,43 @@ def test_capture_argument_checks(M):
             M.pm_step_capture(cnull, pos, vel, mass, 0.1)
         cnull.close()
     torch.cuda.synchronize()
+
+
+def test_replay_keeps_the_external_field_of_capture(M):
+    # the sheets' density is a kernel argument of the captured Newton pass:
+    # changing the context's field later does not change the replayed step
+    _log("graph replay with an external field")
+    w = W.isothermal_sphere(seed=3, N=4096, n=32, b=3.0, r_max=11.0)
+    p = w["params"]
+    n_p = len(w["mass"])
+    dt = float(w["dt"])
+    g = (0.0, 0.3 * p["a0"], 0.2 * p["a0"])
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    ce = M.pm_create(p, n_p, stream=s1)
+    cg = M.pm_create(p, n_p, stream=s2)
+    M.pm_set_external_field(ce, g)
+    M.pm_set_external_field(cg, g)
+    pos_e, vel_e, mass_e = _state(w)
+    pos_g, vel_g, mass_g = _state(w)
+    torch.cuda.synchronize()
+    M.pm_step_capture(cg, pos_g, vel_g, mass_g, dt)
+    M.pm_set_external_field(cg, (0.0, 0.0, 0.0))
+    vel0 = w["vel"].astype(np.float64)
+    for _ in range(2):
+        M.pm_step_replay(cg, 1)
+        M.pm_step(ce, pos_e, vel_e, mass_e, dt)
+        torch.cuda.synchronize()
+        _agree(pos_e, vel_e, pos_g, vel_g, vel0)
+    # and the field changed the steps: the same two eager steps without it differ
+    pos_z, vel_z, mass_z = _state(w)
+    cz = M.pm_create(p, n_p, stream=s1)
+    torch.cuda.synchronize()
+    for _ in range(2):
+        M.pm_step(cz, pos_z, vel_z, mass_z, dt)
+    torch.cuda.synchronize()
+    v1 = host(vel_z).reshape(-1, 3) - vel0
+    ve = host(vel_e).reshape(-1, 3) - vel0
+    assert rel_l2(v1, ve) > 1e-2
+    ce.close()
+    cg.close()
+    cz.close()
