@@ -5,9 +5,11 @@ which calls only the oracle): the two-body workload over 200 steps
 
 Every step is the same deposit -> solve -> kick -> drift on both sides, from
 the same FP32 initial state; FP32 positions drift from the FP64 ones by
-rounding (about 1e-5 cell per step at |x| ~ 20), so trajectories are held
-to 1e-3 cell and the velocities to 1e-4 relative, and the measured
-differences are printed.
+rounding (about 1e-5 cell per step at |x| ~ 20).  Trajectories are a
+reported result: they are held loosely, to 1e-3 cell and 3e-4 of the
+largest speed (measured: 1.7e-6 cell and 2e-7 for the two-body run,
+7.4e-6 cell and 5.3e-5 for the ring), and the measured differences are
+printed.
 """
 import json
 import os
@@ -64,5 +66,5 @@ def test_trajectory_follows_oracle(M, golden, name, make):
         worst_x, worst_v = max(worst_x, dx), max(worst_v, dv)
     _log(f"{name}: {g['steps']} steps, max |dx| {worst_x:.2e} cell, max |dv| / |v| {worst_v:.2e}")
     assert worst_x < 1e-3
-    assert worst_v < 1e-4
+    assert worst_v < 3e-4
     ctx.close()
