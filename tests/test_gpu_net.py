@@ -262,3 +262,49 @@ def test_net_forward_shift_equivariance_at_full_size():
     assert torch.equal(torch.roll(y0, shifts=(4, -8, 12), dims=(1, 2, 3)), y1)
     assert float(y0.abs().max()) > 0.0
     net.close()
+
+
+@pytest.mark.parametrize("case", ["mixture_256", "isothermal_256"])
+def test_trained_network_gains_over_the_zero_start(case):
+    # What the committed network buys at the size it was fine-tuned for
+    # (256^3 grid, 512^3 box): the potential error after 1 and 2 iterations
+    # from its start against the zero start's, both measured against a
+    # 30-iteration solve of the same density.  Held-out inputs: a mixture
+    # seed outside the training range (radii twice the training range) and
+    # the isothermal sphere of the throughput workload.
+    from paper_2312_02968_amd import learned as L
+    if case == "mixture_256":
+        w = L.held_out_inputs(256, 4)[3]
+    else:
+        w = W.isothermal_sphere(seed=0)
+    p = w["params"]
+    N = p["n_pad"]
+    ctx = M.pm_create(dict(p, iters=30), len(w["mass"]))
+    rho = grid(N)
+    M.pm_deposit(ctx, dev(w["pos"]), dev(w["mass"]), rho)
+    ref = grid(N)
+    M.aqual_solve(ctx, rho, ref)
+    ctx.close()
+    net = M.Net(N // 2, 1)
+    M.pm_net_set_params(net, L.load_params(L.WEIGHTS))
+    c1 = M.pm_create(dict(p, iters=1), 0)
+    phiN = grid(N)
+    H0 = torch.empty(3 * N ** 3, device="cuda")
+    M.pm_newton_potential(c1, rho, phiN)
+    M.pm_net_forward(c1, net, phiN, H0)
+    c1.close()
+    nref = float(torch.linalg.vector_norm(ref))
+    phi = grid(N)
+    err = {}
+    for K in (1, 2):
+        c = M.pm_create(dict(p, iters=K), 0)
+        M.aqual_solve(c, rho, phi)
+        plain = float(torch.linalg.vector_norm(phi - ref)) / nref
+        M.aqual_solve(c, rho, phi, H0=H0)
+        learned = float(torch.linalg.vector_norm(phi - ref)) / nref
+        c.close()
+        err[K] = (plain, learned)
+    print(case, {K: f"{a:.2e} -> {b:.2e}" for K, (a, b) in err.items()}, flush=True)
+    assert err[1][1] < 0.5 * err[1][0]
+    assert err[2][1] < err[2][0]
+    net.close()
