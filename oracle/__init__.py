@@ -11,6 +11,10 @@ Modules
 pm       deposit, Newton solve, AQUAL fixed-point iteration, smoothed force,
          leapfrog and diagnostics, in the order of the paper's flow scheme
          (appendix "Flow scheme of the PM code").
+linearised
+         the step-to-step increments of the fields with the linearised
+         algebraic equations and FP16 storage (Sect. 5, item (v)); no kernel
+         implements it yet.
 convnet  FP64 3D conv encoder-decoder (forward, backward, Adam) for the learned
          starting guess.  Parity unpinned against the paper (the paper has no
          such network); pinned by finite differences and closed forms.
