@@ -207,6 +207,67 @@ def pass_bytes(N, K):
     return b
 
 
+def oracle_error(w, n_sample=4096):
+    """Force error of this configuration against the FP64 oracle on the same
+    input, outside the timed region.
+
+    The GPU deposits the workload's initial particles, runs the solve with the
+    configuration's iterations and computes the smoothed force of every
+    particle.  The oracle deposits all particles, solves the whole box and
+    computes the force of n_sample of them.  Errors are relative to the
+    sample's forces: L2, and the largest deviation over the largest force.
+    """
+    import numpy as np
+    import torch
+    from paper_2312_02968_amd import mondpm as M
+    from oracle import pm as orc
+
+    p = w["params"]
+    n = len(w["mass"])
+    R = p["n_pad"] ** 3
+    ctx = M.pm_create(p, n)
+    pos = torch.from_numpy(w["pos"]).cuda()
+    mass = torch.from_numpy(w["mass"]).cuda()
+    rho = torch.zeros(R, dtype=torch.float32, device="cuda")
+    phi = torch.zeros(R, dtype=torch.float32, device="cuda")
+    acc = torch.zeros(3 * n, dtype=torch.float32, device="cuda")
+    M.pm_deposit(ctx, pos, mass, rho)
+    M.aqual_solve(ctx, rho, phi, want_info=False)
+    M.smooth_accel(ctx, phi, pos, acc)
+    torch.cuda.synchronize()
+    got = acc.cpu().numpy().reshape(-1, 3).astype(np.float64)
+    ctx.close()
+    del pos, mass, rho, phi, acc
+    idx = np.random.default_rng(3).choice(n, n_sample, replace=False)
+    op = orc.Params.from_dict(p)
+    print(f"oracle error: FP64 deposit of {n} particles and solve of the {p['n_pad']}^3 box",
+          file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    rho_o = orc.deposit(op, w["pos"].astype(np.float64), w["mass"].astype(np.float64))
+    phi_o, _ = orc.aqual_solve(op, rho_o)
+    del rho_o
+    ref = orc.smooth_accel(op, phi_o, w["pos"][idx].astype(np.float64))
+    t = time.perf_counter() - t0
+    d = got[idx] - ref
+    return {"force_rel_l2": float(np.linalg.norm(d) / np.linalg.norm(ref)),
+            "force_rel_max": float(np.abs(d).max() / np.abs(ref).max()),
+            "sample": (f"deposit, {op.iters}-iteration solve and smoothed force from the initial state; "
+                       f"forces of {n_sample} of {n} particles (seed 3) against the FP64 oracle"),
+            "oracle_s": round(t, 1)}
+
+
+def host_cpu_model():
+    """The host CPU's model name from /proc/cpuinfo (None where it is not there)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(w, n_sample=4096):
     """FP64 oracle on a bounded sample of the workload, scaled to one step.
 
@@ -267,6 +328,7 @@ def cpu_baseline(w, n_sample=4096):
     t_step = t_dep + t_gat + t_newton + (K - 1) * t_iter + t_last_a + t_last_b
     cores = orc.WORKERS
     return {"value": 1.0 / t_step, "unit": "PM steps/s", "cores": cores, "kind": "oracle",
+            "cpu": host_cpu_model(),
             "sample": (f"FP64 oracle (scipy.fft, {cores} workers): deposit and gather+push of "
                        f"{n_sample} and {2 * n_sample} of {N} particles (fixed + per-particle cost "
                        f"fitted, evaluated at N), Newton solve and one full AQUAL iteration on the "
@@ -290,6 +352,9 @@ def main():
                     help="time pm_step with the warm start (previous step's F) and K iterations")
     ap.add_argument("--no-starts", action="store_true",
                     help="skip the learned-start and warm-start comparisons")
+    ap.add_argument("--oracle-error", action="store_true",
+                    help="also report the configuration's force error against the FP64 oracle "
+                         "(about a minute of host work)")
     ap.add_argument("--launch", choices=("graph", "eager"), default="graph",
                     help="time replays of the step recorded as a HIP graph (default) or eager pm_step calls")
     a = ap.parse_args()
@@ -397,7 +462,10 @@ def main():
     out["solver_vs_poisson"] = solver_vs_poisson(w)
     if not a.no_starts and not a.warm:
         out.update(start_comparison(w))
+    if a.oracle_error and not a.warm:
+        out["oracle_error"] = oracle_error(w)
     if not a.no_cpu_baseline:
+        print("cpu baseline: FP64 oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
 
