@@ -37,7 +37,7 @@ import numpy as np
 from . import pm
 
 __all__ = ["nu_value", "nu_slope", "mu_value", "mu_slope", "linearised_nu",
-           "linearised_mu", "to_half", "base_state", "incremental_solve"]
+           "linearised_mu", "to_half", "base_state", "incremental_solve", "advance_base"]
 
 
 def nu_value(p: pm.Params, y: np.ndarray) -> np.ndarray:
@@ -125,13 +125,16 @@ def base_state(p: pm.Params, rho: np.ndarray, tol: float = 1e-13, max_iters: int
 
 
 def incremental_solve(p: pm.Params, base: dict, d_rho: np.ndarray, iters: int,
-                      store=None):
+                      store=None, keep_fields: bool = False):
     """dphi for a density increment d_rho about ``base`` (Sect. 5, item (v)),
     with ``iters`` evaluations of the first linearisation from dH = 0.
 
     Returns (dphi, residuals), residuals r_k = ||dH_k - dH_{k-1}|| / ||dg_N||.
     ``store`` (identity by default) is applied to dg_N, dF, dg_M and dH where
-    they would be written to memory.
+    they would be written to memory.  With keep_fields the increments of the
+    last iteration are returned as a third item: dg_N, dH, dF = dg_N + dH and
+    dg_M (the curl-free part of the last linearised nu), as ``advance_base``
+    takes them.
     """
     if store is None:
         def store(a):
@@ -142,12 +145,15 @@ def incremental_solve(p: pm.Params, base: dict, d_rho: np.ndarray, iters: int,
     dH = np.zeros_like(dgN)
     res = []
     dphih = None
+    dF = dgM = None
     K = max(int(iters), 1)
     for k in range(1, K + 1):
         dF = store(dgN + dH)
         dgM = linearised_nu(p, base["F"], dF)
         gh, dphih = pm.project_curl_free(p, np.stack([pm.fft3(c) for c in dgM]))
         if k == K:
+            if keep_fields:
+                dgM = store(np.stack([pm.ifft3_real(c) for c in gh]))
             break
         dgM = store(np.stack([pm.ifft3_real(c) for c in gh]))
         dFp = linearised_mu(p, base["gM"], dgM)
@@ -156,4 +162,14 @@ def incremental_solve(p: pm.Params, base: dict, d_rho: np.ndarray, iters: int,
         d = dHn - dH
         res.append(math.sqrt(float((d * d).sum())) / norm if norm > 0 else 0.0)
         dH = dHn
-    return pm.ifft3_real(dphih), res
+    dphi = pm.ifft3_real(dphih)
+    if keep_fields:
+        return dphi, res, dict(dgN=dgN, dH=dH, dF=dF, dgM=dgM)
+    return dphi, res
+
+
+def advance_base(base: dict, dphi: np.ndarray, inc: dict) -> dict:
+    """The next step's previous fields: every field plus its increment, so that
+    the next increment is linearised about the updated F and g_M."""
+    return dict(gN=base["gN"] + inc["dgN"], H=base["H"] + inc["dH"], F=base["F"] + inc["dF"],
+                gM=base["gM"] + inc["dgM"], phi=base["phi"] + dphi, info=base.get("info"))
