@@ -7,7 +7,9 @@ Starts with the half kick that puts the velocities half a step behind the
 positions (leapfrog, Sect. 3), then runs the steps.  Every `every` steps it
 prints one JSON line with the total momentum P, angular momentum L, kinetic
 energy, mass, sum m_i phi_i and the number of particles whose ball leaves the
-physical region (pm_diagnostics).  The half kick and the diagnostics solve
+physical region (pm_diagnostics), and the particles' mean distance from the
+centre of mass, its spread (standard deviation) and their mean speed.  The
+half kick and the diagnostics solve
 with the workload's own iterations from a zero start, in a context of their
 own, so that they leave the warm start of the stepping context alone.  The
 momentum is reported relative to
@@ -73,9 +75,14 @@ def main(argv=None):
         d = M.pm_diagnostics(dctx, pos, vel, mass, phi)
         v = vel.double().reshape(-1, 3)
         scale = float((mass.double()[:, None] * v.abs()).sum())
+        x = pos.double().reshape(-1, 3)
+        md = mass.double()
+        com = (md[:, None] * x).sum(0) / md.sum()
+        r = torch.linalg.vector_norm(x - com, dim=1)
         rec = {"step": step, "P_rel": float(np.linalg.norm(d["P"])) / scale, "L": d["L"],
                "Ekin": d["Ekin"], "mass": d["mass"], "Epot_sum": d["Epot_sum"],
-               "out_of_region": d["out_of_region"], "ms_per_step": t_ms}
+               "out_of_region": d["out_of_region"], "r_mean": float(r.mean()), "r_std": float(r.std()),
+               "v_mean": float(torch.linalg.vector_norm(v, dim=1).mean()), "ms_per_step": t_ms}
         print(json.dumps(rec), flush=True)
 
     report(0, None)

@@ -39,7 +39,9 @@ def oracle_run(warm):
         phi, info = orc.aqual_solve(q, rho, H0=H0, keep_fields=True)
         F_prev = info.gN + info.H
         pos, vel = orc.interp_push(q, phi, pos, vel, dt, dt)
-    return dict(Ekin=0.5 * float((m[:, None] * vel * vel).sum()), mass=float(m.sum()))
+    com = (m[:, None] * pos).sum(0) / m.sum()
+    return dict(Ekin=0.5 * float((m[:, None] * vel * vel).sum()), mass=float(m.sum()),
+                r_mean=float(np.linalg.norm(pos - com, axis=1).mean()))
 
 
 @pytest.mark.parametrize("warm", [0, 2], ids=["zero_start", "warm2"])
@@ -61,3 +63,4 @@ def test_run_two_body(capsys, warm):
         assert r["P_rel"] < 0.05
     assert recs[0]["ms_per_step"] is None and recs[-1]["ms_per_step"] > 0
     assert abs(recs[-1]["Ekin"] - ref["Ekin"]) <= 1e-3 * ref["Ekin"]
+    assert abs(recs[-1]["r_mean"] - ref["r_mean"]) <= 1e-4 * ref["r_mean"]
