@@ -1,7 +1,7 @@
 """Throughput of the MOND particle-mesh step on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload isothermal]
-                    [--no-cpu-baseline]
+                    [--no-cpu-baseline] [--no-oracle-error]
 
 Runs W untimed and K timed PM steps (deposit, AQUAL solve with 4 iterations,
 gather, kick and drift) through the C ABI on the default workload: the
@@ -14,8 +14,10 @@ The timed region is K replays of the step recorded once as a HIP graph
 instead).  K eager steps follow with a HIP event pair around every launch on
 the library's stream: they give the per-kernel durations of the roofline
 record, for the kernel with the largest share of the step, and their own
-ms/step.  The line also carries a CPU baseline: the FP64 oracle timed on a
-bounded sample of the same workload on the host cores.
+ms/step.  The line also carries a CPU baseline (the FP64 oracle timed on a
+bounded sample of the same workload on the host cores) and, for FFT boxes up
+to 512^3, the configuration's force error against the FP64 oracle on the
+same input.
 """
 from __future__ import annotations
 
@@ -352,9 +354,9 @@ def main():
                     help="time pm_step with the warm start (previous step's F) and K iterations")
     ap.add_argument("--no-starts", action="store_true",
                     help="skip the learned-start and warm-start comparisons")
-    ap.add_argument("--oracle-error", action="store_true",
-                    help="also report the configuration's force error against the FP64 oracle "
-                         "(about a minute of host work)")
+    ap.add_argument("--no-oracle-error", action="store_true",
+                    help="skip the force error against the FP64 oracle (about a minute of host work; "
+                         "reported by default for FFT boxes up to 512^3 with the zero start)")
     ap.add_argument("--launch", choices=("graph", "eager"), default="graph",
                     help="time replays of the step recorded as a HIP graph (default) or eager pm_step calls")
     a = ap.parse_args()
@@ -462,7 +464,7 @@ def main():
     out["solver_vs_poisson"] = solver_vs_poisson(w)
     if not a.no_starts and not a.warm:
         out.update(start_comparison(w))
-    if a.oracle_error and not a.warm:
+    if not a.no_oracle_error and not a.warm and p["n_pad"] <= 512:
         out["oracle_error"] = oracle_error(w)
     if not a.no_cpu_baseline:
         print("cpu baseline: FP64 oracle on a bounded sample", file=sys.stderr, flush=True)
