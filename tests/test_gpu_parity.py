@@ -213,6 +213,38 @@ def test_warm_start_from_previous_solve(M, K, extra):
     ctx.close()
 
 
+def test_warm_start_with_external_field(M):
+    # both features at once: the sheets are part of every solve's density, so
+    # the previous F and the new g_N both carry the external field
+    _log("warm start with an external field")
+    w = W.random_cloud(32, 16, 60, mu=0, iters=2, radius_frac=0.2)
+    p = w["params"]
+    op = oparams(p)
+    N = p["n_pad"]
+    g = (0.3 * p["a0"], 0.0, 0.2 * p["a0"])
+    ext = orc.external_field_density(op, g)
+    pos1 = w["pos"].astype(np.float64)
+    pos2 = pos1 + 0.4 * w["vel"].astype(np.float64) / np.abs(w["vel"]).max()
+    m = w["mass"].astype(np.float64)
+    rho1 = orc.deposit(op, pos1, m).astype(np.float32)
+    rho2 = orc.deposit(op, pos2, m).astype(np.float32)
+    _, i1 = orc.aqual_solve(op, rho1.astype(np.float64) + ext, keep_fields=True)
+    F1 = i1.gN + i1.H
+    _, gN2 = orc.newton_potential(op, rho2.astype(np.float64) + ext)
+    phi2_ref, _ = orc.aqual_solve(op, rho2.astype(np.float64) + ext, H0=F1 - gN2)
+    phi2_cold, _ = orc.aqual_solve(op, rho2.astype(np.float64) + ext)
+    ctx = M.pm_create(dict(p, flags=M.PM_F_WARM_START), 0)
+    M.pm_set_external_field(ctx, g)
+    phi = grid(N)
+    M.aqual_solve(ctx, dev(rho1), phi)
+    M.aqual_solve(ctx, dev(rho2), phi)
+    got = host(phi).reshape(N, N, N)
+    assert rel_l2(got, phi2_ref) < 1e-5
+    assert rel_max(got, phi2_ref) < 1e-5
+    assert rel_l2(phi2_cold, phi2_ref) > 1e-4          # the start made a difference
+    ctx.close()
+
+
 @pytest.mark.parametrize("mu", [0, 1])
 def test_qumond(M, mu):
     # QuMOND (the equivalent system of Sect. 2) is the solve with one
