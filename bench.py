@@ -439,6 +439,20 @@ def main():
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom, w["workload"]), "kernel": dom,
             "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": int(bytes_launch)}
+    # particle kernels against the HBM roofline: algorithmic bytes 16 N + 4 n^3
+    # (positions and masses read, the physical region of rho written) for the
+    # deposit and 48 N + 4 n^3 (positions and velocities read and written, the
+    # physical region of phi read) for the gather with kick and drift
+    n_phys = p["n"]
+    part = {}
+    for k, b in (("deposit", 16 * N_part + 4 * n_phys ** 3), ("gather", 48 * N_part + 4 * n_phys ** 3),
+                 ("sort", None)):
+        if k in timing:
+            t_ms = timing[k][0] / timing[k][1]
+            part[k] = {"avg_launch_ms": round(t_ms, 4), "launches_per_step": timing[k][1] // a.steps}
+            if b is not None:
+                part[k].update(algorithmic_bytes=b, achieved_gbs=round(b / (t_ms * 1e-3) / 1e9, 1),
+                               frac=round(b / (t_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
     out = {
         "metric": METRIC,
         "value": round(1e3 / ms_step, 3),
@@ -459,6 +473,7 @@ def main():
         "ms_per_step_eager": round(ms_eager, 3),
         "particle_updates_per_s": round(N_part * 1e3 / ms_step, 1),
         "roofline": roof,
+        "particle_kernels": part,
     }
     ctx.close()
     out["solver_vs_poisson"] = solver_vs_poisson(w)

@@ -104,17 +104,25 @@ typedef struct {
 
 typedef struct pm_ctx pm_ctx;
 
-/* Bytes of device memory pm_create allocates for these parameters (the
- * spectra, the Newton potential's spectrum, two real grids, sort buffers
- * for max_particles particles and, with PM_F_RESIDUAL or tol > 0, the
- * previous iterate of F). */
+/* Bytes of device memory a context needs for these parameters (the spectra,
+ * the Newton potential's spectrum, two real grids, sort buffers for
+ * max_particles particles, the tables and, with PM_F_RESIDUAL, tol > 0 or
+ * PM_F_WARM_START, the previous iterate of F); 0 for invalid parameters or
+ * max_particles outside [0, 2^30]. */
 size_t pm_workspace_bytes(const pm_params* p, int64_t max_particles);
 
-/* Validates p (host), allocates the workspace on the current HIP device and
- * builds the tables (twiddles, wavevectors, ball offsets).  stream is a
- * hipStream_t (NULL = the default stream).  Synchronises.  On success *out
- * owns the device memory until pm_destroy. */
-pm_status pm_create(const pm_params* p, int64_t max_particles, void* stream, pm_ctx** out);
+/* Validates p (host) and sets up a context on the current HIP device: the
+ * workspace is cut into the context's buffers and the tables (twiddles,
+ * wavevectors, ball offsets) are written into it.  workspace: device memory
+ * of at least pm_workspace_bytes(p, max_particles) bytes, 256-byte aligned,
+ * owned by the caller, which keeps it alive and unused by anything else
+ * until pm_destroy (the library never frees it); NULL makes the library
+ * allocate and own the workspace (PM_E_NOMEM if that fails).  A too small or
+ * misaligned workspace is PM_E_INVAL.  stream is a hipStream_t (NULL = the
+ * default stream).  Synchronises.  max_particles in [0, 2^30] bounds the N of
+ * every later call. */
+pm_status pm_create(const pm_params* p, int64_t max_particles, void* workspace, size_t workspace_bytes,
+                    void* stream, pm_ctx** out);
 pm_status pm_destroy(pm_ctx* ctx);
 
 /* Mass density of Eq. smooth on the FFT box.  rho: device float [n_pad^3],

@@ -43,18 +43,22 @@ struct pm_ctx {
   bool have_F = false;        // fprev holds the last F of a solve
   double* partials = nullptr;
   double* dacc = nullptr;     // [0] |g_N|^2 sum, [1..64] residual sums, [80..89] diagnostics
-  double* hacc = nullptr;     // pinned host copy of dacc
+  double hacc[128] = {};      // host copy of dacc
   float2* tw = nullptr;
   float* kv = nullptr;
   float* kt = nullptr;
   float* kap = nullptr;
   int* ball = nullptr;
+  int nball = 0;
   int* ibuf = nullptr;        // sort buffers
   double* snorm = nullptr;    // per-particle kernel normalisation (pm_step: deposit -> gather)
-  std::vector<void*> allocs;
+  void* owned = nullptr;      // the workspace when the library allocated it
   FftGeom fg{};
   KernelGeom kg{};
   SortBufs sb{};
+  PieceBufs pb{};
+  int piece_ext = 0;          // compiled ball shape of the tile-piece kernels, 0: none
+  int64_t perm_n = -1;        // sb.perm is a permutation of [0, perm_n) from the last sort
   int npartials = 0;
   hipGraphExec_t step_graph = nullptr;  // one captured pm_step (pm_step_capture)
   Dipole dip{};               // external-field sheets added to every Newton solve's density
@@ -114,6 +118,9 @@ static int timer_of(PassKind k) {
 
 static bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
+// Particle indices are 32-bit in the sort buffers and the particle kernels.
+static constexpr int64_t kMaxParticles = (int64_t)1 << 30;
+
 int32_t pm_spectrum_pitch(int32_t n_pad) {
   const int need = n_pad / 2 + 1;
   return (need + 15) & ~15;
@@ -152,64 +159,117 @@ static std::vector<int> make_ball(double R) {
 
 static bool need_residual(const pm_params& p) { return (p.flags & PM_F_RESIDUAL) || p.tol > 0.0; }
 
-size_t pm_workspace_bytes(const pm_params* p, int64_t max_particles) {
-  if (check_params(p) != PM_OK || max_particles < 0) return 0;
-  const size_t N = p->n_pad, P = pm_spectrum_pitch(p->n_pad);
-  const size_t C = N * N * P * sizeof(float2), R = N * N * N * sizeof(float);
-  size_t b = 4 * C + 2 * R;
-  if (need_residual(*p) || (p->flags & PM_F_WARM_START)) b += 3 * R;
+// Device memory of a context: one region (the caller's workspace or a single
+// allocation of the library) cut into 256-byte aligned pieces.  With base ==
+// nullptr only the size is counted.
+struct Carver {
+  char* base = nullptr;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T* ptr = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += (count ? count : 1) * sizeof(T);
+    return ptr;
+  }
+};
+
+// Sizes that follow from the parameters (set before carve).
+static void derive_sizes(pm_ctx* c, const pm_params* p, int64_t max_particles) {
+  c->p = *p;
+  c->N = p->n_pad;
+  c->n = p->n;
+  c->P = pm_spectrum_pitch(p->n_pad);
+  c->max_particles = max_particles;
+  c->nball = (int)make_ball(p->cutoff * p->sigma).size();
+  c->npartials = x_blocks(c->N) > z_blocks(c->N) ? x_blocks(c->N) : z_blocks(c->N);
+  // The tile-piece kernels are compiled for the balls |d|^2 < 16 and < 36
+  // (radius 4 sigma at sigma = 1 and 1.5 cells): any R^2 in (15, 16] or
+  // (35, 36] gives the same integer cells.
+  const double R2 = (p->cutoff * p->sigma) * (p->cutoff * p->sigma);
+  c->piece_ext = (R2 > 15.0 && R2 <= 16.0) ? 3 : (R2 > 35.0 && R2 <= 36.0) ? 5 : 0;
+  c->pb.cap = 0;
+  if (c->piece_ext) {
+    const int64_t N = c->N;
+    const int64_t ntiles = (N / 8) * (N / 8) * (N / 8);
+    const int64_t mp = max_particles > 0 ? max_particles : 1;
+    const int64_t most = max_pieces(ntiles, mp);
+    const int64_t te = 8 + 2 * c->piece_ext;
+    const int64_t by_bytes = ((int64_t)512 << 20) / (te * te * te * 4);    // 512 MB of staging
+    c->pb.cap = (int)(most < by_bytes ? most : by_bytes);
+  }
+}
+
+// Assigns every device buffer of the context from cv; returns the bytes used.
+static size_t carve(pm_ctx* c, Carver& cv) {
+  const size_t N = c->N, C = N * N * (size_t)c->P, R = N * N * N;
   const size_t ntiles = (N / 8) * (N / 8) * (N / 8);
-  b += (size_t)max_particles * 4 * sizeof(int) + (2 * (ntiles + 1) + 4096 + 16) * sizeof(int);
-  return b;
+  const size_t mp = (size_t)(c->max_particles > 0 ? c->max_particles : 1);
+  const size_t nb = (ntiles + 1023) / 1024;
+  c->spec = cv.take<float2>(3 * C);
+  c->phiN = cv.take<float2>(C);
+  c->rho = cv.take<float>(R);
+  c->phi = cv.take<float>(R);
+  c->fprev = (need_residual(c->p) || (c->p.flags & PM_F_WARM_START)) ? cv.take<float>(3 * R) : nullptr;
+  c->partials = cv.take<double>((size_t)c->npartials);
+  c->dacc = cv.take<double>(128);
+  c->tw = cv.take<float2>(N);
+  c->kv = cv.take<float>(N);
+  c->kt = cv.take<float>(N);
+  c->kap = cv.take<float>(N);
+  c->ball = cv.take<int>((size_t)c->nball);
+  c->ibuf = cv.take<int>(4 * mp + 2 * (ntiles + 1) + nb + 16);
+  c->snorm = cv.take<double>(mp);
+  if (c->piece_ext) {
+    c->pb.pc_off = cv.take<int>(ntiles + 1);
+    c->pb.flag = cv.take<int>(ntiles);
+    c->pb.list_off = cv.take<int>(ntiles + 1);
+    c->pb.list = cv.take<int>(ntiles);
+    c->pb.ptile = cv.take<int>((size_t)max_pieces((int64_t)ntiles, (int64_t)mp));
+    c->pb.stage = cv.take<float>(piece_stage_floats(c->piece_ext, c->pb.cap));
+  }
+  return (cv.off + 255) & ~(size_t)255;
+}
+
+size_t pm_workspace_bytes(const pm_params* p, int64_t max_particles) {
+  if (check_params(p) != PM_OK || max_particles < 0 || max_particles > kMaxParticles) return 0;
+  pm_ctx c;
+  derive_sizes(&c, p, max_particles);
+  Carver cv;
+  return carve(&c, cv);
 }
 
 const char* pm_last_error(void) { return g_err; }
-
-template <typename T>
-static pm_status dalloc(pm_ctx* c, T** ptr, size_t count) {
-  void* v = nullptr;
-  if (count == 0) count = 1;
-  hipError_t e = hipMalloc(&v, count * sizeof(T));
-  if (e != hipSuccess) {
-    snprintf(g_err, sizeof g_err, "hipMalloc(%zu bytes): %s", count * sizeof(T), hipGetErrorString(e));
-    return PM_E_NOMEM;
-  }
-  c->allocs.push_back(v);
-  *ptr = static_cast<T*>(v);
-  return PM_OK;
-}
 
 pm_status pm_destroy(pm_ctx* c) {
   if (!c) return PM_OK;
   (void)(c->st ? hipStreamSynchronize(c->st) : hipDeviceSynchronize());
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   if (c->step_graph) (void)hipGraphExecDestroy(c->step_graph);
-  for (void* v : c->allocs) (void)hipFree(v);
-  if (c->hacc) (void)hipHostFree(c->hacc);
+  if (c->owned) (void)hipFree(c->owned);
   delete c;
   return PM_OK;
 }
 
-pm_status pm_create(const pm_params* p, int64_t max_particles, void* stream, pm_ctx** out) {
+pm_status pm_create(const pm_params* p, int64_t max_particles, void* workspace, size_t workspace_bytes,
+                    void* stream, pm_ctx** out) {
   if (!out) return inval("out is NULL");
   *out = nullptr;
   pm_status s = check_params(p);
   if (s != PM_OK) return s;
-  if (max_particles < 0 || max_particles > (int64_t)1 << 31) return inval("max_particles out of range");
+  if (max_particles < 0 || max_particles > kMaxParticles) return inval("max_particles out of range");
+  if (workspace && (reinterpret_cast<uintptr_t>(workspace) & 255u))
+    return inval("workspace must be 256-byte aligned");
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
   hipDeviceProp_t prop;
   HIPCHK(hipGetDeviceProperties(&prop, dev));
 
   pm_ctx* c = new pm_ctx();
-  c->p = *p;
-  c->N = p->n_pad;
-  c->n = p->n;
-  c->P = pm_spectrum_pitch(p->n_pad);
+  derive_sizes(c, p, max_particles);
   c->st = static_cast<hipStream_t>(stream);
-  c->max_particles = max_particles;
   const int N = c->N;
-  const size_t C = (size_t)N * N * c->P, R = (size_t)N * N * N;
+  const size_t C = (size_t)N * N * c->P;
   const double Rb = p->cutoff * p->sigma;
   std::vector<int> ball = make_ball(Rb);
   const int ext = ball_extent(Rb);
@@ -221,33 +281,36 @@ pm_status pm_create(const pm_params* p, int64_t max_particles, void* stream, pm_
     return inval("kernel ball too large for the LDS of this device");
   }
   const int ntiles = (N / 8) * (N / 8) * (N / 8);
-  c->npartials = x_blocks(N) > z_blocks(N) ? x_blocks(N) : z_blocks(N);
-#define ALLOC(ptr, cnt)                       \
-  do {                                        \
-    pm_status s_ = dalloc(c, &(ptr), (cnt));  \
-    if (s_ != PM_OK) { pm_destroy(c); return s_; } \
-  } while (0)
-  ALLOC(c->spec, 3 * C);
-  ALLOC(c->phiN, C);
-  ALLOC(c->rho, R);
-  ALLOC(c->phi, R);
-  if (need_residual(*p) || (p->flags & PM_F_WARM_START)) ALLOC(c->fprev, 3 * R);
-  ALLOC(c->partials, (size_t)c->npartials);
-  ALLOC(c->dacc, 128);
-  ALLOC(c->tw, (size_t)N);
-  ALLOC(c->kv, (size_t)N);
-  ALLOC(c->kt, (size_t)N);
-  ALLOC(c->kap, (size_t)N);
-  ALLOC(c->ball, ball.size());
-  const size_t mp = (size_t)(max_particles > 0 ? max_particles : 1);
-  const size_t nb = ((size_t)ntiles + 1023) / 1024;
-  ALLOC(c->ibuf, 4 * mp + 2 * ((size_t)ntiles + 1) + nb + 16);
-  ALLOC(c->snorm, mp);
-#undef ALLOC
-  if (hipHostMalloc(reinterpret_cast<void**>(&c->hacc), 128 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
-    pm_destroy(c);
-    return dev_fail(hipErrorOutOfMemory, "hipHostMalloc");
+  {
+    Carver count;
+    const size_t need = carve(c, count);
+    Carver cv;
+    if (workspace) {
+      if (workspace_bytes < need) {
+        delete c;
+        snprintf(g_err, sizeof g_err, "invalid argument: workspace has %zu bytes, needs %zu (pm_workspace_bytes)",
+                 workspace_bytes, need);
+        return PM_E_INVAL;
+      }
+      cv.base = static_cast<char*>(workspace);
+    } else {
+      void* v = nullptr;
+      const hipError_t e = hipMalloc(&v, need);
+      if (e != hipSuccess) {
+        delete c;
+        snprintf(g_err, sizeof g_err, "hipMalloc(%zu bytes): %s", need, hipGetErrorString(e));
+        return PM_E_NOMEM;
+      }
+      c->owned = v;
+      cv.base = static_cast<char*>(v);
+    }
+    carve(c, cv);
   }
+#define CCHK(call)                                              \
+  do {                                                          \
+    hipError_t e_ = (call);                                     \
+    if (e_ != hipSuccess) { pm_destroy(c); return dev_fail(e_, #call); } \
+  } while (0)
 
   // tables (FP64 on the host, stored in FP32)
   const double s_px = p->box / p->n;
@@ -262,11 +325,11 @@ pm_status pm_create(const pm_params* p, int64_t max_particles, void* stream, pm_
     kt[t] = (t == N / 2) ? 0.0f : (float)k;
     kap[t] = (t == 0 || t == N / 2) ? 0.0f : (float)(sin(2.0 * M_PI * m / N) / s_px);
   }
-  HIPCHK(hipMemcpy(c->tw, tw.data(), N * sizeof(float2), hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(c->kv, kv.data(), N * sizeof(float), hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(c->kt, kt.data(), N * sizeof(float), hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(c->kap, kap.data(), N * sizeof(float), hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(c->ball, ball.data(), ball.size() * sizeof(int), hipMemcpyHostToDevice));
+  CCHK(hipMemcpyAsync(c->tw, tw.data(), N * sizeof(float2), hipMemcpyHostToDevice, c->st));
+  CCHK(hipMemcpyAsync(c->kv, kv.data(), N * sizeof(float), hipMemcpyHostToDevice, c->st));
+  CCHK(hipMemcpyAsync(c->kt, kt.data(), N * sizeof(float), hipMemcpyHostToDevice, c->st));
+  CCHK(hipMemcpyAsync(c->kap, kap.data(), N * sizeof(float), hipMemcpyHostToDevice, c->st));
+  CCHK(hipMemcpyAsync(c->ball, ball.data(), ball.size() * sizeof(int), hipMemcpyHostToDevice, c->st));
 
   c->fg.N = N;
   c->fg.P = c->P;
@@ -288,7 +351,10 @@ pm_status pm_create(const pm_params* p, int64_t max_particles, void* stream, pm_
     const size_t te = 8 + 2 * (size_t)ext;
     c->kg.private_tiles = (4 * te * te * te * sizeof(float) <= 96 * 1024) ? 1 : 0;
   }
+  c->kg.piece_ext = c->piece_ext;
 
+  const size_t mp = (size_t)(max_particles > 0 ? max_particles : 1);
+  const size_t nb = ((size_t)ntiles + 1023) / 1024;
   int* ib = c->ibuf;
   c->sb.keys = ib; ib += mp;
   c->sb.rank = ib; ib += mp;
@@ -299,8 +365,9 @@ pm_status pm_create(const pm_params* p, int64_t max_particles, void* stream, pm_
   c->sb.blocksums = ib; ib += nb;
   c->sb.flags = ib;
   c->sb.ntiles = ntiles;
-  HIPCHK(hipMemset(c->sb.flags, 0, 16 * sizeof(int)));
-  HIPCHK(hipDeviceSynchronize());
+  CCHK(fill_zero(reinterpret_cast<float*>(c->sb.flags), 16, c->st));
+  CCHK(c->st ? hipStreamSynchronize(c->st) : hipDeviceSynchronize());
+#undef CCHK
   *out = c;
   return PM_OK;
 }
@@ -458,6 +525,29 @@ static pm_status run_solve(pm_ctx* c, const float* rho, const float* H0, float* 
   return PM_OK;
 }
 
+// Tile sort of the particles, then (tile-piece kernels) the piece plan.
+static hipError_t sort_and_plan(pm_ctx* c, const float* pos, int64_t n) {
+  Timed t(c, PM_T_SORT);
+  hipError_t e = sort_particles(c->kg, c->sb, pos, n, c->st, c->perm_n == n);
+  c->perm_n = (e == hipSuccess) ? n : -1;
+  if (e == hipSuccess && c->piece_ext && n > 0) e = piece_plan(c->pb, c->sb, c->N, c->st);
+  return e;
+}
+
+static hipError_t deposit_any(pm_ctx* c, const float* pos, const float* mass, int64_t n, float* rho,
+                              double* s_store) {
+  Timed t(c, PM_T_DEPOSIT);
+  if (c->piece_ext) return deposit_pieces(c->kg, c->sb, c->pb, pos, mass, n, rho, c->st);
+  return deposit_sorted(c->kg, c->sb, pos, mass, n, rho, s_store, c->st);
+}
+
+static hipError_t gather_any(pm_ctx* c, const float* phi, float* pos, float* vel, float* acc, int64_t n,
+                             float dt_kick, float dt_drift, int mode, const double* s_store) {
+  Timed t(c, PM_T_GATHER);
+  if (c->piece_ext) return gather_pieces(c->kg, c->sb, c->pb, phi, pos, vel, acc, n, dt_kick, dt_drift, mode, c->st);
+  return gather_sorted(c->kg, c->sb, phi, pos, vel, acc, n, dt_kick, dt_drift, mode, s_store, c->st);
+}
+
 static pm_status check_ctx(pm_ctx* c, int64_t n) {
   if (!c) return inval("ctx is NULL");
   if (n < 0 || n > c->max_particles) return inval("particle count exceeds max_particles");
@@ -478,8 +568,8 @@ pm_status pm_deposit(pm_ctx* c, const float* pos, const float* mass, int64_t n, 
   if (!rho || (n > 0 && (!pos || !mass))) return inval("NULL buffer");
   const long long R = (long long)c->N * c->N * c->N;
   { Timed t(c, PM_T_FILL); HIPCHK(fill_zero(rho, R, c->st)); }
-  { Timed t(c, PM_T_SORT); HIPCHK(sort_particles(c->kg, c->sb, pos, n, c->st)); }
-  { Timed t(c, PM_T_DEPOSIT); HIPCHK(deposit_sorted(c->kg, c->sb, pos, mass, n, rho, nullptr, c->st)); }
+  HIPCHK(sort_and_plan(c, pos, n));
+  HIPCHK(deposit_any(c, pos, mass, n, rho, nullptr));
   return PM_OK;
 }
 
@@ -487,10 +577,8 @@ pm_status smooth_accel(pm_ctx* c, const float* phi, const float* pos, int64_t n,
   pm_status s = check_ctx(c, n);
   if (s != PM_OK) return s;
   if (!phi || (n > 0 && (!pos || !acc))) return inval("NULL buffer");
-  { Timed t(c, PM_T_SORT); HIPCHK(sort_particles(c->kg, c->sb, pos, n, c->st)); }
-  { Timed t(c, PM_T_GATHER);
-    HIPCHK(gather_sorted(c->kg, c->sb, phi, const_cast<float*>(pos), nullptr, acc, n, 0.f, 0.f, 0, nullptr,
-                         c->st)); }
+  HIPCHK(sort_and_plan(c, pos, n));
+  HIPCHK(gather_any(c, phi, const_cast<float*>(pos), nullptr, acc, n, 0.f, 0.f, 0, nullptr));
   return PM_OK;
 }
 
@@ -499,10 +587,8 @@ pm_status interp_push(pm_ctx* c, const float* phi, float* pos, float* vel, int64
   pm_status s = check_ctx(c, n);
   if (s != PM_OK) return s;
   if (!phi || (n > 0 && (!pos || !vel))) return inval("NULL buffer");
-  { Timed t(c, PM_T_SORT); HIPCHK(sort_particles(c->kg, c->sb, pos, n, c->st)); }
-  { Timed t(c, PM_T_GATHER);
-    HIPCHK(gather_sorted(c->kg, c->sb, phi, pos, vel, nullptr, n, (float)dt_kick, (float)dt_drift, 1, nullptr,
-                         c->st)); }
+  HIPCHK(sort_and_plan(c, pos, n));
+  HIPCHK(gather_any(c, phi, pos, vel, nullptr, n, (float)dt_kick, (float)dt_drift, 1, nullptr));
   return PM_OK;
 }
 
@@ -514,12 +600,11 @@ pm_status pm_step(pm_ctx* c, float* pos, float* vel, const float* mass, int64_t 
   const long long R = (long long)c->N * c->N * c->N;
   if (info) HIPCHK(fill_zero(reinterpret_cast<float*>(c->sb.flags), 1, c->st));
   { Timed t(c, PM_T_FILL); HIPCHK(fill_zero(c->rho, R, c->st)); }
-  { Timed t(c, PM_T_SORT); HIPCHK(sort_particles(c->kg, c->sb, pos, n, c->st)); }
-  { Timed t(c, PM_T_DEPOSIT); HIPCHK(deposit_sorted(c->kg, c->sb, pos, mass, n, c->rho, c->snorm, c->st)); }
+  HIPCHK(sort_and_plan(c, pos, n));
+  HIPCHK(deposit_any(c, pos, mass, n, c->rho, c->snorm));
   s = run_solve(c, c->rho, nullptr, c->phi, info, info != nullptr);
   if (s != PM_OK) return s;
-  { Timed t(c, PM_T_GATHER);
-    HIPCHK(gather_sorted(c->kg, c->sb, c->phi, pos, vel, nullptr, n, (float)dt, (float)dt, 1, c->snorm, c->st)); }
+  HIPCHK(gather_any(c, c->phi, pos, vel, nullptr, n, (float)dt, (float)dt, 1, c->snorm));
   if (info) {
     int flag = 0;
     HIPCHK(hipMemcpyAsync(&flag, c->sb.flags, sizeof(int), hipMemcpyDeviceToHost, c->st));

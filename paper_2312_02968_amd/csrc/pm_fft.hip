@@ -52,7 +52,7 @@ __device__ __forceinline__ long long sidx(long long row, int k, long long NN) {
 // x pass
 // ----------------------------------------------------------------------------
 // XMODE
-enum { X_FWD_REAL = 0, X_INV_REAL = 1, X_FUSED_NU = 2, X_FUSED_MU = 3 };
+enum { X_FWD_REAL = 0, X_INV_REAL = 1, X_FUSED_NU = 2, X_FUSED_MU = 3, X_FUSED_NU_KEEP = 4 };
 
 // r2c split: LDS holds Z = FFT_H(x[2m] + i x[2m+1]) for each sequence; turn
 // it into X[k], k = 0..H (X[H] goes to element H, one past the complex data).
@@ -121,9 +121,9 @@ __device__ __forceinline__ void add_dipole(float2& x, const Dipole& dip, long lo
 //   X_FWD_REAL : real rows (float, row pitch 2H) -> spectrum rows
 //   X_INV_REAL : spectrum rows -> real rows
 //   X_FUSED_*  : spectrum rows -> c2r -> nu or mu on the 3-vector -> r2c ->
-//                spectrum rows (in place).  With fprev != nullptr (X_FUSED_NU)
-//                the squared change of F against fprev is accumulated in FP64
-//                into partials[blockIdx.x] and F is stored to fprev.
+//                spectrum rows (in place).  X_FUSED_NU_KEEP is X_FUSED_NU that
+//                also accumulates the squared change of F against fprev in
+//                FP64 into partials[blockIdx.x] and stores F to fprev.
 template <int H, int ROWS, int NC, int NT, int XMODE>
 __global__ __launch_bounds__(NT) void k_xpass(float2* spec, long long comp_stride,
                                               float* real, long long real_comp_stride,
@@ -166,12 +166,12 @@ __global__ __launch_bounds__(NT) void k_xpass(float2* spec, long long comp_strid
     block_fft<H, S, NT, true, true>(lds, 1, IS, tw_s, 2);
   }
 
-  if (XMODE == X_FUSED_NU || XMODE == X_FUSED_MU) {
+  if (XMODE == X_FUSED_NU || XMODE == X_FUSED_NU_KEEP || XMODE == X_FUSED_MU) {
     double acc = 0.0;
     for (int b = threadIdx.x; b < ROWS * H; b += NT) {
       const int r = b % ROWS, m = b / ROWS;
       float2 v0 = lds[m * IS + r], v1 = lds[m * IS + ROWS + r], v2 = lds[m * IS + 2 * ROWS + r];
-      if (XMODE == X_FUSED_NU && fprev != nullptr) {
+      if (XMODE == X_FUSED_NU_KEEP) {
         const long long e = (long long)(row0 + r) * N + 2 * m;
         const long long cs = (long long)N * N * N;
         float2* f0 = reinterpret_cast<float2*>(fprev + e);
@@ -186,19 +186,19 @@ __global__ __launch_bounds__(NT) void k_xpass(float2* spec, long long comp_strid
       // two grid points per complex entry: .x is x = 2m, .y is x = 2m+1
       {
         const float m0 = sqrtf(v0.x * v0.x + v1.x * v1.x + v2.x * v2.x);
-        const float f = (XMODE == X_FUSED_NU) ? nu_ratio(mu_mode, m0, inv_a0) : mu_ratio(mu_mode, m0, inv_a0);
+        const float f = (XMODE != X_FUSED_MU) ? nu_ratio(mu_mode, m0, inv_a0) : mu_ratio(mu_mode, m0, inv_a0);
         v0.x *= f; v1.x *= f; v2.x *= f;
       }
       {
         const float m1 = sqrtf(v0.y * v0.y + v1.y * v1.y + v2.y * v2.y);
-        const float f = (XMODE == X_FUSED_NU) ? nu_ratio(mu_mode, m1, inv_a0) : mu_ratio(mu_mode, m1, inv_a0);
+        const float f = (XMODE != X_FUSED_MU) ? nu_ratio(mu_mode, m1, inv_a0) : mu_ratio(mu_mode, m1, inv_a0);
         v0.y *= f; v1.y *= f; v2.y *= f;
       }
       lds[m * IS + r] = v0;
       lds[m * IS + ROWS + r] = v1;
       lds[m * IS + 2 * ROWS + r] = v2;
     }
-    if (XMODE == X_FUSED_NU && fprev != nullptr) {
+    if (XMODE == X_FUSED_NU_KEEP) {
       // block reduction of acc (FP64)
       __shared__ double red[NT / 64];
       for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
@@ -318,23 +318,90 @@ __device__ __forceinline__ void fft512_wave(float2* v, float2* xb, int j, const 
   Dft<8, INV>::run(v);
 }
 
+// 256-point FFT of a row held by 32 lanes, v[r] = x[j + 32 r] (j = lane in
+// the row, r < 8); result in the same layout.  With x = j + 32 r and
+// k = s + 8 q1 + 64 q2: a radix-8 DFT over r (giving s), twiddles
+// w_256^(j s); then, for each s, the 32-point DFT over j = j1 + 4 j2 as a
+// radix-8 DFT over j2 (giving q1), twiddles w_32^(j1 q1) and a radix-4 DFT
+// over j1 (giving q2).  After the first exchange lane s + 8 j1 holds the 8
+// values j2; after the second, lane s + 8 m holds the 4 values j1 of q1 = m
+// and of q1 = m + 4, so the two radix-4 DFTs leave X[lane + 32 (h + 2 q2)]
+// in v[4 h + q2], which a register permutation puts back at r = h + 2 q2.
+// xb: the row's 272-entry LDS row; tw_s: the 512-entry table w_512^t.
+template <bool INV>
+__device__ __forceinline__ void fft256_lane32(float2* v, float2* xb, int j, const float2* tw_s) {
+  Dft<8, INV>::run(v);
+#pragma unroll
+  for (int s = 1; s < 8; ++s) {
+    float2 w = tw_s[2 * j * s];                          // w_256^(j s)
+    if (INV) w.y = -w.y;
+    v[s] = cmul(v[s], w);
+  }
+#pragma unroll
+  for (int s = 0; s < 8; ++s) xb[xpad(32 * s + j)] = v[s];
+  wave_sync();
+  const int s = j & 7, hi = j >> 3;                      // hi: j1 now, m after the second exchange
+#pragma unroll
+  for (int r = 0; r < 8; ++r) v[r] = xb[xpad(32 * s + hi + 4 * r)];
+  wave_sync();
+  Dft<8, INV>::run(v);
+#pragma unroll
+  for (int q = 1; q < 8; ++q) {
+    float2 w = tw_s[16 * hi * q];                        // w_32^(j1 q1)
+    if (INV) w.y = -w.y;
+    v[q] = cmul(v[q], w);
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) xb[xpad(32 * s + 4 * q + hi)] = v[q];
+  wave_sync();
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int a = 0; a < 4; ++a) v[4 * h + a] = xb[xpad(32 * s + 4 * (hi + 4 * h) + a)];
+  wave_sync();
+  Dft<4, INV>::run(v);
+  Dft<4, INV>::run(v + 4);
+  float2 t[8];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) t[h + 2 * q] = v[4 * h + q];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) v[r] = t[r];
+}
+
+#ifndef PM_X256_LANES
+#define PM_X256_LANES 32
+#endif
+
 template <int H>
 struct XWave {
   static constexpr int N = 2 * H;
-  static constexpr int LANES = (H == 256) ? 16 : 64;
+  static constexpr int LANES = (H == 256) ? PM_X256_LANES : 64;
   static constexpr int RG = H / LANES;              // elements per lane and component
   static constexpr int G = 64 / LANES;              // rows per wave
   static constexpr int ROWS = 4 * G;                // rows per block (4 waves)
   static constexpr int XB = H + H / 16;             // padded LDS row (xpad)
   template <bool INV>
   __device__ __forceinline__ static void fft(float2* v, float2* xb, int j, const float2* tw_s) {
-    if constexpr (H == 256) fft256_group<INV>(v, xb, j, tw_s);
+    if constexpr (H == 256 && LANES == 16) fft256_group<INV>(v, xb, j, tw_s);
+    else if constexpr (H == 256) fft256_lane32<INV>(v, xb, j, tw_s);
     else fft512_wave<INV>(v, xb, j, tw_s);
   }
 };
 
+// Occupancy floor (waves per SIMD) asked of the compiler for the fused
+// 256-point passes; 1 leaves the register allocation free.
+#ifndef PM_X256_WAVES
+#define PM_X256_WAVES 1
+#endif
+template <int H, int XMODE>
+struct XWaves {
+  static constexpr int value = (H == 256 && (XMODE == X_FUSED_NU || XMODE == X_FUSED_MU)) ? PM_X256_WAVES : 1;
+};
+
 template <int H, int XMODE, int NC>
-__global__ __launch_bounds__(256) void k_xpass_wave(float2* spec, long long comp_stride, float* real,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(XWaves<H, XMODE>::value))) void k_xpass_wave(float2* spec, long long comp_stride, float* real,
                                                     long long real_comp_stride, const float2* __restrict__ tw,
                                                     int mu_mode, float inv_a0, float* fprev, double* partials,
                                                     Dipole dip) {
@@ -389,12 +456,12 @@ __global__ __launch_bounds__(256) void k_xpass_wave(float2* spec, long long comp
     for (int c = 0; c < NC; ++c) X::template fft<true>(v[c], xb, j, tw_s);
   }
 
-  if constexpr (XMODE == X_FUSED_NU || XMODE == X_FUSED_MU) {
+  if constexpr (XMODE == X_FUSED_NU || XMODE == X_FUSED_NU_KEEP || XMODE == X_FUSED_MU) {
     double acc = 0.0;
 #pragma unroll
     for (int r = 0; r < RG; ++r) {
       float2 a0 = v[0][r], a1 = v[1][r], a2 = v[2][r];
-      if (XMODE == X_FUSED_NU && fprev != nullptr) {
+      if (XMODE == X_FUSED_NU_KEEP) {
         const long long e = row * N + 2 * (j + LANES * r);
         const long long cs = (long long)N * N * N;
         float2* f0 = reinterpret_cast<float2*>(fprev + e);
@@ -408,13 +475,13 @@ __global__ __launch_bounds__(256) void k_xpass_wave(float2* spec, long long comp
       }
       const float m0 = sqrtf(a0.x * a0.x + a1.x * a1.x + a2.x * a2.x);
       const float m1 = sqrtf(a0.y * a0.y + a1.y * a1.y + a2.y * a2.y);
-      const float f0 = (XMODE == X_FUSED_NU) ? nu_ratio(mu_mode, m0, inv_a0) : mu_ratio(mu_mode, m0, inv_a0);
-      const float f1 = (XMODE == X_FUSED_NU) ? nu_ratio(mu_mode, m1, inv_a0) : mu_ratio(mu_mode, m1, inv_a0);
+      const float f0 = (XMODE != X_FUSED_MU) ? nu_ratio(mu_mode, m0, inv_a0) : mu_ratio(mu_mode, m0, inv_a0);
+      const float f1 = (XMODE != X_FUSED_MU) ? nu_ratio(mu_mode, m1, inv_a0) : mu_ratio(mu_mode, m1, inv_a0);
       v[0][r] = make_float2(a0.x * f0, a0.y * f1);
       v[1][r] = make_float2(a1.x * f0, a1.y * f1);
       v[2][r] = make_float2(a2.x * f0, a2.y * f1);
     }
-    if (XMODE == X_FUSED_NU && fprev != nullptr) {
+    if (XMODE == X_FUSED_NU_KEEP) {
       __shared__ double red[4];
       for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
       if (lane == 0) red[wave] = acc;
@@ -884,7 +951,9 @@ hipError_t run_pass(const FftGeom& g, const PassDesc& d, hipStream_t st) {
     case PASS_X_INV_REAL:
       return launch_x<N, X_INV_REAL, 1>(g, d.spec, d.real, d.real_cs, 0, 0.f, nullptr, nullptr, st);
     case PASS_X_NU:
-      return launch_x<N, X_FUSED_NU, 3>(g, d.spec, nullptr, 0, d.mu_mode, d.inv_a0, d.fprev, d.partials, st);
+      if (d.fprev)
+        return launch_x<N, X_FUSED_NU_KEEP, 3>(g, d.spec, nullptr, 0, d.mu_mode, d.inv_a0, d.fprev, d.partials, st);
+      return launch_x<N, X_FUSED_NU, 3>(g, d.spec, nullptr, 0, d.mu_mode, d.inv_a0, nullptr, nullptr, st);
     case PASS_X_MU:
       return launch_x<N, X_FUSED_MU, 3>(g, d.spec, nullptr, 0, d.mu_mode, d.inv_a0, nullptr, nullptr, st);
     case PASS_Y_FWD: return launch_y<N, false>(g, d.spec, d.ncomp, st);

@@ -77,6 +77,8 @@ struct KernelGeom {
   int analytic;     // literal prefactor instead of the ball-sum normalisation
   double analytic_norm;  // (2 pi)^1.5 sigma^3
   int private_tiles;     // deposit: one LDS tile copy per wave (no LDS atomics)
+  int piece_ext;         // 3 or 5: the ball has a compiled shape (radius 4 at sigma 1
+                         // or 1.5) and the tile-piece kernels run; 0: generic kernels
 };
 
 struct SortBufs {
@@ -91,8 +93,36 @@ struct SortBufs {
   int* flags;       // [0]: bounds violations
 };
 
+// Tile pieces (pm_pieces.hip): a tile's sorted particles in runs of at most
+// kPiece, each deposited into its own staging slot (slots < cap) or straight
+// into rho with atomics (slots >= cap).
+constexpr int kPiece = 2048;
+struct PieceBufs {
+  int* pc_off;      // [ntiles + 1] first piece of each tile (exclusive scan)
+  int* flag;        // [ntiles] scratch: pieces per tile, then destination flags
+  int* list_off;    // [ntiles + 1] exclusive scan of the destination flags
+  int* list;        // [ntiles] tiles that receive staged cells
+  int* ptile;       // [pieces] tile of each piece
+  float* stage;     // [cap][TE^3] staged halo boxes
+  int cap;
+};
+// most pieces a sort of n particles into ntiles tiles can make
+inline int64_t max_pieces(int64_t ntiles, int64_t n) { return (ntiles < n ? ntiles : n) + n / kPiece + 1; }
+// staging floats for cap pieces of a ball with the given extent
+size_t piece_stage_floats(int ext, int cap);
+hipError_t piece_plan(const PieceBufs& pb, const SortBufs& sb, int N, hipStream_t st);
+hipError_t deposit_pieces(const KernelGeom& kg, const SortBufs& sb, const PieceBufs& pb, const float* pos,
+                          const float* mass, int64_t n, float* rho, hipStream_t st);
+hipError_t gather_pieces(const KernelGeom& kg, const SortBufs& sb, const PieceBufs& pb, const float* phi,
+                         float* pos, float* vel, float* acc, int64_t n, float dt_kick, float dt_drift, int mode,
+                         hipStream_t st);
+// out[0..n) = exclusive scan of in[0..n), out[n] = total (n <= 4096 * 1024)
+hipError_t scan_exclusive(const int* in, int n, int* out, int* blocksums, hipStream_t st);
+
+// prev_order: sb.perm holds the previous sort's permutation of these n
+// particles (it is read as the processing order, then replaced)
 hipError_t sort_particles(const KernelGeom& kg, const SortBufs& sb, const float* pos, int64_t n,
-                          hipStream_t st);
+                          hipStream_t st, bool prev_order = false);
 // s_store (nullable): receives each particle's kernel normalisation (FP64)
 hipError_t deposit_sorted(const KernelGeom& kg, const SortBufs& sb, const float* pos, const float* mass,
                           int64_t n, float* rho, double* s_store, hipStream_t st);

@@ -92,7 +92,7 @@ __device__ __forceinline__ Part particle_setup(const KernelGeom& kg, const int* 
 }
 
 __device__ __forceinline__ Part particle_setup(const KernelGeom& kg, const int* __restrict__ ball_lds,
-                                               const float* __restrict__ pos, int i, int lane) {
+                                               const float* __restrict__ pos, int64_t i, int lane) {
   return particle_setup(kg, ball_lds, pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], lane);
 }
 
@@ -102,11 +102,15 @@ __device__ __forceinline__ Part particle_setup(const KernelGeom& kg, const int* 
 // by key: one lane per distinct key adds the group size, and each lane takes
 // the base plus the number of lower lanes in its group (any order within a
 // tile is a valid rank order).
+// order (nullable) is the previous sort's permutation of the same particles:
+// particles move little between steps, so taking them in that order gives a
+// wave few distinct tiles and few atomics.
 __global__ __launch_bounds__(256) void k_keys(const float* __restrict__ pos, int64_t n, int N, int nphys,
-                                              double inv_s, int ext, int* keys, int* rank, int* counts,
-                                              int* flags) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool valid = i < n;
+                                              double inv_s, int ext, const int* __restrict__ order, int* keys,
+                                              int* rank, int* counts, int* flags) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = j < n;
+  const int64_t i = valid ? (order ? (int64_t)order[j] : j) : 0;
   const int lane = threadIdx.x & 63;
   const int half = N / 2;
   int key = -1;
@@ -309,8 +313,9 @@ __global__ __launch_bounds__(kNT) void k_deposit(KernelGeom kg, const int* __res
   for (int jb = wave * 64; jb < pl.nsparse; jb += kWaves * 64) {
     const bool has = jb + lane < pl.nsparse;
     const int il = has ? perm[pl.sparse[jb + lane]] : 0;
-    const float xl = has ? pos[3 * il] : 0.f, yl = has ? pos[3 * il + 1] : 0.f,
-                zl = has ? pos[3 * il + 2] : 0.f, ml = has ? mass[il] : 0.f;
+    const int64_t i3 = 3 * (int64_t)il;
+    const float xl = has ? pos[i3] : 0.f, yl = has ? pos[i3 + 1] : 0.f,
+                zl = has ? pos[i3 + 2] : 0.f, ml = has ? mass[il] : 0.f;
     const int nb = min(64, pl.nsparse - jb);
     for (int t = 0; t < nb; ++t) {
       const int it_ = __shfl(il, t, 64);
@@ -331,8 +336,9 @@ __global__ __launch_bounds__(kNT) void k_deposit(KernelGeom kg, const int* __res
       const int jl = jb + kWaves * lane;
       const bool has = jl < pe;
       const int il = has ? perm[jl] : 0;
-      const float xl = has ? pos[3 * il] : 0.f, yl = has ? pos[3 * il + 1] : 0.f,
-                  zl = has ? pos[3 * il + 2] : 0.f, ml = has ? mass[il] : 0.f;
+      const int64_t i3 = 3 * (int64_t)il;
+      const float xl = has ? pos[i3] : 0.f, yl = has ? pos[i3 + 1] : 0.f,
+                  zl = has ? pos[i3 + 2] : 0.f, ml = has ? mass[il] : 0.f;
       const int nb = min(64, (pe - jb + kWaves - 1) / kWaves);
       for (int u = 0; u < nb; ++u) {
         const int iu = __shfl(il, u, 64);
@@ -405,7 +411,7 @@ __device__ __forceinline__ float3 gather_one(const KernelGeom& kg, const int* __
 }
 
 // Writes the result of lane's particle il (acceleration, or kick + drift).
-__device__ __forceinline__ void gather_store(int il, float3 g, float x, float y, float z, float* pos, float* vel,
+__device__ __forceinline__ void gather_store(int64_t il, float3 g, float x, float y, float z, float* pos, float* vel,
                                              float* acc, float dt_kick, float dt_drift, int mode) {
   if (mode == 0) {
     acc[3 * il] = g.x;
@@ -450,8 +456,9 @@ __global__ __launch_bounds__(kNT) void k_gather(KernelGeom kg, const int* __rest
   for (int jb = wave * 64; jb < pl.nsparse; jb += kWaves * 64) {
     const bool has = jb + lane < pl.nsparse;
     const int il = has ? perm[pl.sparse[jb + lane]] : 0;
-    const float xl = has ? pos[3 * il] : 0.f, yl = has ? pos[3 * il + 1] : 0.f,
-                zl = has ? pos[3 * il + 2] : 0.f;
+    const int64_t i3 = 3 * (int64_t)il;
+    const float xl = has ? pos[i3] : 0.f, yl = has ? pos[i3 + 1] : 0.f,
+                zl = has ? pos[i3 + 2] : 0.f;
     const double sl = (has && s_store) ? s_store[il] : 0.0;
     float3 mine = make_float3(0.f, 0.f, 0.f);
     const int nb = min(64, pl.nsparse - jb);
@@ -477,8 +484,9 @@ __global__ __launch_bounds__(kNT) void k_gather(KernelGeom kg, const int* __rest
       const int jl = jb + kWaves * lane;
       const bool has = jl < pe;
       const int il = has ? perm[jl] : 0;
-      const float xl = has ? pos[3 * il] : 0.f, yl = has ? pos[3 * il + 1] : 0.f,
-                  zl = has ? pos[3 * il + 2] : 0.f;
+      const int64_t i3 = 3 * (int64_t)il;
+      const float xl = has ? pos[i3] : 0.f, yl = has ? pos[i3 + 1] : 0.f,
+                  zl = has ? pos[i3 + 2] : 0.f;
       const double sl = (has && s_store) ? s_store[il] : 0.0;
       float3 mine = make_float3(0.f, 0.f, 0.f);
       const int nb = min(64, (pe - jb + kWaves - 1) / kWaves);
@@ -532,7 +540,7 @@ __global__ __launch_bounds__(kNT) void k_diag_phi(KernelGeom kg, const float* __
   const int N = kg.N;
   double tot = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * kWaves + wave; i < n; i += (int64_t)gridDim.x * kWaves) {
-    const Part p = particle_setup(kg, ball, pos, (int)i, lane);
+    const Part p = particle_setup(kg, ball, pos, i, lane);
     const double norm = kg.analytic ? kg.analytic_norm : p.S;
     double acc = 0.0;
     const int nit = (kg.nball + 63) / 64;
@@ -564,19 +572,24 @@ hipError_t fill_zero(float* p, long long count, hipStream_t st) {
   return hipGetLastError();
 }
 
+hipError_t scan_exclusive(const int* in, int n, int* out, int* blocksums, hipStream_t st) {
+  const int nb = (n + 1023) / 1024;
+  hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(1024), 0, st, in, n, out, blocksums);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, blocksums, nb, out + n);
+  hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(1024), 0, st, out, n, blocksums);
+  return hipGetLastError();
+}
+
 hipError_t sort_particles(const KernelGeom& kg, const SortBufs& sb, const float* pos, int64_t n,
-                          hipStream_t st) {
+                          hipStream_t st, bool prev_order) {
   hipError_t e = fill_zero(reinterpret_cast<float*>(sb.counts), sb.ntiles + 1, st);
   if (e != hipSuccess) return e;
   if (n > 0) {
     hipLaunchKernelGGL(k_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, pos, n, kg.N, kg.n,
-                       kg.inv_s, kg.ext, sb.keys, sb.rank, sb.counts, sb.flags);
+                       kg.inv_s, kg.ext, prev_order ? sb.perm : nullptr, sb.keys, sb.rank, sb.counts, sb.flags);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  const int nb = (sb.ntiles + 1023) / 1024;
-  hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(1024), 0, st, sb.counts, sb.ntiles, sb.offsets, sb.blocksums);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, sb.blocksums, nb, sb.offsets + sb.ntiles);
-  hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(1024), 0, st, sb.offsets, sb.ntiles, sb.blocksums);
+  if ((e = scan_exclusive(sb.counts, sb.ntiles, sb.offsets, sb.blocksums, st)) != hipSuccess) return e;
   if (n > 0) {
     hipLaunchKernelGGL(k_scatter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, sb.keys, sb.rank,
                        sb.offsets, sb.perm, sb.skey);

@@ -13,7 +13,9 @@ import os
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmondpm.so")
+# MONDPM_LIB names another build of the same library (for timing build
+# variants side by side); by default the in-tree build is loaded.
+LIB_PATH = os.environ.get("MONDPM_LIB") or os.path.join(_HERE, "libmondpm.so")
 
 PM_MU_STANDARD, PM_MU_DEEP, PM_MU_NEWTON = 0, 1, 2
 PM_OK, PM_E_INVAL, PM_E_DEVICE, PM_E_NOMEM, PM_E_BOUNDS, PM_E_NOTCONV, PM_E_NONFINITE = 0, -1, -2, -3, -4, -5, -6
@@ -57,7 +59,7 @@ def lib():
         P, VP, I64, D = ctypes.POINTER, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double
         L.pm_workspace_bytes.argtypes = [P(PmParams), I64]
         L.pm_workspace_bytes.restype = ctypes.c_size_t
-        L.pm_create.argtypes = [P(PmParams), I64, VP, P(VP)]
+        L.pm_create.argtypes = [P(PmParams), I64, VP, ctypes.c_size_t, VP, P(VP)]
         L.pm_destroy.argtypes = [VP]
         L.pm_deposit.argtypes = [VP, VP, VP, I64, VP]
         L.aqual_solve.argtypes = [VP, VP, VP, VP, P(PmSolveInfo)]
@@ -143,16 +145,30 @@ def _ptr(t, dtype=torch.float32, numel=None, name="tensor"):
 
 
 class Ctx:
-    """Owns a pm_ctx (device workspace) bound to a stream."""
+    """Owns a pm_ctx bound to a stream.  By default its workspace is a torch
+    tensor (caller-owned device memory, as the C ABI expects); with
+    workspace="library" the library allocates it instead."""
 
-    def __init__(self, params, max_particles=0, stream=None):
+    def __init__(self, params, max_particles=0, stream=None, workspace="torch"):
         self.params = dict(params)
         self._p = make_params(params)
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
+        self.workspace = None
+        ws_ptr, ws_bytes = None, 0
+        if workspace == "torch":
+            ws_bytes = int(lib().pm_workspace_bytes(ctypes.byref(self._p), int(max_particles)))
+            if ws_bytes == 0:
+                _check(PM_E_INVAL, "pm_workspace_bytes")
+            # 256 spare bytes to align the start
+            self.workspace = torch.empty(ws_bytes + 256, dtype=torch.uint8, device="cuda")
+            base = self.workspace.data_ptr()
+            ws_ptr = ctypes.c_void_p((base + 255) & ~255)
+        elif workspace != "library":
+            raise ValueError("workspace must be 'torch' or 'library'")
         h = ctypes.c_void_p()
-        _check(lib().pm_create(ctypes.byref(self._p), int(max_particles),
+        _check(lib().pm_create(ctypes.byref(self._p), int(max_particles), ws_ptr, ws_bytes,
                                ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)), "pm_create")
         self.handle = h
         self.max_particles = int(max_particles)
@@ -162,6 +178,7 @@ class Ctx:
         if getattr(self, "handle", None):
             lib().pm_destroy(self.handle)
             self.handle = None
+        self.workspace = None
 
     def __del__(self):
         try:
@@ -170,8 +187,8 @@ class Ctx:
             pass
 
 
-def pm_create(params, max_particles=0, stream=None) -> Ctx:
-    return Ctx(params, max_particles, stream)
+def pm_create(params, max_particles=0, stream=None, workspace="torch") -> Ctx:
+    return Ctx(params, max_particles, stream, workspace)
 
 
 def pm_destroy(ctx: Ctx):

@@ -52,3 +52,16 @@ def test_net_parameter_layout_and_argument_checks_without_gpu():
     assert L.pm_net_create(12, 1, None, C.byref(h)) == M.PM_E_INVAL      # not a power of two
     assert L.pm_net_create(16, 0, None, C.byref(h)) == M.PM_E_INVAL      # no slots
     assert L.pm_net_create(4, 1, None, C.byref(h)) == M.PM_E_INVAL       # too small for 3 levels
+
+
+def test_workspace_argument_checks_without_gpu():
+    import ctypes as C
+    from paper_2312_02968_amd import mondpm as M
+    import workloads as W
+    L = M.lib()
+    p = M.make_params(W.params(64))
+    h = C.c_void_p()
+    # a misaligned caller workspace is refused before any device call
+    assert L.pm_create(C.byref(p), 0, C.c_void_p(0x1000 + 8), 1 << 30, None, C.byref(h)) == M.PM_E_INVAL
+    assert L.pm_create(C.byref(p), -1, None, 0, None, C.byref(h)) == M.PM_E_INVAL
+    assert M.pm_workspace_bytes(W.params(64), (1 << 30) + 1) == 0

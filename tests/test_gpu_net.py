@@ -308,3 +308,37 @@ def test_trained_network_gains_over_the_zero_start(case):
     assert err[1][1] < 0.5 * err[1][0]
     assert err[2][1] < err[2][0]
     net.close()
+
+
+@pytest.mark.parametrize("weights", ["nan", "zero"])
+def test_learned_start_falls_back_to_the_zero_start(weights):
+    # The learned path in tolerance mode judges its own solve: non-finite
+    # weights give a non-finite start, the solve from it is rejected and the
+    # plain solve from H = 0 runs instead, reaching the tolerance with the
+    # plain result.  Zero weights give the start H0 = 0, whose solve is the
+    # plain one and is kept.
+    from paper_2312_02968_amd import learned as L
+    w = W.random_cloud(4, 32, 400, mu=W.MU_STANDARD)
+    p = dict(w["params"], iters=30, tol=2e-3)
+    N = p["n_pad"]
+    ctx = M.pm_create(p, 400)
+    rho = grid(N)
+    M.pm_deposit(ctx, dev(w["pos"]), dev(w["mass"]), rho)
+    phi_plain = grid(N)
+    ip = M.aqual_solve(ctx, rho, phi_plain)
+    assert ip["status"] == M.PM_OK
+    net = M.Net(N // 2, 1)
+    v = np.full(M.pm_net_param_count(), np.nan if weights == "nan" else 0.0, dtype=np.float32)
+    M.pm_net_set_params(net, v)
+    phiN, phi = grid(N), grid(N)
+    H0 = torch.empty(3 * N ** 3, device="cuda")
+    info, fell_back = L.learned_solve_tol(ctx, net, rho, phiN, H0, phi)
+    assert info["status"] == M.PM_OK
+    if weights == "nan":
+        assert fell_back
+        assert torch.equal(phi, phi_plain)
+    else:
+        assert not fell_back
+        assert rel_l2(host(phi), host(phi_plain)) < 1e-6
+    net.close()
+    ctx.close()

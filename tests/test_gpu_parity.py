@@ -491,3 +491,20 @@ def test_invalid_arguments(M):
     with pytest.raises(M.PmError):
         M.pm_deposit(ctx, dev(np.zeros((5, 3))), dev(np.ones(5)), grid(32))   # N > max_particles
     ctx.close()
+
+
+def test_library_owned_and_caller_workspace_agree(M):
+    # pm_create with a NULL workspace (the library allocates) against the
+    # caller-owned torch workspace every other test uses: the same step.
+    w = W.random_cloud(21, 32, 600, mu=W.MU_STANDARD)
+    p = w["params"]
+    _log("workspace: library vs caller", p["n_pad"])
+    out = []
+    for kind in ("library", "torch"):
+        ctx = M.pm_create(p, 600, workspace=kind)
+        pos, vel = dev(w["pos"]), dev(w["vel"])
+        M.pm_step(ctx, pos, vel, dev(w["mass"]), float(w["dt"]), want_info=False)
+        out.append((host(pos), host(vel)))
+        ctx.close()
+    assert rel_l2(out[0][1], out[1][1]) < 1e-6
+    assert np.max(np.abs(out[0][0] - out[1][0])) < 1e-5
