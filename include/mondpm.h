@@ -147,6 +147,20 @@ pm_status pm_deposit(pm_ctx* ctx, const float* pos, const float* mass, int64_t N
 pm_status aqual_solve(pm_ctx* ctx, const float* rho, const float* H0, float* phi,
                       pm_solve_info* info);
 
+/* pm_deposit for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * no context, no workspace, and no allocation of any kind.  Same result as
+ * pm_deposit on a context with parameters p (rho: device float [n_pad^3],
+ * overwritten; pos, mass as there), enqueued on stream (a hipStream_t, NULL
+ * = the default stream) without waiting.  Its scratch (the ball table and the
+ * sort buffers, about 18 MB) is one fixed array per GPU that the library
+ * holds until the process ends; every call on a GPU uses it, so calls that
+ * overlap on one GPU (other streams or threads) race and must be serialised
+ * by the caller.  Limits: N <= 2^20 and n_pad <= 512, otherwise PM_E_INVAL
+ * with nothing enqueued. */
+pm_status pm_deposit_noalloc(const pm_params* p, const float* pos, const float* mass, int64_t N, float* rho,
+                             void* stream);
+
 /* Kernel-smoothed acceleration of Eq. gi: g_i = -sum_d w_id (D phi)(c_i + d)
  * with D the central-difference gradient and the same weights as pm_deposit.
  * phi: device float [n_pad^3]; acc: device float [N][3] (written). */

@@ -4,6 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <vector>
 
 #include "mondpm.h"
@@ -570,6 +571,140 @@ pm_status pm_deposit(pm_ctx* c, const float* pos, const float* mass, int64_t n, 
   { Timed t(c, PM_T_FILL); HIPCHK(fill_zero(rho, R, c->st)); }
   HIPCHK(sort_and_plan(c, pos, n));
   HIPCHK(deposit_any(c, pos, mass, n, rho, nullptr));
+  return PM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Deposit without device allocation (pm_deposit_noalloc)
+// ---------------------------------------------------------------------------
+// Its scratch (the ball table and the sort buffers) is a fixed static device
+// array.  Host code never passes the array's name to a kernel: each device's
+// address of it is taken once with hipGetSymbolAddress and used from then on.
+namespace {
+constexpr int64_t kNaMaxParticles = (int64_t)1 << 20;
+constexpr int kNaMaxNpad = 512;
+constexpr size_t kNaMaxTiles = (size_t)(kNaMaxNpad / 8) * (kNaMaxNpad / 8) * (kNaMaxNpad / 8);
+constexpr size_t kNaMaxBall = 21 * 21 * 21;        // cutoff * sigma <= 10 cells
+constexpr size_t na_round(size_t b) { return (b + 255) & ~(size_t)255; }
+constexpr size_t kNaBallBytes = na_round(kNaMaxBall * sizeof(int));
+constexpr size_t kNaSortInts = 4 * (size_t)kNaMaxParticles + 2 * (kNaMaxTiles + 1) + (kNaMaxTiles + 1023) / 1024 + 16;
+constexpr size_t kNaScratchBytes = kNaBallBytes + na_round(kNaSortInts * sizeof(int));
+constexpr int kNaMaxDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNaScratchBytes];
+
+static std::mutex g_na_mutex;
+static void* g_na_ptr[kNaMaxDevices];
+static int g_na_lds[kNaMaxDevices];
+
+// Ball offsets |d|^2 < R2 in the order of make_ball (dz slowest, dx fastest),
+// packed as in the context's table; one block compacts 1024 candidates at a
+// time with ballots.
+__global__ __launch_bounds__(1024) void k_ball_table(int m, double R2, int* out) {
+  __shared__ int wsum[16];
+  __shared__ int base;
+  const int side = 2 * m + 1, total = side * side * side;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (threadIdx.x == 0) base = 0;
+  __syncthreads();
+  for (int c0 = 0; c0 < total; c0 += 1024) {
+    const int c = c0 + (int)threadIdx.x;
+    bool in = false;
+    int e = 0;
+    if (c < total) {
+      const int dx = c % side - m, dy = (c / side) % side - m, dz = c / (side * side) - m;
+      in = (double)(dx * dx + dy * dy + dz * dz) < R2;
+      e = (dx + 16) | ((dy + 16) << 8) | ((dz + 16) << 16);
+    }
+    const unsigned long long bal = __ballot(in);
+    if (lane == 0) wsum[wave] = __popcll(bal);
+    __syncthreads();
+    int before = base;
+    for (int w = 0; w < wave; ++w) before += wsum[w];
+    if (in) out[before + __popcll(bal & ((1ull << lane) - 1ull))] = e;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int t = 0;
+      for (int w = 0; w < 16; ++w) t += wsum[w];
+      base += t;
+    }
+    __syncthreads();
+  }
+}
+
+pm_status pm_deposit_noalloc(const pm_params* p, const float* pos, const float* mass, int64_t n, float* rho,
+                             void* stream) {
+  pm_status s = check_params(p);
+  if (s != PM_OK) return s;
+  if (n < 0 || n > kNaMaxParticles) return inval("pm_deposit_noalloc takes at most 2^20 particles");
+  if (p->n_pad > kNaMaxNpad) return inval("pm_deposit_noalloc takes n_pad <= 512");
+  if (!rho || (n > 0 && (!pos || !mass))) return inval("NULL buffer");
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kNaMaxDevices) return inval("device id out of range");
+  void* base = nullptr;
+  int lds_max = 0;
+  {
+    std::lock_guard<std::mutex> lock(g_na_mutex);
+    if (!g_na_ptr[dev]) {
+      void* ptr = nullptr;
+      HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+      HIPCHK(hipDeviceGetAttribute(&g_na_lds[dev], hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+      g_na_ptr[dev] = ptr;
+    }
+    base = g_na_ptr[dev];
+    lds_max = g_na_lds[dev];
+  }
+  // ball of radius R (no host buffer: count here, build the table on the device)
+  const double R = p->cutoff * p->sigma;
+  const int m = (int)floor(R), ext = ball_extent(R);
+  int nball = 0;
+  for (int dz = -m; dz <= m; ++dz)
+    for (int dy = -m; dy <= m; ++dy)
+      for (int dx = -m; dx <= m; ++dx)
+        if ((double)(dx * dx + dy * dy + dz * dz) < R * R) ++nball;
+  const size_t te = 8 + 2 * (size_t)ext;
+  const bool priv = 4 * te * te * te * sizeof(float) <= 96 * 1024;
+  const size_t lds_need = sizeof(float) * (((size_t)nball + 3 & ~(size_t)3) + (priv ? 4 : 1) * te * te * te);
+  if (lds_need + 4 * 512 * sizeof(int) + 64 > (size_t)lds_max) return inval("kernel ball too large for the LDS of this device");
+
+  const int N = p->n_pad;
+  const double s_px = p->box / p->n;
+  KernelGeom kg{};
+  kg.N = N;
+  kg.n = p->n;
+  kg.s = (float)s_px;
+  kg.inv_s = 1.0 / s_px;
+  kg.inv2sig2 = (float)(1.0 / (2.0 * p->sigma * p->sigma));
+  kg.ext = ext;
+  kg.nball = nball;
+  kg.ball = static_cast<int*>(base);
+  kg.analytic = (p->flags & PM_F_ANALYTIC_NORM) ? 1 : 0;
+  kg.analytic_norm = pow(2.0 * M_PI, 1.5) * p->sigma * p->sigma * p->sigma;
+  kg.private_tiles = priv ? 1 : 0;
+
+  const size_t ntiles = (size_t)(N / 8) * (N / 8) * (N / 8);
+  const size_t mp = (size_t)(n > 0 ? n : 1);
+  int* ib = reinterpret_cast<int*>(static_cast<char*>(base) + kNaBallBytes);
+  SortBufs sb{};
+  sb.keys = ib; ib += mp;
+  sb.rank = ib; ib += mp;
+  sb.perm = ib; ib += mp;
+  sb.skey = ib; ib += mp;
+  sb.counts = ib; ib += ntiles + 1;
+  sb.offsets = ib; ib += ntiles + 1;
+  sb.blocksums = ib; ib += (ntiles + 1023) / 1024;
+  sb.flags = ib;
+  sb.ntiles = (int)ntiles;
+
+  hipLaunchKernelGGL(k_ball_table, dim3(1), dim3(1024), 0, st, m, R * R, const_cast<int*>(kg.ball));
+  HIPCHK(hipGetLastError());
+  HIPCHK(fill_zero(reinterpret_cast<float*>(sb.flags), 16, st));
+  HIPCHK(fill_zero(rho, (long long)N * N * N, st));
+  HIPCHK(sort_particles(kg, sb, pos, n, st));
+  HIPCHK(deposit_sorted(kg, sb, pos, mass, n, rho, nullptr, st));
   return PM_OK;
 }
 

@@ -62,6 +62,7 @@ def lib():
         L.pm_create.argtypes = [P(PmParams), I64, VP, ctypes.c_size_t, VP, P(VP)]
         L.pm_destroy.argtypes = [VP]
         L.pm_deposit.argtypes = [VP, VP, VP, I64, VP]
+        L.pm_deposit_noalloc.argtypes = [P(PmParams), VP, VP, I64, VP, VP]
         L.aqual_solve.argtypes = [VP, VP, VP, VP, P(PmSolveInfo)]
         L.smooth_accel.argtypes = [VP, VP, VP, I64, VP]
         L.interp_push.argtypes = [VP, VP, VP, VP, I64, D, D]
@@ -101,7 +102,7 @@ def lib():
         L.pm_net_adam.argtypes = [VP, F32]
         L.pm_net_train_step.argtypes = [VP, I32, F32, P(D)]
         L.pm_net_forward.argtypes = [VP, VP, VP, VP]
-        for f in ("pm_create", "pm_destroy", "pm_deposit", "aqual_solve", "smooth_accel", "interp_push",
+        for f in ("pm_create", "pm_destroy", "pm_deposit", "pm_deposit_noalloc", "aqual_solve", "smooth_accel", "interp_push",
                   "pm_step", "pm_step_capture", "pm_step_replay", "pm_diagnostics", "pm_fft_r2c", "pm_fft_c2r", "pm_set_timing",
                   "pm_read_timing", "pm_newton_potential", "pm_apparent_density", "pm_set_external_field", "aqual_solve_field", "pm_net_create",
                   "pm_net_destroy", "pm_net_set_params", "pm_net_get_params", "pm_net_get_grads",
@@ -208,6 +209,18 @@ def pm_deposit(ctx: Ctx, pos, mass, rho):
     n = mass.numel()
     _check(lib().pm_deposit(ctx.handle, _ptr(pos, numel=3 * n, name="pos"), _ptr(mass, name="mass"), n,
                             _ptr(rho, numel=ctx.N ** 3, name="rho")), "pm_deposit")
+    return rho
+
+
+def pm_deposit_noalloc(params, pos, mass, rho, stream=None):
+    """pm_deposit without a context or any device allocation (fixed scratch)."""
+    n = mass.numel()
+    p = make_params(params)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    _check(lib().pm_deposit_noalloc(ctypes.byref(p), _ptr(pos, numel=3 * n, name="pos"), _ptr(mass, name="mass"),
+                                    n, _ptr(rho, numel=int(params["n_pad"]) ** 3, name="rho"),
+                                    ctypes.c_void_p(stream.cuda_stream)), "pm_deposit_noalloc")
     return rho
 
 

@@ -54,7 +54,7 @@ def test_net_parameter_layout_and_argument_checks_without_gpu():
     assert L.pm_net_create(4, 1, None, C.byref(h)) == M.PM_E_INVAL       # too small for 3 levels
 
 
-def test_workspace_argument_checks_without_gpu():
+def test_workspace_and_noalloc_argument_checks_without_gpu():
     import ctypes as C
     from paper_2312_02968_amd import mondpm as M
     import workloads as W
@@ -65,3 +65,9 @@ def test_workspace_argument_checks_without_gpu():
     assert L.pm_create(C.byref(p), 0, C.c_void_p(0x1000 + 8), 1 << 30, None, C.byref(h)) == M.PM_E_INVAL
     assert L.pm_create(C.byref(p), -1, None, 0, None, C.byref(h)) == M.PM_E_INVAL
     assert M.pm_workspace_bytes(W.params(64), (1 << 30) + 1) == 0
+    # the no-allocation deposit refuses inputs beyond its fixed scratch
+    fake = C.c_void_p(0x1000)
+    assert L.pm_deposit_noalloc(C.byref(p), fake, fake, (1 << 20) + 1, fake, None) == M.PM_E_INVAL
+    big = M.make_params(W.params(512))                       # n_pad 1024
+    assert L.pm_deposit_noalloc(C.byref(big), fake, fake, 10, fake, None) == M.PM_E_INVAL
+    assert L.pm_deposit_noalloc(C.byref(p), None, None, 10, fake, None) == M.PM_E_INVAL
