@@ -357,6 +357,9 @@ def main():
     ap.add_argument("--no-oracle-error", action="store_true",
                     help="skip the force error against the FP64 oracle (about a minute of host work; "
                          "reported by default for FFT boxes up to 512^3 with the zero start)")
+    ap.add_argument("--dft", choices=("fp32", "bf16x3"), default="fp32",
+                    help="arithmetic of the y passes' radix-16 stage: FP32 butterflies (default) or "
+                         "BF16x3 dense DFT-16 products on the matrix cores (PM_F_DFT_BF16X3)")
     ap.add_argument("--launch", choices=("graph", "eager"), default="graph",
                     help="time replays of the step recorded as a HIP graph (default) or eager pm_step calls")
     a = ap.parse_args()
@@ -378,6 +381,8 @@ def main():
     w = make_workload(a.workload)
     if a.warm:
         w["params"] = dict(w["params"], iters=a.warm, flags=w["params"].get("flags", 0) | M.PM_F_WARM_START)
+    if a.dft == "bf16x3":
+        w["params"] = dict(w["params"], flags=w["params"].get("flags", 0) | M.PM_F_DFT_BF16X3)
     p = w["params"]
     N_part = len(w["mass"])
     dt = float(w["dt"])
@@ -468,7 +473,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": w["workload"], "grid": p["n"], "fft_box": Npad, "particles": N_part,
                    "iterations": K, "start": "warm" if a.warm else "zero", "sigma_cells": p["sigma"],
-                   "mu": "standard" if p["mu"] == 0 else ("deep" if p["mu"] == 1 else "newton"), "dt": dt},
+                   "mu": "standard" if p["mu"] == 0 else ("deep" if p["mu"] == 1 else "newton"), "dt": dt,
+                   "dft": a.dft},
         "launch": a.launch,
         "ms_per_step_eager": round(ms_eager, 3),
         "particle_updates_per_s": round(N_part * 1e3 / ms_step, 1),
@@ -477,7 +483,7 @@ def main():
     }
     ctx.close()
     out["solver_vs_poisson"] = solver_vs_poisson(w)
-    if not a.no_starts and not a.warm:
+    if not a.no_starts and not a.warm and a.dft == "fp32":
         out.update(start_comparison(w))
     if not a.no_oracle_error and not a.warm and p["n_pad"] <= 512:
         out["oracle_error"] = oracle_error(w)

@@ -72,6 +72,14 @@ typedef enum {
                                    iters >= 2: F is updated only between two
                                    evaluations of nu.                         */
 
+#define PM_F_DFT_BF16X3    0x8u /* the y passes of every 3D transform run their
+                                   radix-16 stage as dense 16-point DFT matrix
+                                   products on the matrix cores with BF16x3
+                                   split operands (about 16 bits kept, FP32
+                                   accumulation) instead of FP32 butterflies;
+                                   a precision and speed option measured
+                                   against the FP32 path.  n_pad 64..512.      */
+
 /* Statement of the problem (Sect. 2, Sect. 3 and the table of symbols). */
 typedef struct {
   int32_t  n;        /* physical cells per axis, power of two, 8..512          */

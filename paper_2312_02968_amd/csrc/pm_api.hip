@@ -142,6 +142,8 @@ static pm_status check_params(const pm_params* p) {
   if ((p->flags & PM_F_WARM_START) && p->iters < 2)
     return inval("PM_F_WARM_START needs iters >= 2 (with one iteration F is never updated)");
   if (!(p->tol >= 0.0)) return inval("tol must be >= 0");
+  if ((p->flags & PM_F_DFT_BF16X3) && (p->n_pad < 64 || p->n_pad > 512))
+    return inval("PM_F_DFT_BF16X3 needs n_pad in [64, 512]");
   return PM_OK;
 }
 
@@ -227,6 +229,7 @@ static size_t carve(pm_ctx* c, Carver& cv) {
     c->pb.list_off = cv.take<int>(ntiles + 1);
     c->pb.list = cv.take<int>(ntiles);
     c->pb.ptile = cv.take<int>((size_t)max_pieces((int64_t)ntiles, (int64_t)mp));
+    c->pb.counter = cv.take<int>(16);
     c->pb.stage = cv.take<float>(piece_stage_floats(c->piece_ext, c->pb.cap));
   }
   return (cv.off + 255) & ~(size_t)255;
@@ -336,6 +339,7 @@ pm_status pm_create(const pm_params* p, int64_t max_particles, void* workspace, 
   c->fg.P = c->P;
   c->fg.comp_stride = (long long)C;
   c->fg.tw = c->tw;
+  c->fg.bf16x3 = (p->flags & PM_F_DFT_BF16X3) ? 1 : 0;
 
   c->kg.N = N;
   c->kg.n = p->n;

@@ -622,6 +622,124 @@ __global__ __launch_bounds__(NT) void k_ypass(float2* spec, long long comp_strid
   store_cols<L, T, NT, Last::R, NH>(v, E, ptr, nv, 16);
 }
 
+// ----------------------------------------------------------------------------
+// y pass with the radix-16 stage on the matrix cores, BF16x3 split products.
+//
+// A length-L transform (L = 16 M) is X[k2 + 16 k1] = sum_n1 W_M^(n1 k1)
+// W_L^(n1 k2) sum_n2 x[n1 + M n2] W_16^(n2 k2).  The inner DFT-16 over n2 is a
+// dense 16 x 16 complex matrix F times the 16 values of every (n1, column):
+// with real and imaginary parts stacked, Re Y = [Re F | -Im F] [Re x; Im x]
+// and Im Y = [Im F | Re F] [Re x; Im x], one 16 x 32 by 32 x 16 product per
+// n1 for the 16 columns of the block, i.e. v_mfma_f32_16x16x32_bf16.  Each
+// FP32 operand is split into BF16 parts a = a_hi + a_lo (a_lo the BF16
+// rounding of a - a_hi) and a b = a_hi b_hi + a_hi b_lo + a_lo b_hi, three
+// products accumulated in FP32: about 16 bits of the operands survive
+// (the term a_lo b_lo and the rounding of the lo parts are dropped).  The
+// twiddles W_L^(n1 k2) and the outer DFT-M over n1 stay in FP32 on the VALU.
+// Operand layout of the instruction (16 x 32 A, 32 x 16 B, 16 x 16 D): lane l
+// holds A[l mod 16][8 (l div 16) + j], B[8 (l div 16) + j][l mod 16] for
+// j < 8, and D[4 (l div 16) + i][l mod 16] for i < 4.
+// ----------------------------------------------------------------------------
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
+  hi = (__bf16)x;
+  lo = (__bf16)(x - (float)hi);
+}
+
+template <int L, bool INV>
+__global__ __launch_bounds__(256) void k_ypass_mfma(float2* spec, long long comp_stride, int ncols,
+                                                    const float2* __restrict__ tw) {
+  constexpr int M = L / 16;
+  constexpr int TPW = M / 4;                       // n1 values per wave
+  constexpr int RS = 17;                           // LDS row of the 16 columns, padded
+  constexpr int ZS = 256 + 4;                      // LDS row of the 256 (k2, column) sequences
+  constexpr int XE = L * RS > M * ZS ? L * RS : M * ZS;
+  static_assert(M >= 4, "at least one n1 per wave");
+  extern __shared__ float2 lds[];
+  float2* X = lds;                                 // X[n][c] at n RS + c, then Z[n1][q] at n1 ZS + q
+  float2* tw_s = lds + XE;
+  // block order as in k_ypass
+  const int nt = gridDim.x, nc = gridDim.z;
+  const long long b = blockIdx.x + (long long)nt * (blockIdx.y + (long long)L * blockIdx.z);
+  int t, kz, comp;
+  if constexpr (!INV) {
+    t = (int)(b % nt);
+    comp = (int)((b / nt) % nc);
+    kz = L - 1 - (int)(b / ((long long)nt * nc));
+  } else {
+    kz = (int)(b % L);
+    comp = (int)((b / L) % nc);
+    t = nt - 1 - (int)(b / ((long long)L * nc));
+  }
+  const int nv = min(16, ncols - t * 16);
+  float2* base = spec + comp * comp_stride + ((long long)t * L + kz) * L * 16;
+  load_twiddles<L>(tw_s, tw, 256);
+  for (int i = threadIdx.x; i < L * 16; i += 256) {
+    const int r = i >> 4, c = i & 15;
+    X[r * RS + c] = (c < nv) ? base[(long long)r * 16 + c] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane & 15, grp = lane >> 4;
+  // A fragments: rows k2 = col of [Re F | -Im F] and [Im F | Re F]
+  bf16x8_t arh, arl, aih, ail;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int kk = 8 * grp + j, n2 = kk & 15, q = (col * n2) & 15;
+    const float c = q < 8 ? kC16[q] : -kC16[q - 8];
+    const float sn = q < 8 ? kS16[q] : -kS16[q - 8];
+    const float fr = c, fi = INV ? sn : -sn;           // W_16^(n2 k2), conjugated for the inverse
+    const bool re = kk < 16;
+    __bf16 h, l;
+    split_bf16(re ? fr : -fi, h, l); arh[j] = h; arl[j] = l;
+    split_bf16(re ? fi : fr, h, l); aih[j] = h; ail[j] = l;
+  }
+  // B fragments of the wave's n1 values: column col, n2 = kk mod 16, real part for kk < 16
+  bf16x8_t bh[TPW], bl[TPW];
+#pragma unroll
+  for (int u = 0; u < TPW; ++u) {
+    const int n1 = wave + 4 * u;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int kk = 8 * grp + j, n2 = kk & 15;
+      const float2 x = X[(n1 + M * n2) * RS + col];
+      __bf16 h, l;
+      split_bf16(kk < 16 ? x.x : x.y, h, l);
+      bh[u][j] = h;
+      bl[u][j] = l;
+    }
+  }
+  __syncthreads();                                 // X is overwritten by Z below
+#pragma unroll
+  for (int u = 0; u < TPW; ++u) {
+    const int n1 = wave + 4 * u;
+    f32x4_t yr = {0.f, 0.f, 0.f, 0.f}, yi = {0.f, 0.f, 0.f, 0.f};
+    yr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, bh[u], yr, 0, 0, 0);
+    yr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, bl[u], yr, 0, 0, 0);
+    yr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arl, bh[u], yr, 0, 0, 0);
+    yi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, bh[u], yi, 0, 0, 0);
+    yi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, bl[u], yi, 0, 0, 0);
+    yi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ail, bh[u], yi, 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int k2 = 4 * grp + i;
+      float2 w = tw_s[n1 * k2];                    // W_L^(n1 k2), n1 k2 < L
+      if (INV) w.y = -w.y;
+      X[n1 * ZS + k2 * 16 + col] = cmul(make_float2(yr[i], yi[i]), w);
+    }
+  }
+  __syncthreads();
+  // the DFT-M over n1 of the 256 sequences q = 16 k2 + column (in place)
+  block_fft<M, 256, 256, true, INV>(X, 1, ZS, tw_s, L / M);
+  for (int i = threadIdx.x; i < L * 16; i += 256) {
+    const int k = i >> 4, c = i & 15;
+    if (c < nv) base[(long long)k * 16 + c] = X[(k >> 4) * ZS + (k & 15) * 16 + c];
+  }
+}
+
 enum { Z_FWD = 0, Z_INV = 1, Z_NEWTON = 2, Z_CURL = 3, Z_CURL_FINAL = 4, Z_DIV = 5, Z_NEWTON_H0 = 6, Z_POISSON = 7,
        Z_NEWTON_WARM = 8, Z_APPARENT = 9 };
 
@@ -931,6 +1049,20 @@ hipError_t launch_y(const FftGeom& g, float2* spec, int ncomp, hipStream_t st) {
   return hipGetLastError();
 }
 
+template <int N, bool INV>
+hipError_t launch_y_mfma(const FftGeom& g, float2* spec, int ncomp, hipStream_t st) {
+  if constexpr (N >= 64 && N <= 512) {
+    constexpr int M = N / 16;
+    constexpr size_t xe = (size_t)N * 17 > (size_t)M * 260 ? (size_t)N * 17 : (size_t)M * 260;
+    const int tiles = (N / 2 + 1 + 15) / 16;
+    hipLaunchKernelGGL((k_ypass_mfma<N, INV>), dim3(tiles, N, ncomp), dim3(256), sizeof(float2) * (xe + N), st,
+                       spec, g.comp_stride, N / 2 + 1, g.tw);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
 template <int N, int ZOP>
 hipError_t launch_z(const FftGeom& g, ZArgs a, hipStream_t st) {
   using C = Cfg<N>;
@@ -956,8 +1088,10 @@ hipError_t run_pass(const FftGeom& g, const PassDesc& d, hipStream_t st) {
       return launch_x<N, X_FUSED_NU, 3>(g, d.spec, nullptr, 0, d.mu_mode, d.inv_a0, nullptr, nullptr, st);
     case PASS_X_MU:
       return launch_x<N, X_FUSED_MU, 3>(g, d.spec, nullptr, 0, d.mu_mode, d.inv_a0, nullptr, nullptr, st);
-    case PASS_Y_FWD: return launch_y<N, false>(g, d.spec, d.ncomp, st);
-    case PASS_Y_INV: return launch_y<N, true>(g, d.spec, d.ncomp, st);
+    case PASS_Y_FWD:
+      return g.bf16x3 ? launch_y_mfma<N, false>(g, d.spec, d.ncomp, st) : launch_y<N, false>(g, d.spec, d.ncomp, st);
+    case PASS_Y_INV:
+      return g.bf16x3 ? launch_y_mfma<N, true>(g, d.spec, d.ncomp, st) : launch_y<N, true>(g, d.spec, d.ncomp, st);
     case PASS_Z_FWD: return launch_z<N, Z_FWD>(g, d.z, st);
     case PASS_Z_INV: return launch_z<N, Z_INV>(g, d.z, st);
     case PASS_Z_NEWTON:

@@ -11,6 +11,7 @@ struct FftGeom {
   int P;                  // kx slots of a spectrum: 16 * ceil((N/2 + 1) / 16)
   long long comp_stride;  // complex entries per spectrum component (N * N * P)
   const float2* tw;       // exp(-2 pi i t / N), t < N
+  int bf16x3 = 0;         // y passes with the radix-16 stage on the matrix cores (BF16x3)
 };
 
 // Arguments of a z pass (see pm_fft.hip).
@@ -96,13 +97,17 @@ struct SortBufs {
 // Tile pieces (pm_pieces.hip): a tile's sorted particles in runs of at most
 // kPiece, each deposited into its own staging slot (slots < cap) or straight
 // into rho with atomics (slots >= cap).
-constexpr int kPiece = 2048;
+#ifndef PM_PIECE
+#define PM_PIECE 1024
+#endif
+constexpr int kPiece = PM_PIECE;
 struct PieceBufs {
   int* pc_off;      // [ntiles + 1] first piece of each tile (exclusive scan)
   int* flag;        // [ntiles] scratch: pieces per tile, then destination flags
   int* list_off;    // [ntiles + 1] exclusive scan of the destination flags
   int* list;        // [ntiles] tiles that receive staged cells
   int* ptile;       // [pieces] tile of each piece
+  int* counter;     // [2] work counters of the deposit and the gather
   float* stage;     // [cap][TE^3] staged halo boxes
   int cap;
 };

@@ -12,7 +12,7 @@
 // wy[dy] wz[dz] sum_{|dx| <= h} wx[dx].
 //
 // Work split.  After the tile sort (8^3-cell tiles), each tile's particles are
-// cut into pieces of at most kPiece, dealt to the blocks round robin.
+// cut into pieces of at most kPiece; blocks take pieces from a work counter.
 //  - Deposit: a piece accumulates its balls in an LDS copy of the tile plus a
 //    halo of EXT cells, as exact 64-bit fixed-point sums (below), and stores
 //    the piece's halo box to a staging slot.  A
@@ -39,6 +39,7 @@ namespace {
 constexpr int kTile = 8;
 constexpr int kNT = 256;
 constexpr int kWaves = kNT / 64;
+constexpr int kPieceBits = 32 - __builtin_clz((unsigned)kPiece - 1u);   // ceil(log2 kPiece)
 
 __device__ __forceinline__ int wrapi(int i, int N) { return i & (N - 1); }
 
@@ -105,8 +106,14 @@ __device__ __forceinline__ void lane_setup(Lane<EXT>& L, const KernelGeom& kg, f
   L.S = S;
 }
 
-// Pieces are dealt to the blocks round robin (piece p to block p mod grid):
-// no work counter, and the same order on every run.
+// Blocks take pieces from a work counter (pieces differ in size by three
+// orders of magnitude); the tile of a piece is one load from the map.
+__device__ __forceinline__ int next_piece(int* counter, int* slot) {
+  __syncthreads();
+  if (threadIdx.x == 0) *slot = atomicAdd(counter, 1);
+  __syncthreads();
+  return *slot;
+}
 
 // ---------------------------------------------------------------------------
 // deposit
@@ -122,7 +129,7 @@ __device__ __forceinline__ void lane_setup(Lane<EXT>& L, const KernelGeom& kg, f
 // the smallest possible central-cell weight; a cell sums at most kPiece
 // contributions per ball cell.
 __device__ __forceinline__ unsigned long long to_fixed(float c, int k) {
-  const float t = ldexpf(fabsf(c), k);                  // < 2^50 by the choice of k
+  const float t = ldexpf(fabsf(c), k);                  // < 2^61 by the choice of k
   const unsigned hi = (unsigned)(t * 2.3283064365386963e-10f);   // t / 2^32, truncated
   const unsigned lo = (unsigned)fmaf(-(float)hi, 4294967296.0f, t);
   const unsigned long long u = ((unsigned long long)hi << 32) | lo;
@@ -134,7 +141,7 @@ __global__ __launch_bounds__(kNT) void k_deposit_pieces(KernelGeom kg, const int
                                                         const int* __restrict__ offsets,
                                                         const int* __restrict__ pc_off,
                                                         const int* __restrict__ ptile, int ntiles, int piece,
-                                                        const float* __restrict__ pos,
+                                                        int* counter, const float* __restrict__ pos,
                                                         const float* __restrict__ mass, float* stage, int cap,
                                                         float* rho) {
   constexpr int TE = kTile + 2 * EXT;
@@ -144,7 +151,8 @@ __global__ __launch_bounds__(kNT) void k_deposit_pieces(KernelGeom kg, const int
   const int N = kg.N, nt = N / kTile;
   const double s3 = (double)kg.s * kg.s * kg.s;
   const int total = pc_off[ntiles];
-  for (int p = blockIdx.x; p < total; p += gridDim.x) {
+  __shared__ int slot;
+  for (int p = next_piece(counter, &slot); p < total; p = next_piece(counter, &slot)) {
     const int t = ptile[p];
     const int a = offsets[t] + (p - pc_off[t]) * piece;
     const int b = min(a + piece, offsets[t + 1]);
@@ -160,15 +168,15 @@ __global__ __launch_bounds__(kNT) void k_deposit_pieces(KernelGeom kg, const int
       for (int j = a + (int)threadIdx.x; j < b; j += kNT) mloc = fmaxf(mloc, fabsf(mass[perm[j]]));
       atomicMax(&mbits, __float_as_uint(mloc));     // non-negative floats order as their bits
       __syncthreads();
-      // A = max |m| / (w0 s^3) bounds every contribution; 2^k A < 2^50 and
-      // kPiece (2^11) of them stay below 2^61
+      // A = max |m| / (w0 s^3) bounds every contribution; with 2^k A below
+      // 2^(61 - log2 kPiece), the kPiece contributions to a cell stay below 2^61
       // the normalisation is at least the central cell's weight, whose offset
       // is at most 1/2 cell per axis (or the analytic prefactor)
       const double norm_lo = kg.analytic ? kg.analytic_norm : (double)expf(-0.75f * kg.inv2sig2);
       const double A = (double)__uint_as_float(mbits) / (norm_lo * s3);
       int e = 0;
       frexp(A > 0.0 ? A : 1.0, &e);                 // A < 2^e
-      k = 50 - e;
+      k = 61 - kPieceBits - e;
     }
     for (int j = a + (int)threadIdx.x; j < b; j += kNT) {
       const int64_t i = perm[j];
@@ -287,6 +295,8 @@ __global__ __launch_bounds__(kNT) void k_deposit_reduce(const int* __restrict__ 
         const bool in = lx >= 0 && lx < TE && ly >= 0 && ly < TE && lz >= 0 && lz < TE && sq0[nb] < sq1[nb];
         v[nb] = in ? stage[(size_t)sq0[nb] * TE3 + (lz * TE + ly) * TE + lx] : 0.0f;
       });
+      const long long g = ((long long)(tz * kTile + cz) * N + (ty * kTile + cy)) * N + (tx * kTile + cx);
+      const float r0 = rho[g];
       float sum = 0.0f;
 #pragma unroll
       for (int nb = 0; nb < 27; ++nb) sum += v[nb];
@@ -294,10 +304,20 @@ __global__ __launch_bounds__(kNT) void k_deposit_reduce(const int* __restrict__ 
         const int dx = nb % 3 - 1, dy = (nb / 3) % 3 - 1, dz = nb / 9 - 1;
         const int lx = cx - dx * kTile + EXT, ly = cy - dy * kTile + EXT, lz = cz - dz * kTile + EXT;
         if (lx < 0 || lx >= TE || ly < 0 || ly >= TE || lz < 0 || lz >= TE) continue;
-        for (int q = sq0[nb] + 1; q < sq1[nb]; ++q) sum += stage[(size_t)q * TE3 + (lz * TE + ly) * TE + lx];
+        // four independent loads in flight, summed in a fixed order
+        const float* src = stage + (lz * TE + ly) * TE + lx;
+        float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+        int q = sq0[nb] + 1;
+        for (; q + 3 < sq1[nb]; q += 4) {
+          s0 += src[(size_t)q * TE3];
+          s1 += src[(size_t)(q + 1) * TE3];
+          s2 += src[(size_t)(q + 2) * TE3];
+          s3 += src[(size_t)(q + 3) * TE3];
+        }
+        for (; q < sq1[nb]; ++q) s0 += src[(size_t)q * TE3];
+        sum += (s0 + s1) + (s2 + s3);
       }
-      const long long g = ((long long)(tz * kTile + cz) * N + (ty * kTile + cy)) * N + (tx * kTile + cx);
-      if (sum != 0.0f) rho[g] += sum;
+      if (sum != 0.0f) rho[g] = r0 + sum;
     }
   }
 }
@@ -310,7 +330,7 @@ __global__ __launch_bounds__(kNT) void k_gather_pieces(KernelGeom kg, const int*
                                                        const int* __restrict__ offsets,
                                                        const int* __restrict__ pc_off,
                                                        const int* __restrict__ ptile, int ntiles, int piece,
-                                                       const float* __restrict__ phi, float* pos,
+                                                       int* counter, const float* __restrict__ phi, float* pos,
                                                        float* vel, float* acc, float dt_kick, float dt_drift,
                                                        int mode) {
   constexpr int HE = EXT + 1;                      // ball plus the difference stencil
@@ -319,7 +339,8 @@ __global__ __launch_bounds__(kNT) void k_gather_pieces(KernelGeom kg, const int*
   extern __shared__ float tile[];
   const int N = kg.N, nt = N / kTile;
   const int total = pc_off[ntiles];
-  for (int p = blockIdx.x; p < total; p += gridDim.x) {
+  __shared__ int slot;
+  for (int p = next_piece(counter, &slot); p < total; p = next_piece(counter, &slot)) {
     const int t = ptile[p];
     const int a = offsets[t] + (p - pc_off[t]) * piece;
     const int b = min(a + piece, offsets[t + 1]);
@@ -454,12 +475,13 @@ hipError_t piece_plan(const PieceBufs& pb, const SortBufs& sb, int N, hipStream_
 hipError_t deposit_pieces(const KernelGeom& kg, const SortBufs& sb, const PieceBufs& pb, const float* pos,
                           const float* mass, int64_t n, float* rho, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipError_t e = hipSuccess;
+  hipError_t e = fill_zero(reinterpret_cast<float*>(pb.counter), 1, st);
+  if (e != hipSuccess) return e;
   const int nt = kg.N / kTile;
   switch (kg.piece_ext) {
     case 3:
       hipLaunchKernelGGL((k_deposit_pieces<3, 16>), dim3(kPersistBlocks), dim3(kNT), deposit_lds<3>(), st, kg,
-                         sb.perm, sb.offsets, pb.pc_off, pb.ptile, sb.ntiles, kPiece, pos, mass, pb.stage,
+                         sb.perm, sb.offsets, pb.pc_off, pb.ptile, sb.ntiles, kPiece, pb.counter, pos, mass, pb.stage,
                          pb.cap, rho);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       hipLaunchKernelGGL((k_deposit_reduce<3>), dim3(kPersistBlocks), dim3(kNT), 0, st, pb.list,
@@ -467,7 +489,7 @@ hipError_t deposit_pieces(const KernelGeom& kg, const SortBufs& sb, const PieceB
       break;
     case 5:
       hipLaunchKernelGGL((k_deposit_pieces<5, 36>), dim3(kPersistBlocks), dim3(kNT), deposit_lds<5>(), st, kg,
-                         sb.perm, sb.offsets, pb.pc_off, pb.ptile, sb.ntiles, kPiece, pos, mass, pb.stage,
+                         sb.perm, sb.offsets, pb.pc_off, pb.ptile, sb.ntiles, kPiece, pb.counter, pos, mass, pb.stage,
                          pb.cap, rho);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       hipLaunchKernelGGL((k_deposit_reduce<5>), dim3(kPersistBlocks), dim3(kNT), 0, st, pb.list,
@@ -483,15 +505,17 @@ hipError_t gather_pieces(const KernelGeom& kg, const SortBufs& sb, const PieceBu
                          float* pos, float* vel, float* acc, int64_t n, float dt_kick, float dt_drift, int mode,
                          hipStream_t st) {
   if (n <= 0) return hipSuccess;
+  hipError_t e = fill_zero(reinterpret_cast<float*>(pb.counter + 1), 1, st);
+  if (e != hipSuccess) return e;
   switch (kg.piece_ext) {
     case 3:
       hipLaunchKernelGGL((k_gather_pieces<3, 16>), dim3(kPersistBlocks), dim3(kNT), gather_lds<3>(), st, kg,
-                         sb.perm, sb.offsets, pb.pc_off, pb.ptile, sb.ntiles, kPiece, phi, pos, vel, acc,
+                         sb.perm, sb.offsets, pb.pc_off, pb.ptile, sb.ntiles, kPiece, pb.counter + 1, phi, pos, vel, acc,
                          dt_kick, dt_drift, mode);
       break;
     case 5:
       hipLaunchKernelGGL((k_gather_pieces<5, 36>), dim3(kPersistBlocks), dim3(kNT), gather_lds<5>(), st, kg,
-                         sb.perm, sb.offsets, pb.pc_off, pb.ptile, sb.ntiles, kPiece, phi, pos, vel, acc,
+                         sb.perm, sb.offsets, pb.pc_off, pb.ptile, sb.ntiles, kPiece, pb.counter + 1, phi, pos, vel, acc,
                          dt_kick, dt_drift, mode);
       break;
     default:

@@ -22,6 +22,7 @@ PM_OK, PM_E_INVAL, PM_E_DEVICE, PM_E_NOMEM, PM_E_BOUNDS, PM_E_NOTCONV, PM_E_NONF
 PM_F_ANALYTIC_NORM = 0x1
 PM_F_RESIDUAL = 0x2
 PM_F_WARM_START = 0x4
+PM_F_DFT_BF16X3 = 0x8
 TIMERS = ["x_fwd_real", "x_fwd_real3", "x_inv_real", "x_nu", "x_mu", "y_fwd", "y_inv", "z_fwd",
           "z_inv", "z_newton", "z_curl", "z_curl_final", "z_div", "sort", "deposit", "gather", "fill",
           "reduce"]
