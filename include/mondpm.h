@@ -323,6 +323,16 @@ pm_status pm_net_get_target(pm_net* net, int32_t slot, float* y);
 pm_status pm_net_run(pm_net* net, int32_t batch);
 /* output of slot after pm_net_run / pm_net_backward: device float [3][n^3]. */
 pm_status pm_net_output(pm_net* net, int32_t slot, float* y);
+/* A tensor the last pm_net_run or pm_net_backward stored for slot, as FP32
+ * channels first: out device float [C][(n >> level)^3].  which = 0..12: the
+ * BF16 activations x (4 channels, level 0), a1, s1 (16, 0), p1 (16, 1),
+ * a2, s2 (32, 1), p2 (32, 2), a3, b3 (64, 2), a4, d2 (32, 1), a5, d1 (16, 0),
+ * in forward order (a = first convolution of a level, s = skip tensor,
+ * p = pooled, b3 = bottleneck, d = decoder output); which = 13..22: the BF16
+ * gradient buffers of the backward pass with their last contents: g16a,
+ * g16b (16, 0), gc1 (48, 0), g32a, g32b (32, 1), gc2 (96, 1), g64a, g64b
+ * (64, 2), gp1 (16, 1), gp2 (32, 2).  For per-layer checks of the kernels. */
+pm_status pm_net_get_tensor(pm_net* net, int32_t which, int32_t slot, float* out);
 /* rms of slot (host double out).  Synchronises. */
 pm_status pm_net_get_rms(pm_net* net, int32_t slot, double* rms);
 /* forward and backward over slots [0, batch) with the loss

@@ -1143,6 +1143,15 @@ pm_status pm_net_get_target(pm_net* m, int32_t slot, float* y) {
   return PM_OK;
 }
 
+pm_status pm_net_get_tensor(pm_net* m, int32_t which, int32_t slot, float* out) {
+  pm_status s = check_slot(m, slot);
+  if (s != PM_OK) return s;
+  if (!out) return inval("out is NULL");
+  if (which < 0 || which > 22) return inval("unknown tensor");
+  HIPCHK(net::get_tensor(m->b, which, slot, out, m->st));
+  return PM_OK;
+}
+
 pm_status pm_net_output(pm_net* m, int32_t slot, float* y) {
   pm_status s = check_slot(m, slot);
   if (s != PM_OK) return s;

@@ -79,6 +79,11 @@ hipError_t start_field(const Buffers& b, float* H0, hipStream_t st);
 hipError_t set_input(const Buffers& b, int slot, const float* x4, hipStream_t st);
 // and back: the 4 input channels of a slot as FP32 [4][n^3] (device).
 hipError_t get_input(const Buffers& b, int slot, float* x4, hipStream_t st);
+// A stored activation or gradient tensor of a slot as FP32 channels first
+// (device [C][voxels of its level]); which: 0..12 the activations x, a1, s1,
+// p1, a2, s2, p2, a3, b3, a4, d2, a5, d1; 13..22 the gradient buffers g16a,
+// g16b, gc1, g32a, g32b, gc2, g64a, g64b, gp1, gp2 (their last contents).
+hipError_t get_tensor(const Buffers& b, int which, int slot, float* out, hipStream_t st);
 // Text naming the step that failed in the last failing call (then cleared).
 const char* last_failure();
 

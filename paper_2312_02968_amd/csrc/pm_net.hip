@@ -724,6 +724,18 @@ __global__ __launch_bounds__(NT) void k_get_input(const bf16* __restrict__ x, in
   }
 }
 
+// out[c][v] = t[v][cs + c] for c < C (a stored tensor, channels last with
+// pitch CP, as FP32 channels first)
+__global__ __launch_bounds__(NT) void k_get_tensor(const bf16* __restrict__ t, int64_t nvox, int CP, int C,
+                                                   float* __restrict__ out) {
+  const int64_t total = nvox * C;
+  for (int64_t j = blockIdx.x * (int64_t)NT + threadIdx.x; j < total; j += (int64_t)gridDim.x * NT) {
+    const int c = (int)(j / nvox);
+    const int64_t v = j % nvox;
+    out[j] = bf(t[v * CP + c]);
+  }
+}
+
 // wf[o][t][c] = w[t][c][o] (zero for c >= cin); wb[c][t][o] = w[taps - 1 - t][c][o]
 __global__ __launch_bounds__(NT) void k_pack(const float* __restrict__ w, int taps, int cin, int cin_p, int cout,
                                              bf16* __restrict__ wf, bf16* __restrict__ wb) {
@@ -969,6 +981,23 @@ hipError_t get_input(const Buffers& b, int slot, float* x4, hipStream_t st) {
   const int64_t nvox = level_voxels(b.n, 0);
   hipLaunchKernelGGL(k_get_input, dim3(grid_for(nvox)), dim3(NT), 0, st, b.x + (int64_t)slot * nvox * 16, nvox, x4);
   return launched("k_get_input");
+}
+
+hipError_t get_tensor(const Buffers& b, int which, int slot, float* out, hipStream_t st) {
+  // stored tensor, its level and channels (pitch = channels, except the input)
+  struct T { const bf16* p; int level; int C; int CP; };
+  const T tab[] = {
+      {b.x, 0, 4, 16},    {b.a1, 0, 16, 16},  {b.s1, 0, 16, 16},  {b.p1, 1, 16, 16},  {b.a2, 1, 32, 32},
+      {b.s2, 1, 32, 32},  {b.p2, 2, 32, 32},  {b.a3, 2, 64, 64},  {b.b3, 2, 64, 64},  {b.a4, 1, 32, 32},
+      {b.d2, 1, 32, 32},  {b.a5, 0, 16, 16},  {b.d1, 0, 16, 16},
+      {b.g16a, 0, 16, 16}, {b.g16b, 0, 16, 16}, {b.gc1, 0, 48, 48}, {b.g32a, 1, 32, 32}, {b.g32b, 1, 32, 32},
+      {b.gc2, 1, 96, 96}, {b.g64a, 2, 64, 64}, {b.g64b, 2, 64, 64}, {b.gp1, 1, 16, 16}, {b.gp2, 2, 32, 32}};
+  if (which < 0 || which >= (int)(sizeof tab / sizeof tab[0])) return hipErrorInvalidValue;
+  const T& t = tab[which];
+  const int64_t nvox = level_voxels(b.n, t.level);
+  hipLaunchKernelGGL(k_get_tensor, dim3(grid_for(nvox * t.C)), dim3(NT), 0, st, t.p + (int64_t)slot * nvox * t.CP,
+                     nvox, t.CP, t.C, out);
+  return launched("k_get_tensor");
 }
 
 }  // namespace net

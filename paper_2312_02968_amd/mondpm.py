@@ -98,6 +98,7 @@ def lib():
         L.pm_net_get_target.argtypes = [VP, I32, VP]
         L.pm_net_run.argtypes = [VP, I32]
         L.pm_net_output.argtypes = [VP, I32, VP]
+        L.pm_net_get_tensor.argtypes = [VP, I32, I32, VP]
         L.pm_net_get_rms.argtypes = [VP, I32, P(D)]
         L.pm_net_backward.argtypes = [VP, I32, P(D)]
         L.pm_net_adam.argtypes = [VP, F32]
@@ -108,7 +109,7 @@ def lib():
                   "pm_read_timing", "pm_newton_potential", "pm_apparent_density", "pm_set_external_field", "aqual_solve_field", "pm_net_create",
                   "pm_net_destroy", "pm_net_set_params", "pm_net_get_params", "pm_net_get_grads",
                   "pm_net_input", "pm_net_target", "pm_net_set_input", "pm_net_get_input",
-                  "pm_net_set_target", "pm_net_get_target", "pm_net_run", "pm_net_output", "pm_net_get_rms",
+                  "pm_net_set_target", "pm_net_get_target", "pm_net_run", "pm_net_output", "pm_net_get_tensor", "pm_net_get_rms",
                   "pm_net_backward", "pm_net_adam", "pm_net_train_step", "pm_net_forward"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
@@ -448,6 +449,25 @@ def pm_net_run(net: Net, batch=1):
 def pm_net_output(net: Net, slot, y):
     _check(lib().pm_net_output(net.handle, int(slot), _ptr(y, numel=3 * net.n ** 3, name="y")), "pm_net_output")
     return y
+
+
+# tensors of pm_net_get_tensor: name -> (index, channels, level)
+NET_TENSORS = {
+    "x": (0, 4, 0), "a1": (1, 16, 0), "s1": (2, 16, 0), "p1": (3, 16, 1), "a2": (4, 32, 1),
+    "s2": (5, 32, 1), "p2": (6, 32, 2), "a3": (7, 64, 2), "b3": (8, 64, 2), "a4": (9, 32, 1),
+    "d2": (10, 32, 1), "a5": (11, 16, 0), "d1": (12, 16, 0),
+    "g16a": (13, 16, 0), "g16b": (14, 16, 0), "gc1": (15, 48, 0), "g32a": (16, 32, 1), "g32b": (17, 32, 1),
+    "gc2": (18, 96, 1), "g64a": (19, 64, 2), "g64b": (20, 64, 2), "gp1": (21, 16, 1), "gp2": (22, 32, 2),
+}
+
+
+def pm_net_get_tensor(net: Net, name, slot=0):
+    """A stored activation or gradient tensor as a CUDA tensor [C, m, m, m]."""
+    which, C, level = NET_TENSORS[name]
+    m = net.n >> level
+    out = torch.empty(C * m ** 3, device="cuda")
+    _check(lib().pm_net_get_tensor(net.handle, int(which), int(slot), _ptr(out)), "pm_net_get_tensor")
+    return out.view(C, m, m, m)
 
 
 def pm_net_get_rms(net: Net, slot=0) -> float:
