@@ -35,7 +35,7 @@ METRIC = "PM steps/s at 256³ grid, 2^20 particles; learned vs plain solve time 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.json")
 KERNEL_SOURCES = ("paper_2312_02968_amd/csrc/pm_fft.hip", "paper_2312_02968_amd/csrc/pm_device.h",
-                  "paper_2312_02968_amd/csrc/pm_particles.hip")
+                  "paper_2312_02968_amd/csrc/pm_particles.hip", "paper_2312_02968_amd/csrc/pm_pieces.hip")
 
 
 def source_hash():
@@ -62,6 +62,104 @@ def measured_traffic(kernel, workload):
             or kernel not in t.get("kernels", {})):
         return None
     return t["kernels"][kernel]["bytes_per_launch"]
+
+
+_X_MODES = {0: "x_fwd_real", 1: "x_inv_real", 2: "x_nu", 3: "x_mu", 4: "x_nu"}
+_Z_OPS = {0: "z_fwd", 1: "z_inv", 2: "z_newton", 3: "z_curl", 4: "z_curl_final", 5: "z_div", 6: "z_newton",
+          7: "z_poisson", 8: "z_newton", 9: "z_apparent"}
+
+
+def timer_name(kernel):
+    """The library's timer name for an FFT-pass kernel symbol as rocprofv3
+    prints it (the timers of the roofline record); other kernels keep their
+    base name."""
+    import re
+    m = re.search(r"(k_[a-z0-9_]+)<([^>]*)>", kernel)
+    if not m:
+        m2 = re.search(r"(k_[a-z0-9_]+|__amd_rocclr_[A-Za-z]+)", kernel)
+        return m2.group(1) if m2 else kernel.split("(")[0].strip()
+    base, args = m.group(1), [t.strip() for t in m.group(2).split(",")]
+    if base in ("k_ypass", "k_ypass_mfma"):
+        return "y_inv" if args[-1] == "true" else "y_fwd"
+    if base == "k_xpass_wave":              # <H, XMODE, NC>
+        mode, nc = int(args[1]), int(args[2])
+    elif base == "k_xpass":                 # <H, ROWS, NC, NT, XMODE>
+        mode, nc = int(args[4]), int(args[2])
+    elif base == "k_zpass":                 # <L, T, NT, HZ, ZOP>
+        return _Z_OPS.get(int(args[4]), base)
+    else:
+        return base
+    name = _X_MODES.get(mode, base)
+    return name + "3" if name == "x_fwd_real" and nc == 3 else name
+
+
+def _counter_means(path, counter, K=None):
+    """{kernel timer name: (mean counter value per dispatch, dispatches)} from
+    a rocprofv3 --pmc CSV (rows of one dispatch are summed first).  With K,
+    the y passes (launched with three field components 2K - 1 times per PM
+    step and with one component once) are averaged in that mix, as the
+    algorithmic bytes per launch are."""
+    import csv
+    import glob
+    from collections import defaultdict
+    files = glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {path}")
+    per_disp = defaultdict(float)
+    name_of = {}
+    grid_of = {}
+    for fn in files:
+        for r in csv.DictReader(open(fn)):
+            if r["Counter_Name"] != counter:
+                continue
+            d = (fn, r["Dispatch_Id"])
+            per_disp[d] += float(r["Counter_Value"])
+            name_of[d] = timer_name(r["Kernel_Name"])
+            grid_of[d] = int(r["Grid_Size"])
+    acc = defaultdict(lambda: defaultdict(list))
+    for d, v in per_disp.items():
+        acc[name_of[d]][grid_of[d]].append(v)
+    out = {}
+    for k, by_grid in acc.items():
+        n = sum(len(v) for v in by_grid.values())
+        if K and k in ("y_fwd", "y_inv") and len(by_grid) == 2:
+            g1, g3 = sorted(by_grid)
+            m1 = sum(by_grid[g1]) / len(by_grid[g1])
+            m3 = sum(by_grid[g3]) / len(by_grid[g3])
+            out[k] = ((2 * K - 1) * m3 + m1) / (2 * K), n
+        else:
+            allv = [x for v in by_grid.values() for x in v]
+            out[k] = sum(allv) / len(allv), n
+    return out
+
+
+def ingest_counters(root, workload, src_hash, K):
+    """Write profiles/traffic_counters.json from four rocprofv3 --pmc runs under
+    root: FETCH_SIZE and WRITE_SIZE of the bench command, and of the copy
+    probe (FETCH_SIZE_copy, WRITE_SIZE_copy), which fixes the KiB-to-bytes
+    scale of each counter (HBM bytes = FETCH x fetch_scale + WRITE x
+    write_scale, in KiB)."""
+    fetch = _counter_means(os.path.join(root, "FETCH_SIZE"), "FETCH_SIZE", K)
+    write = _counter_means(os.path.join(root, "WRITE_SIZE"), "WRITE_SIZE", K)
+    cf = _counter_means(os.path.join(root, "FETCH_SIZE_copy"), "FETCH_SIZE")
+    cw = _counter_means(os.path.join(root, "WRITE_SIZE_copy"), "WRITE_SIZE")
+    copy_kib = 1024.0 * 1024.0                   # one 1 GiB copy per dispatch
+    kc = "__amd_rocclr_copyBuffer"
+    fs = round(copy_kib / max(cf[kc][0], 1.0), 2)
+    ws = round(copy_kib / max(cw[kc][0], 1.0), 2)
+    kern = {}
+    for k in sorted(set(fetch) | set(write)):
+        fk = fetch.get(k, (0.0, 0))[0]
+        wk = write.get(k, (0.0, 0))[0]
+        kern[k] = {"fetch_kib": round(fk, 1), "write_kib": round(wk, 1),
+                   "bytes_per_launch": int(1024 * (fk * fs + wk * ws)),
+                   "dispatches": max(fetch.get(k, (0, 0))[1], write.get(k, (0, 0))[1])}
+    out = {"source_hash": src_hash, "workload": workload, "fetch_scale": fs, "write_scale": ws,
+           "copy_probe_kib": {"fetch": cf[kc][0], "write": cw[kc][0]}, "kernels": kern}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+    for k, v in sorted(kern.items(), key=lambda kv: -kv[1]["bytes_per_launch"]):
+        print(f"{k:24s} {v['fetch_kib']:12.0f} {v['write_kib']:12.0f} {v['bytes_per_launch'] / 1e9:8.3f} GB")
 
 
 def copy_probe():
@@ -348,6 +446,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--timing", action="store_true", help="print per-kernel timing table to stderr")
     ap.add_argument("--copy-probe", action="store_true", help="only run the counter-calibration copy")
+    ap.add_argument("--ingest-counters", metavar="DIR",
+                    help="only write the counter summary from the rocprofv3 --pmc runs under DIR")
+    ap.add_argument("--source-hash", help="with --ingest-counters: hash of the sources the runs were built from "
+                                          "(default: the sources here)")
     ap.add_argument("--fft-compare", action="store_true",
                     help="only time this library's 512^3 real transforms beside rocFFT's")
     ap.add_argument("--warm", type=int, default=0, metavar="K",
@@ -365,6 +467,10 @@ def main():
     a = ap.parse_args()
     if a.copy_probe:
         copy_probe()
+        return
+    if a.ingest_counters:
+        w = make_workload(a.workload)
+        ingest_counters(a.ingest_counters, w["workload"], a.source_hash or source_hash(), w["params"]["iters"])
         return
     if a.fft_compare:
         fft_compare()
