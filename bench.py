@@ -268,6 +268,79 @@ def solver_vs_poisson(w, reps=5):
             "paper": "15-42x a standard Poisson solver (Python with FFTW, Intel Core i7-9750H)"}
 
 
+def increment_bytes(N, K, half):
+    """Algorithmic HBM bytes of one increment solve (aqual_solve_increment,
+    fixed K, no residual) by the same counting as pass_bytes: complex entries
+    of 4 bytes (FP16 spectra) or 8 (FP32); the Newton spectrum of d_rho and
+    the last one-component spectrum stay FP32; the linearised x passes also
+    read the base field (3 R1)."""
+    C1 = N * N * (N // 2 + 1)
+    e = 4 if half else 8
+    Ch, Cf = C1 * e, C1 * 8
+    R1 = N ** 3 * 4
+    b = R1 + Cf                       # x_fwd_real of d_rho
+    b += 2 * Cf                       # y_fwd, one component, FP32
+    b += Cf + Cf + 3 * Ch             # z_newton: rho_hat in, phi_N_hat and dg_N out
+    b += 6 * Ch                       # y_inv
+    b += K * (6 * Ch + 3 * R1)        # x(linearised nu)
+    b += K * 6 * Ch                   # y_fwd
+    b += (K - 1) * (6 * Ch + 6 * Ch + 6 * Ch + 3 * R1 + 6 * Ch + 6 * Ch + Cf + 6 * Ch)  # z, y, x(mu), y, z(div), y
+    b += 3 * Ch + Cf                  # z_curl_final
+    b += 2 * Cf + Cf + R1             # y_inv (one component) and x_inv_real
+    return b
+
+
+def incremental_record(w, K=2, reps=10):
+    """The linearised increment solve (Sect. 5, item (v)) of one drift of the
+    workload, about the fields of a 6-iteration solve of the starting density,
+    outside the timed region: time per solve with FP32 and FP16 spectra
+    (best of reps), algorithmic bytes, and the FP16 result against the FP32
+    one."""
+    import torch
+    from paper_2312_02968_amd import mondpm as M
+    p = w["params"]
+    N = p["n_pad"]
+    R = N ** 3
+    ctx = M.pm_create(dict(p, iters=6, flags=p.get("flags", 0) | M.PM_F_RESIDUAL), len(w["mass"]))
+    pos = torch.from_numpy(w["pos"]).cuda()
+    vel = torch.from_numpy(w["vel"]).cuda()
+    mass = torch.from_numpy(w["mass"]).cuda()
+    rho = torch.empty(R, device="cuda")
+    M.pm_deposit(ctx, pos, mass, rho)
+    phi = torch.empty_like(rho)
+    F = torch.empty(3 * R, device="cuda")
+    M.aqual_solve_field(ctx, rho, phi, F, want_info=False)
+    gM = torch.empty_like(F)
+    M.pm_potential_field(ctx, phi, gM)
+    rho1 = torch.empty_like(rho)
+    M.pm_deposit(ctx, pos + float(w["dt"]) * vel, mass, rho1)
+    drho = rho1 - rho
+    del rho1
+    ctx.close()
+    ctx = M.pm_create(dict(p, iters=K), 0)
+    out = {"K": K, "base_iterations": 6, "drift": "one step of the workload's dt"}
+    res = {}
+    for name, st in (("fp32", M.PM_STORE_FP32), ("fp16", M.PM_STORE_FP16)):
+        d = torch.empty_like(rho)
+        M.aqual_solve_increment(ctx, drho, F, gM, d, storage=st, want_info=False)
+        torch.cuda.synchronize()
+        t = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            M.aqual_solve_increment(ctx, drho, F, gM, d, storage=st, want_info=False)
+            torch.cuda.synchronize()
+            t.append((time.perf_counter() - t0) * 1e3)
+        b = increment_bytes(N, K, st == M.PM_STORE_FP16)
+        res[name] = d
+        out[name] = {"ms": round(min(t), 3), "algorithmic_bytes": b,
+                     "achieved_gbs": round(b / (min(t) * 1e-3) / 1e9, 1)}
+    diff = (res["fp16"] - res["fp32"]).double().norm() / res["fp32"].double().norm()
+    out["fp16_vs_fp32_dphi_rel_l2"] = float(f"{float(diff):.3e}")
+    out["full_solve_bytes_K4"] = sum(v[0] for v in pass_bytes(N, p["iters"]).values())
+    ctx.close()
+    return out
+
+
 def make_workload(name):
     import workloads as W
     if name == "isothermal":
@@ -589,6 +662,8 @@ def main():
     }
     ctx.close()
     out["solver_vs_poisson"] = solver_vs_poisson(w)
+    if not a.warm and a.dft == "fp32":
+        out["incremental_step"] = incremental_record(w)
     if not a.no_starts and not a.warm and a.dft == "fp32":
         out.update(start_comparison(w))
     if not a.no_oracle_error and not a.warm and p["n_pad"] <= 512:

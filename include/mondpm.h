@@ -271,6 +271,45 @@ pm_status pm_apparent_density(pm_ctx* ctx, const float* phi, float* rho_a);
 pm_status aqual_solve_field(pm_ctx* ctx, const float* rho, const float* H0, float* phi, float* F,
                             pm_solve_info* info);
 
+/* ---- Linearised increments (Sect. 5, items (iv) and (v)) ---------------
+ * Between two steps the fields change little; the paper proposes to solve
+ * for the increments with Eqs. inverse and interpolation linearised about
+ * the previous fields,
+ *     dg_M = nu dF + nu'(F/a0) (F . dF) / (a0 |F|) F        (about F),
+ *     dF'  = mu dg_M + mu'(g_M/a0) (g_M . dg_M) / (a0 |g_M|) g_M   (about g_M),
+ * the linear steps (Newton field, curl-free and divergence-free
+ * projections) unchanged, and the increments stored in few digits.
+ *
+ * aqual_solve_increment runs the iteration of aqual_solve on increments:
+ * dg_N from d_rho, dH = 0, then iters times dF = dg_N + dH, dg_M from the
+ * first linearisation, its curl-free part (giving d_phi), and (except after
+ * the last) dF' from the second linearisation and dH = the divergence-free
+ * part of dF' - dg_N.  Both maps are zero where the field they are
+ * linearised about is zero.  d_rho: device float [n_pad^3]; F, gM: device
+ * float [3][n_pad^3], the previous solve's F (aqual_solve_field) and g_M
+ * (pm_potential_field of its phi); d_phi: device float [n_pad^3], written;
+ * d_F: device float [3][n_pad^3] or NULL, receives dF of the last
+ * iteration (F + d_F and the field of phi + d_phi are the next step's F and
+ * g_M).  storage: PM_STORE_FP32, or PM_STORE_FP16, which keeps every
+ * intermediate spectrum of the increments in FP16, each component of each
+ * pass's tile scaled by its own power of two (the Newton spectrum of d_rho
+ * and the last, one-component spectrum of d_phi stay FP32).  The residual
+ * r_k (PM_F_RESIDUAL or tol > 0) is ||dH_k - dH_{k-1}|| / ||dg_N||; info
+ * and tol behave as in aqual_solve.  The context's kept F (warm start) is
+ * overwritten when it computes residuals, so the next warm start on it
+ * starts from zero. */
+#define PM_STORE_FP32 0
+#define PM_STORE_FP16 1
+pm_status aqual_solve_increment(pm_ctx* ctx, const float* d_rho, const float* F, const float* gM,
+                                int32_t storage, float* d_phi, float* d_F, pm_solve_info* info);
+
+/* g = -i kt phi_hat on the FFT box: the field of a potential as the solve's
+ * curl-free projection forms it (kt the wavevector with the Nyquist entry
+ * zeroed, Sect. 2.1).  For the phi of aqual_solve it is that solve's g_M,
+ * the base of the second linearisation.  phi: device float [n_pad^3];
+ * g: device float [3][n_pad^3], written. */
+pm_status pm_potential_field(pm_ctx* ctx, const float* phi, float* g);
+
 /* ---- Learned starting guess --------------------------------------------
  * Sect. 2.1 lets the iteration start from any divergence-free H; the paper
  * starts from zero and notes that a good start saves iterations.  A 3-level

@@ -42,6 +42,7 @@ struct pm_ctx {
   float* phi = nullptr;
   float* fprev = nullptr;     // previous F for the residual and the warm start (optional)
   bool have_F = false;        // fprev holds the last F of a solve
+  float* scales = nullptr;    // scale tables of the increment solve's half-precision spectra
   double* partials = nullptr;
   double* dacc = nullptr;     // [0] |g_N|^2 sum, [1..64] residual sums, [80..89] diagnostics
   double hacc[128] = {};      // host copy of dacc
@@ -101,6 +102,10 @@ static int timer_of(PassKind k) {
     case PASS_X_FWD_REAL: return PM_T_X_FWD_REAL;
     case PASS_X_FWD_REAL3: return PM_T_X_FWD_REAL3;
     case PASS_X_INV_REAL: return PM_T_X_INV_REAL;
+    case PASS_X_INV_REAL3: return PM_T_X_INV_REAL;
+    case PASS_X_LIN_NU: return PM_T_X_NU;
+    case PASS_X_LIN_MU: return PM_T_X_MU;
+    case PASS_Z_GRAD: return PM_T_Z_FWD;
     case PASS_X_NU: return PM_T_X_NU;
     case PASS_X_MU: return PM_T_X_MU;
     case PASS_Y_FWD: return PM_T_Y_FWD;
@@ -214,6 +219,7 @@ static size_t carve(pm_ctx* c, Carver& cv) {
   c->rho = cv.take<float>(R);
   c->phi = cv.take<float>(R);
   c->fprev = (need_residual(c->p) || (c->p.flags & PM_F_WARM_START)) ? cv.take<float>(3 * R) : nullptr;
+  c->scales = cv.take<float>(scale_floats((int)N, c->P));
   c->partials = cv.take<double>((size_t)c->npartials);
   c->dacc = cv.take<double>(128);
   c->tw = cv.take<float2>(N);
@@ -340,6 +346,12 @@ pm_status pm_create(const pm_params* p, int64_t max_particles, void* workspace, 
   c->fg.comp_stride = (long long)C;
   c->fg.tw = c->tw;
   c->fg.bf16x3 = (p->flags & PM_F_DFT_BF16X3) ? 1 : 0;
+  c->fg.sc.xs = c->scales;
+  c->fg.sc.xcs = (long long)N * N;
+  c->fg.sc.ys = c->scales + 3 * c->fg.sc.xcs;
+  c->fg.sc.ycs = (long long)(c->P / 16) * N;
+  c->fg.sc.zs = c->fg.sc.ys + 3 * c->fg.sc.ycs;
+  c->fg.sc.zcs = 2 * c->fg.sc.ycs;
 
   c->kg.N = N;
   c->kg.n = p->n;
@@ -408,8 +420,19 @@ static ZArgs zargs(pm_ctx* c) {
   return z;
 }
 
+// The increment form of the solve (Sect. 5, item (v)): the density, the
+// Newton field and H are increments, Eqs. inverse and interpolation are
+// linearised about F and g_M of the previous solve, and the spectra between
+// passes are stored in FP16 when io = 1.
+struct Increment {
+  const float* F;      // [3][N^3] F = g_N + H of the previous solve
+  const float* gM;     // [3][N^3] its g_M (curl-free part of nu(|F|/a0) F)
+  int io;              // 0: FP32 spectra; 1: FP16
+  float* dF;           // nullable: receives dF of the last iteration
+};
+
 static pm_status run_solve(pm_ctx* c, const float* rho, const float* H0, float* phi_out, pm_solve_info* info,
-                           bool want_info) {
+                           bool want_info, const Increment* inc = nullptr) {
   const pm_params& p = c->p;
   const int N = c->N;
   const long long R = (long long)N * N * N;
@@ -417,21 +440,26 @@ static pm_status run_solve(pm_ctx* c, const float* rho, const float* H0, float* 
   const int K = p.iters;
   const float inv_a0 = (p.mu == PM_MU_NEWTON) ? 0.0f : (float)(1.0 / p.a0);
   const double N3 = (double)N * N * N;
+  const int io = inc ? inc->io : 0;
+  // the potential's spectrum: in place, or with FP16 spectra past their end
+  // (they fill the first half of the spectrum buffer)
+  float2* fin = io ? c->spec + (3 * c->fg.comp_stride) / 2 : c->spec;
   pm_solve_info loc{};
   loc.status = PM_OK;
 
-  // Newton: rho -> (x, y) spectrum in the phiN buffer
+  // Newton: rho -> (x, y) spectrum in the phiN buffer (the external-field
+  // sheets are constant, so an increment carries none)
   {
     PassDesc d = pdesc(PASS_X_FWD_REAL, c->phiN);
     d.real = const_cast<float*>(rho);
-    d.dip = c->dip;
+    if (!inc) d.dip = c->dip;
     HIPCHK(pass(c, d));
     HIPCHK(pass(c, pdesc(PASS_Y_FWD, c->phiN, 1)));
   }
   // warm start: F0 = P_L g_N + P_T F_prev from the last F of the previous solve
-  const bool keep_F = (p.flags & PM_F_WARM_START) != 0;
+  const bool keep_F = !inc && (p.flags & PM_F_WARM_START) != 0;
   const bool warm = keep_F && c->have_F && !H0;
-  const float* start = H0 ? H0 : (warm ? c->fprev : nullptr);
+  const float* start = inc ? nullptr : (H0 ? H0 : (warm ? c->fprev : nullptr));
   if (start) {
     PassDesc d = pdesc(PASS_X_FWD_REAL3, c->spec);
     d.real = const_cast<float*>(start);
@@ -439,22 +467,32 @@ static pm_status run_solve(pm_ctx* c, const float* rho, const float* H0, float* 
     HIPCHK(pass(c, d));
     HIPCHK(pass(c, pdesc(PASS_Y_FWD, c->spec, 3)));
   }
+  auto spec3 = [&](PassKind k) {
+    PassDesc d = pdesc(k, c->spec, 3);
+    d.io = io;
+    return d;
+  };
   {
     PassDesc d = pdesc(PASS_Z_NEWTON, c->spec);
     d.z = zargs(c);
-    d.z.with_h0 = warm ? 2 : (H0 ? 1 : 0);
+    d.z.with_h0 = warm ? 2 : (start ? 1 : 0);
+    d.io = io ? 2 : 0;
     HIPCHK(pass(c, d));
     HIPCHK(reduce_partials(c->partials, z_blocks(N), c->dacc, c->st));
-    HIPCHK(pass(c, pdesc(PASS_Y_INV, c->spec, 3)));
+    HIPCHK(pass(c, spec3(PASS_Y_INV)));
   }
   int k_done = 0;
   for (int k = 1; k <= K; ++k) {
     {
-      PassDesc d = pdesc(PASS_X_NU, c->spec, 3);
+      PassDesc d = spec3(inc ? PASS_X_LIN_NU : PASS_X_NU);
       d.mu_mode = p.mu;
       d.inv_a0 = inv_a0;
-      // F is kept every iteration for the residual; for the warm start only the last one
-      d.fprev = (resid || (keep_F && k == K)) ? c->fprev : nullptr;
+      d.base = inc ? inc->F : nullptr;
+      // F (or dF) is kept every iteration for the residual; for the warm start
+      // (or the caller's dF) only the last one
+      if (resid) d.fprev = c->fprev;
+      else if (keep_F && k == K) d.fprev = c->fprev;
+      else if (inc && inc->dF && k == K) d.fprev = inc->dF;
       d.partials = c->partials;
       HIPCHK(pass(c, d));
     }
@@ -475,37 +513,46 @@ static pm_status run_solve(pm_ctx* c, const float* rho, const float* H0, float* 
       }
     }
     k_done = k;
-    HIPCHK(pass(c, pdesc(PASS_Y_FWD, c->spec, 3)));
+    HIPCHK(pass(c, spec3(PASS_Y_FWD)));
     if (final_it) {
       PassDesc d = pdesc(PASS_Z_CURL_FINAL, c->spec);
       d.z = zargs(c);
+      d.io = io ? 3 : 0;
+      d.z.out = fin;
       HIPCHK(pass(c, d));
       break;
     }
     {
-      PassDesc d = pdesc(PASS_Z_CURL, c->spec);
+      PassDesc d = spec3(PASS_Z_CURL);
       d.z = zargs(c);
       HIPCHK(pass(c, d));
     }
-    HIPCHK(pass(c, pdesc(PASS_Y_INV, c->spec, 3)));
+    HIPCHK(pass(c, spec3(PASS_Y_INV)));
     {
-      PassDesc d = pdesc(PASS_X_MU, c->spec, 3);
+      PassDesc d = spec3(inc ? PASS_X_LIN_MU : PASS_X_MU);
       d.mu_mode = p.mu;
       d.inv_a0 = inv_a0;
+      d.base = inc ? inc->gM : nullptr;
       HIPCHK(pass(c, d));
     }
-    HIPCHK(pass(c, pdesc(PASS_Y_FWD, c->spec, 3)));
+    HIPCHK(pass(c, spec3(PASS_Y_FWD)));
     {
-      PassDesc d = pdesc(PASS_Z_DIV, c->spec);
+      PassDesc d = spec3(PASS_Z_DIV);
       d.z = zargs(c);
       HIPCHK(pass(c, d));
     }
-    HIPCHK(pass(c, pdesc(PASS_Y_INV, c->spec, 3)));
+    HIPCHK(pass(c, spec3(PASS_Y_INV)));
   }
-  if (resid || keep_F) c->have_F = true;
-  HIPCHK(pass(c, pdesc(PASS_Y_INV, c->spec, 1)));
+  if (inc) {
+    // fprev now holds an increment, not a field a warm start could use
+    if (resid) c->have_F = false;
+    if (resid && inc->dF) HIPCHK(hipMemcpyAsync(inc->dF, c->fprev, 3 * R * sizeof(float), hipMemcpyDeviceToDevice, c->st));
+  } else if (resid || keep_F) {
+    c->have_F = true;
+  }
+  HIPCHK(pass(c, pdesc(PASS_Y_INV, fin, 1)));
   {
-    PassDesc d = pdesc(PASS_X_INV_REAL, c->spec);
+    PassDesc d = pdesc(PASS_X_INV_REAL, fin);
     d.real = phi_out;
     HIPCHK(pass(c, d));
   }
@@ -925,6 +972,36 @@ pm_status aqual_solve_field(pm_ctx* c, const float* rho, const float* H0, float*
   if (info) info->bounds_flag = 0;
   const size_t R = (size_t)c->N * c->N * c->N;
   HIPCHK(hipMemcpyAsync(F, c->fprev, 3 * R * sizeof(float), hipMemcpyDeviceToDevice, c->st));
+  return PM_OK;
+}
+
+pm_status aqual_solve_increment(pm_ctx* c, const float* d_rho, const float* F, const float* gM, int32_t storage,
+                                float* d_phi, float* d_F, pm_solve_info* info) {
+  if (!c) return inval("ctx is NULL");
+  if (!d_rho || !F || !gM || !d_phi) return inval("d_rho, F, gM and d_phi are required");
+  if (storage != PM_STORE_FP32 && storage != PM_STORE_FP16) return inval("storage must be PM_STORE_FP32 or PM_STORE_FP16");
+  Increment inc{F, gM, storage == PM_STORE_FP16 ? 1 : 0, d_F};
+  pm_status s = run_solve(c, d_rho, nullptr, d_phi, info, info != nullptr, &inc);
+  if (s == PM_OK && info) info->bounds_flag = 0;
+  return s;
+}
+
+pm_status pm_potential_field(pm_ctx* c, const float* phi, float* g) {
+  if (!c) return inval("ctx is NULL");
+  if (!phi || !g) return inval("phi and g are required");
+  const long long R = (long long)c->N * c->N * c->N;
+  PassDesc d = pdesc(PASS_X_FWD_REAL, c->spec);
+  d.real = const_cast<float*>(phi);
+  HIPCHK(pass(c, d));
+  HIPCHK(pass(c, pdesc(PASS_Y_FWD, c->spec, 1)));
+  PassDesc z = pdesc(PASS_Z_GRAD, c->spec);
+  z.z = zargs(c);
+  HIPCHK(pass(c, z));
+  HIPCHK(pass(c, pdesc(PASS_Y_INV, c->spec, 3)));
+  PassDesc x = pdesc(PASS_X_INV_REAL3, c->spec);
+  x.real = g;
+  x.real_cs = R;
+  HIPCHK(pass(c, x));
   return PM_OK;
 }
 

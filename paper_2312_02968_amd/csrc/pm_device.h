@@ -203,6 +203,51 @@ __device__ __forceinline__ float mu_ratio(int mode, float gm, float inv_a0) {
   return x * rsqrtf(fmaf(x, x, 1.0f));
 }
 
+// Logarithmic slopes y nu'(y) / nu(y) and x mu'(x) / mu(x) of the same
+// functions, for the linearisations of Eqs. inverse and interpolation about
+// a field A (Sect. 5, item (v)):  f(|A|/a0) (dA + s (A . dA) / |A|^2 A).
+// Standard nu: s = -1 / (2 nu^2 y^2 sqrt(1/4 + 1/y^2)), written for y >= 1
+// as -t^2 / (nu^2 sqrt(1 + 4 t^2)), t = 1/y, with nu^2 = (1 + sqrt(1 + 4
+// t^2)) / 2, and for y < 1 as -1 / ((y + sqrt(y^2 + 4)) sqrt(1 + y^2/4));
+// deep MOND -1/2; Newton 0.  Standard mu: 1 / (1 + x^2); deep MOND 1;
+// Newton 0.
+__device__ __forceinline__ float nu_logslope(int mode, float y) {
+  if (mode == 2) return 0.0f;
+  if (mode == 1) return -0.5f;
+  if (y >= 1.0f) {
+    const float t = 1.0f / y;
+    const float q = sqrtf(fmaf(4.0f * t, t, 1.0f));
+    return -(t * t) / (0.5f * (1.0f + q) * q);
+  }
+  return -1.0f / ((y + sqrtf(fmaf(y, y, 4.0f))) * sqrtf(fmaf(0.25f * y, y, 1.0f)));
+}
+
+__device__ __forceinline__ float mu_logslope(int mode, float x) {
+  if (mode == 2) return 0.0f;
+  if (mode == 1) return 1.0f;
+  return 1.0f / fmaf(x, x, 1.0f);
+}
+
+// d <- the linearised map of Eq. inverse (MU = false: nu about A = F) or of
+// Eq. interpolation (MU = true: mu about A = g_M) applied to d; zero where
+// A = 0, where the maps have no derivative.
+template <bool MU>
+__device__ __forceinline__ void linearised(int mode, float inv_a0, float A0, float A1, float A2, float& d0,
+                                           float& d1, float& d2) {
+  const float am2 = A0 * A0 + A1 * A1 + A2 * A2;
+  if (!(am2 > 0.0f)) {
+    d0 = d1 = d2 = 0.0f;
+    return;
+  }
+  const float am = sqrtf(am2);
+  const float f = MU ? mu_ratio(mode, am, inv_a0) : nu_ratio(mode, am, inv_a0);
+  const float sl = MU ? mu_logslope(mode, am * inv_a0) : nu_logslope(mode, am * inv_a0);
+  const float c = sl * (A0 * d0 + A1 * d1 + A2 * d2) / am2;
+  d0 = f * fmaf(c, A0, d0);
+  d1 = f * fmaf(c, A1, d1);
+  d2 = f * fmaf(c, A2, d2);
+}
+
 }  // namespace pm
 
 namespace pm {

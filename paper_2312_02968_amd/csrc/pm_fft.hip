@@ -20,6 +20,8 @@
 // row is in LDS, which is where the algebraic equations (nu, mu) are applied.
 // Every pass reads its block's data completely before writing, and blocks
 // own disjoint data, so all passes run in place.
+#include <hip/hip_fp16.h>
+
 #include "pm_device.h"
 #include "pm_internal.h"
 
@@ -49,10 +51,67 @@ __device__ __forceinline__ long long sidx(long long row, int k, long long NN) {
 }
 
 // ----------------------------------------------------------------------------
+// Half-precision spectra of the increment solve.  The increments of the fields
+// from one step to the next are small, so they may be stored with few digits
+// (Sect. 5, items (iv) and (v)).  A stored complex value is (value / scale)
+// rounded to FP16 per part, where the scale is a power of two per field
+// component and writer tile, chosen so that the tile's largest part maps
+// below 2^15: every value within 2^29 of the tile's largest keeps FP16's 11
+// significant bits.  Tiles and their scale tables (Scales):
+//   x pass, one row (z, y):                xs[c][z N + y]
+//   y pass, 16 kx of one plane:            ys[c][kx / 16][plane]
+//   z pass, 8 kx of one ky row (all kz):   zs[c][kx / 16][ky][(kx % 16) / 8]
+// Every reader looks up the scale of each element it loads in the table of
+// the pass that wrote it: the x pass reads what the inverse y pass wrote,
+// the forward y pass what the x pass wrote, the z pass what the forward y
+// pass wrote and the inverse y pass what the z pass wrote.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ float tile_scale(float m) {
+  if (!(m > 0.0f) || !isfinite(m)) return 1.0f;     // zeros, or a NaN / Inf that passes through
+  int e;
+  frexpf(m, &e);                                     // m < 2^e
+  return ldexpf(1.0f, e - 15);
+}
+__device__ __forceinline__ float2 from_half(__half2 h, float scale) {
+  const float2 f = __half22float2(h);
+  return make_float2(f.x * scale, f.y * scale);
+}
+__device__ __forceinline__ __half2 to_half(float2 v, float inv) { return __floats2half2_rn(v.x * inv, v.y * inv); }
+__device__ __forceinline__ float amax2(float2 v) { return fmaxf(fabsf(v.x), fabsf(v.y)); }
+
+// Block-wide maximum of m[0..NC) (every thread gets the result).
+template <int NT, int NC>
+__device__ __forceinline__ void block_max(float* m) {
+  __shared__ float red[NC][NT / 64];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    float x = m[c];
+    for (int o = 32; o > 0; o >>= 1) x = fmaxf(x, __shfl_xor(x, o, 64));
+    if ((threadIdx.x & 63) == 0) red[c][threadIdx.x >> 6] = x;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    float x = red[c][0];
+    for (int w = 1; w < NT / 64; ++w) x = fmaxf(x, red[c][w]);
+    m[c] = x;
+  }
+}
+
+// ----------------------------------------------------------------------------
 // x pass
 // ----------------------------------------------------------------------------
-// XMODE
-enum { X_FWD_REAL = 0, X_INV_REAL = 1, X_FUSED_NU = 2, X_FUSED_MU = 3, X_FUSED_NU_KEEP = 4 };
+// XMODE.  X_LIN_*: the increment solve's linearised equations (pm_device.h,
+// linearised) about the base field `base` in place of nu / mu.
+enum { X_FWD_REAL = 0, X_INV_REAL = 1, X_FUSED_NU = 2, X_FUSED_MU = 3, X_FUSED_NU_KEEP = 4, X_LIN_NU = 5,
+       X_LIN_NU_KEEP = 6, X_LIN_MU = 7 };
+template <int XMODE>
+struct XKind {
+  static constexpr bool fused = XMODE == X_FUSED_NU || XMODE == X_FUSED_NU_KEEP || XMODE == X_FUSED_MU;
+  static constexpr bool lin = XMODE == X_LIN_NU || XMODE == X_LIN_NU_KEEP || XMODE == X_LIN_MU;
+  static constexpr bool keep = XMODE == X_FUSED_NU_KEEP || XMODE == X_LIN_NU_KEEP;
+  static constexpr bool mu = XMODE == X_FUSED_MU || XMODE == X_LIN_MU;
+};
 
 // r2c split: LDS holds Z = FFT_H(x[2m] + i x[2m+1]) for each sequence; turn
 // it into X[k], k = 0..H (X[H] goes to element H, one past the complex data).
@@ -124,11 +183,16 @@ __device__ __forceinline__ void add_dipole(float2& x, const Dipole& dip, long lo
 //                spectrum rows (in place).  X_FUSED_NU_KEEP is X_FUSED_NU that
 //                also accumulates the squared change of F against fprev in
 //                FP64 into partials[blockIdx.x] and stores F to fprev.
-template <int H, int ROWS, int NC, int NT, int XMODE>
+//   X_LIN_*    : as X_FUSED_* with the linearised maps about `base`.
+// IO = 1: the spectrum rows are FP16 (read with the y pass's scales, written
+// with one scale per row and component).
+template <int H, int ROWS, int NC, int NT, int XMODE, int IO = 0>
 __global__ __launch_bounds__(NT) void k_xpass(float2* spec, long long comp_stride,
                                               float* real, long long real_comp_stride,
                                               const float2* __restrict__ tw, int mu_mode, float inv_a0,
-                                              float* fprev, double* partials, Dipole dip) {
+                                              float* fprev, double* partials, Dipole dip,
+                                              const float* __restrict__ base, Scales sc) {
+  using XK = XKind<XMODE>;
   constexpr int S = NC * ROWS;
   constexpr int IS = S + 1;
   extern __shared__ float2 lds[];
@@ -137,6 +201,7 @@ __global__ __launch_bounds__(NT) void k_xpass(float2* spec, long long comp_strid
   const long long NN = (long long)N * N;
   float2* tw_s = lds + (H + 1) * IS;
   for (int t = threadIdx.x; t < N; t += NT) tw_s[t] = tw[t];
+  const __half2* spec_h = reinterpret_cast<const __half2*>(spec);
 
   // ---- load
   if (XMODE == X_FWD_REAL) {
@@ -152,11 +217,19 @@ __global__ __launch_bounds__(NT) void k_xpass(float2* spec, long long comp_strid
     for (int b = threadIdx.x; b < S * H; b += NT) {
       const int q = b / H, k = b % H;
       const int c = q / ROWS, r = q % ROWS;
-      lds[k * IS + q] = spec[c * comp_stride + sidx(row0 + r, k, NN)];
+      if constexpr (IO == 1)
+        lds[k * IS + q] = from_half(spec_h[c * comp_stride + sidx(row0 + r, k, NN)],
+                                    sc.ys[c * sc.ycs + (long long)(k >> 4) * N + (row0 + r) / N]);
+      else
+        lds[k * IS + q] = spec[c * comp_stride + sidx(row0 + r, k, NN)];
     }
     for (int q = threadIdx.x; q < S; q += NT) {
       const int c = q / ROWS, r = q % ROWS;
-      lds[H * IS + q] = spec[c * comp_stride + sidx(row0 + r, H, NN)];
+      if constexpr (IO == 1)
+        lds[H * IS + q] = from_half(spec_h[c * comp_stride + sidx(row0 + r, H, NN)],
+                                    sc.ys[c * sc.ycs + (long long)(H >> 4) * N + (row0 + r) / N]);
+      else
+        lds[H * IS + q] = spec[c * comp_stride + sidx(row0 + r, H, NN)];
     }
   }
   __syncthreads();
@@ -166,14 +239,14 @@ __global__ __launch_bounds__(NT) void k_xpass(float2* spec, long long comp_strid
     block_fft<H, S, NT, true, true>(lds, 1, IS, tw_s, 2);
   }
 
-  if (XMODE == X_FUSED_NU || XMODE == X_FUSED_NU_KEEP || XMODE == X_FUSED_MU) {
+  if constexpr (XK::fused || XK::lin) {
     double acc = 0.0;
     for (int b = threadIdx.x; b < ROWS * H; b += NT) {
       const int r = b % ROWS, m = b / ROWS;
       float2 v0 = lds[m * IS + r], v1 = lds[m * IS + ROWS + r], v2 = lds[m * IS + 2 * ROWS + r];
-      if (XMODE == X_FUSED_NU_KEEP) {
-        const long long e = (long long)(row0 + r) * N + 2 * m;
-        const long long cs = (long long)N * N * N;
+      const long long e = (long long)(row0 + r) * N + 2 * m;
+      const long long cs = (long long)N * N * N;
+      if (XK::keep) {
         float2* f0 = reinterpret_cast<float2*>(fprev + e);
         float2* f1 = reinterpret_cast<float2*>(fprev + cs + e);
         float2* f2 = reinterpret_cast<float2*>(fprev + 2 * cs + e);
@@ -184,21 +257,29 @@ __global__ __launch_bounds__(NT) void k_xpass(float2* spec, long long comp_strid
         *f0 = v0; *f1 = v1; *f2 = v2;
       }
       // two grid points per complex entry: .x is x = 2m, .y is x = 2m+1
-      {
-        const float m0 = sqrtf(v0.x * v0.x + v1.x * v1.x + v2.x * v2.x);
-        const float f = (XMODE != X_FUSED_MU) ? nu_ratio(mu_mode, m0, inv_a0) : mu_ratio(mu_mode, m0, inv_a0);
-        v0.x *= f; v1.x *= f; v2.x *= f;
-      }
-      {
-        const float m1 = sqrtf(v0.y * v0.y + v1.y * v1.y + v2.y * v2.y);
-        const float f = (XMODE != X_FUSED_MU) ? nu_ratio(mu_mode, m1, inv_a0) : mu_ratio(mu_mode, m1, inv_a0);
-        v0.y *= f; v1.y *= f; v2.y *= f;
+      if constexpr (XK::lin) {
+        const float2 b0 = *reinterpret_cast<const float2*>(base + e);
+        const float2 b1 = *reinterpret_cast<const float2*>(base + cs + e);
+        const float2 b2 = *reinterpret_cast<const float2*>(base + 2 * cs + e);
+        linearised<XK::mu>(mu_mode, inv_a0, b0.x, b1.x, b2.x, v0.x, v1.x, v2.x);
+        linearised<XK::mu>(mu_mode, inv_a0, b0.y, b1.y, b2.y, v0.y, v1.y, v2.y);
+      } else {
+        {
+          const float m0 = sqrtf(v0.x * v0.x + v1.x * v1.x + v2.x * v2.x);
+          const float f = !XK::mu ? nu_ratio(mu_mode, m0, inv_a0) : mu_ratio(mu_mode, m0, inv_a0);
+          v0.x *= f; v1.x *= f; v2.x *= f;
+        }
+        {
+          const float m1 = sqrtf(v0.y * v0.y + v1.y * v1.y + v2.y * v2.y);
+          const float f = !XK::mu ? nu_ratio(mu_mode, m1, inv_a0) : mu_ratio(mu_mode, m1, inv_a0);
+          v0.y *= f; v1.y *= f; v2.y *= f;
+        }
       }
       lds[m * IS + r] = v0;
       lds[m * IS + ROWS + r] = v1;
       lds[m * IS + 2 * ROWS + r] = v2;
     }
-    if (XMODE == X_FUSED_NU_KEEP) {
+    if (XK::keep) {
       // block reduction of acc (FP64)
       __shared__ double red[NT / 64];
       for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
@@ -216,14 +297,39 @@ __global__ __launch_bounds__(NT) void k_xpass(float2* spec, long long comp_strid
   if (XMODE != X_INV_REAL) {
     block_fft<H, S, NT, true, false>(lds, 1, IS, tw_s, 2);
     r2c_split<H, S, NT>(lds, IS, tw_s);
-    for (int b = threadIdx.x; b < S * H; b += NT) {
-      const int q = b / H, k = b % H;
-      const int c = q / ROWS, r = q % ROWS;
-      spec[c * comp_stride + sidx(row0 + r, k, NN)] = lds[k * IS + q];
-    }
-    for (int q = threadIdx.x; q < S; q += NT) {
-      const int c = q / ROWS, r = q % ROWS;
-      spec[c * comp_stride + sidx(row0 + r, H, NN)] = lds[H * IS + q];
+    if constexpr (IO == 1) {
+      // one scale per row and component: the largest part over k = 0..H
+      __shared__ float inv_s[S];
+      static_assert(S <= NT, "one thread per row and component");
+      if (threadIdx.x < S) {
+        const int q = threadIdx.x;
+        float mx = 0.0f;
+        for (int k = 0; k <= H; ++k) mx = fmaxf(mx, amax2(lds[k * IS + q]));
+        const float sc_q = tile_scale(mx);
+        inv_s[q] = 1.0f / sc_q;
+        sc.xs[(q / ROWS) * sc.xcs + row0 + q % ROWS] = sc_q;
+      }
+      __syncthreads();
+      __half2* dst_h = reinterpret_cast<__half2*>(spec);
+      for (int b = threadIdx.x; b < S * H; b += NT) {
+        const int q = b / H, k = b % H;
+        const int c = q / ROWS, r = q % ROWS;
+        dst_h[c * comp_stride + sidx(row0 + r, k, NN)] = to_half(lds[k * IS + q], inv_s[q]);
+      }
+      for (int q = threadIdx.x; q < S; q += NT) {
+        const int c = q / ROWS, r = q % ROWS;
+        dst_h[c * comp_stride + sidx(row0 + r, H, NN)] = to_half(lds[H * IS + q], inv_s[q]);
+      }
+    } else {
+      for (int b = threadIdx.x; b < S * H; b += NT) {
+        const int q = b / H, k = b % H;
+        const int c = q / ROWS, r = q % ROWS;
+        spec[c * comp_stride + sidx(row0 + r, k, NN)] = lds[k * IS + q];
+      }
+      for (int q = threadIdx.x; q < S; q += NT) {
+        const int c = q / ROWS, r = q % ROWS;
+        spec[c * comp_stride + sidx(row0 + r, H, NN)] = lds[H * IS + q];
+      }
     }
   } else {
     for (int b = threadIdx.x; b < S * H; b += NT) {
@@ -400,12 +506,13 @@ struct XWaves {
   static constexpr int value = (H == 256 && (XMODE == X_FUSED_NU || XMODE == X_FUSED_MU)) ? PM_X256_WAVES : 1;
 };
 
-template <int H, int XMODE, int NC>
+template <int H, int XMODE, int NC, int IO = 0>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(XWaves<H, XMODE>::value))) void k_xpass_wave(float2* spec, long long comp_stride, float* real,
                                                     long long real_comp_stride, const float2* __restrict__ tw,
                                                     int mu_mode, float inv_a0, float* fprev, double* partials,
-                                                    Dipole dip) {
+                                                    Dipole dip, const float* __restrict__ base, Scales sc) {
   using X = XWave<H>;
+  using XK = XKind<XMODE>;
   constexpr int N = X::N, LANES = X::LANES, RG = X::RG;
   constexpr long long NN = (long long)N * N;
   extern __shared__ float2 lds[];
@@ -434,11 +541,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(XWaves<H, X
   } else {
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      const float2* src = spec + c * comp_stride;
       float2 x[RG];
+      float2 nyq;
+      if constexpr (IO == 1) {
+        const __half2* src = reinterpret_cast<const __half2*>(spec) + c * comp_stride;
+        const float* ysc = sc.ys + c * sc.ycs + row / N;
 #pragma unroll
-      for (int r = 0; r < RG; ++r) x[r] = src[sidx(row, j + LANES * r, NN)];
-      const float2 nyq = src[sidx(row, H, NN)];
+        for (int r = 0; r < RG; ++r) {
+          const int k = j + LANES * r;
+          x[r] = from_half(src[sidx(row, k, NN)], ysc[(long long)(k >> 4) * N]);
+        }
+        nyq = from_half(src[sidx(row, H, NN)], ysc[(long long)(H >> 4) * N]);
+      } else {
+        const float2* src = spec + c * comp_stride;
+#pragma unroll
+        for (int r = 0; r < RG; ++r) x[r] = src[sidx(row, j + LANES * r, NN)];
+        nyq = src[sidx(row, H, NN)];
+      }
       // merge: Z[k] = (Xk + conj Xm) + i (Xk - conj Xm) conj(W^k), Xm = X[H - k]
 #pragma unroll
       for (int r = 0; r < RG; ++r) {
@@ -456,14 +575,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(XWaves<H, X
     for (int c = 0; c < NC; ++c) X::template fft<true>(v[c], xb, j, tw_s);
   }
 
-  if constexpr (XMODE == X_FUSED_NU || XMODE == X_FUSED_NU_KEEP || XMODE == X_FUSED_MU) {
+  if constexpr (XK::fused || XK::lin) {
     double acc = 0.0;
 #pragma unroll
     for (int r = 0; r < RG; ++r) {
       float2 a0 = v[0][r], a1 = v[1][r], a2 = v[2][r];
-      if (XMODE == X_FUSED_NU_KEEP) {
-        const long long e = row * N + 2 * (j + LANES * r);
-        const long long cs = (long long)N * N * N;
+      const long long e = row * N + 2 * (j + LANES * r);
+      const long long cs = (long long)N * N * N;
+      if (XK::keep) {
         float2* f0 = reinterpret_cast<float2*>(fprev + e);
         float2* f1 = reinterpret_cast<float2*>(fprev + cs + e);
         float2* f2 = reinterpret_cast<float2*>(fprev + 2 * cs + e);
@@ -473,15 +592,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(XWaves<H, X
         acc += d0 * d0 + d1 * d1 + d2 * d2 + e0 * e0 + e1 * e1 + e2 * e2;
         *f0 = a0; *f1 = a1; *f2 = a2;
       }
-      const float m0 = sqrtf(a0.x * a0.x + a1.x * a1.x + a2.x * a2.x);
-      const float m1 = sqrtf(a0.y * a0.y + a1.y * a1.y + a2.y * a2.y);
-      const float f0 = (XMODE != X_FUSED_MU) ? nu_ratio(mu_mode, m0, inv_a0) : mu_ratio(mu_mode, m0, inv_a0);
-      const float f1 = (XMODE != X_FUSED_MU) ? nu_ratio(mu_mode, m1, inv_a0) : mu_ratio(mu_mode, m1, inv_a0);
-      v[0][r] = make_float2(a0.x * f0, a0.y * f1);
-      v[1][r] = make_float2(a1.x * f0, a1.y * f1);
-      v[2][r] = make_float2(a2.x * f0, a2.y * f1);
+      if constexpr (XK::lin) {
+        const float2 b0 = *reinterpret_cast<const float2*>(base + e);
+        const float2 b1 = *reinterpret_cast<const float2*>(base + cs + e);
+        const float2 b2 = *reinterpret_cast<const float2*>(base + 2 * cs + e);
+        linearised<XK::mu>(mu_mode, inv_a0, b0.x, b1.x, b2.x, a0.x, a1.x, a2.x);
+        linearised<XK::mu>(mu_mode, inv_a0, b0.y, b1.y, b2.y, a0.y, a1.y, a2.y);
+        v[0][r] = a0;
+        v[1][r] = a1;
+        v[2][r] = a2;
+      } else {
+        const float m0 = sqrtf(a0.x * a0.x + a1.x * a1.x + a2.x * a2.x);
+        const float m1 = sqrtf(a0.y * a0.y + a1.y * a1.y + a2.y * a2.y);
+        const float f0 = !XK::mu ? nu_ratio(mu_mode, m0, inv_a0) : mu_ratio(mu_mode, m0, inv_a0);
+        const float f1 = !XK::mu ? nu_ratio(mu_mode, m1, inv_a0) : mu_ratio(mu_mode, m1, inv_a0);
+        v[0][r] = make_float2(a0.x * f0, a0.y * f1);
+        v[1][r] = make_float2(a1.x * f0, a1.y * f1);
+        v[2][r] = make_float2(a2.x * f0, a2.y * f1);
+      }
     }
-    if (XMODE == X_FUSED_NU_KEEP) {
+    if (XK::keep) {
       __shared__ double red[4];
       for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
       if (lane == 0) red[wave] = acc;
@@ -491,32 +621,70 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(XWaves<H, X
   }
 
   if (XMODE == X_INV_REAL) {
-    float2* dst = reinterpret_cast<float2*>(real + row * N);
 #pragma unroll
-    for (int r = 0; r < RG; ++r) dst[j + LANES * r] = v[0][r];
+    for (int c = 0; c < NC; ++c) {
+      float2* dst = reinterpret_cast<float2*>(real + c * real_comp_stride + row * N);
+#pragma unroll
+      for (int r = 0; r < RG; ++r) dst[j + LANES * r] = v[c][r];
+    }
     return;
   }
 
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     X::template fft<false>(v[c], xb, j, tw_s);
-    float2* dst = spec + c * comp_stride;
     // split: X[k] = E + W^k O, E = (Zk + conj Zm)/2, O = -i (Zk - conj Zm)/2
+    if constexpr (IO == 1) {
+      float2 o[RG];
+      float2 nyq = make_float2(0.0f, 0.0f);
+      float mx = 0.0f;
 #pragma unroll
-    for (int r = 0; r < RG; ++r) {
-      float2 zm;
-      zm.x = __shfl(v[c][RG - 1 - r].x, pl, 64);
-      zm.y = __shfl(v[c][RG - 1 - r].y, pl, 64);
-      if (j == 0) zm = v[c][(RG - r) & (RG - 1)];
-      const float2 zk = v[c][r];
-      const int k = j + LANES * r;
-      const float2 e = cscale(cadd(zk, cconj(zm)), 0.5f);
-      const float2 o = cscale(mul_mi<false>(csub(zk, cconj(zm))), 0.5f);
-      if (k == 0) {
-        dst[sidx(row, 0, NN)] = make_float2(zk.x + zk.y, 0.0f);
-        dst[sidx(row, H, NN)] = make_float2(zk.x - zk.y, 0.0f);
-      } else {
-        dst[sidx(row, k, NN)] = cadd(e, cmul(tw_s[k], o));
+      for (int r = 0; r < RG; ++r) {
+        float2 zm;
+        zm.x = __shfl(v[c][RG - 1 - r].x, pl, 64);
+        zm.y = __shfl(v[c][RG - 1 - r].y, pl, 64);
+        if (j == 0) zm = v[c][(RG - r) & (RG - 1)];
+        const float2 zk = v[c][r];
+        const int k = j + LANES * r;
+        const float2 e = cscale(cadd(zk, cconj(zm)), 0.5f);
+        const float2 od = cscale(mul_mi<false>(csub(zk, cconj(zm))), 0.5f);
+        if (k == 0) {
+          o[r] = make_float2(zk.x + zk.y, 0.0f);
+          nyq = make_float2(zk.x - zk.y, 0.0f);
+        } else {
+          o[r] = cadd(e, cmul(tw_s[k], od));
+        }
+        mx = fmaxf(mx, amax2(o[r]));
+      }
+      mx = fmaxf(mx, amax2(nyq));
+      // one scale per row: the largest part over the LANES lanes of the row
+      for (int w = LANES / 2; w > 0; w >>= 1) mx = fmaxf(mx, __shfl_xor(mx, w, 64));
+      const float sc_r = tile_scale(mx), inv = 1.0f / sc_r;
+      __half2* dst = reinterpret_cast<__half2*>(spec) + c * comp_stride;
+#pragma unroll
+      for (int r = 0; r < RG; ++r) dst[sidx(row, j + LANES * r, NN)] = to_half(o[r], inv);
+      if (j == 0) {
+        dst[sidx(row, H, NN)] = to_half(nyq, inv);
+        sc.xs[c * sc.xcs + row] = sc_r;
+      }
+    } else {
+      float2* dst = spec + c * comp_stride;
+#pragma unroll
+      for (int r = 0; r < RG; ++r) {
+        float2 zm;
+        zm.x = __shfl(v[c][RG - 1 - r].x, pl, 64);
+        zm.y = __shfl(v[c][RG - 1 - r].y, pl, 64);
+        if (j == 0) zm = v[c][(RG - r) & (RG - 1)];
+        const float2 zk = v[c][r];
+        const int k = j + LANES * r;
+        const float2 e = cscale(cadd(zk, cconj(zm)), 0.5f);
+        const float2 o = cscale(mul_mi<false>(csub(zk, cconj(zm))), 0.5f);
+        if (k == 0) {
+          dst[sidx(row, 0, NN)] = make_float2(zk.x + zk.y, 0.0f);
+          dst[sidx(row, H, NN)] = make_float2(zk.x - zk.y, 0.0f);
+        } else {
+          dst[sidx(row, k, NN)] = cadd(e, cmul(tw_s[k], o));
+        }
       }
     }
   }
@@ -572,13 +740,76 @@ __device__ __forceinline__ void store_cols(const float2* v, int E, float2* const
   }
 }
 
+// Half-precision forms of load_cols / store_cols.  Element (row i, column q)
+// of set c is src[c][i * row_stride + q] times the scale
+// scl[c][i * srs + ((q + qoff[c]) >> 3) * sq].
+template <int L, int T, int NT, int R, int NC>
+__device__ __forceinline__ void load_cols_h(float2* v, int E, const __half2* const* src, const int* nv,
+                                            long long row_stride, const float* const* scl, int srs, int sq,
+                                            const int* qoff) {
+  using B = Bfly<L, T, NT, R>;
+#pragma unroll
+  for (int u = 0; u < B::BPT; ++u) {
+    const int b = threadIdx.x + u * NT;
+    if (!B::valid(b)) continue;
+    const int q = b % T, j = b / T;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = j + r * (L / R);
+      const long long off = (long long)i * row_stride + q;
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        v[c * E + u * R + r] = (q < nv[c]) ? from_half(src[c][off], scl[c][i * srs + ((q + qoff[c]) >> 3) * sq])
+                                           : make_float2(0.0f, 0.0f);
+    }
+  }
+}
+
+// Largest part of each set's valid elements (as store_cols stores them).
+template <int L, int T, int NT, int R, int NC>
+__device__ __forceinline__ void cols_absmax(const float2* v, int E, const int* nv, float* m) {
+  using B = Bfly<L, T, NT, R>;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) m[c] = 0.0f;
+#pragma unroll
+  for (int u = 0; u < B::BPT; ++u) {
+    const int b = threadIdx.x + u * NT;
+    if (!B::valid(b)) continue;
+    const int q = b % T;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        if (q < nv[c]) m[c] = fmaxf(m[c], amax2(v[c * E + u * R + r]));
+  }
+}
+
+template <int L, int T, int NT, int R, int NC>
+__device__ __forceinline__ void store_cols_h(const float2* v, int E, __half2* const* dst, const int* nv,
+                                             long long row_stride, const float* inv) {
+  using B = Bfly<L, T, NT, R>;
+#pragma unroll
+  for (int u = 0; u < B::BPT; ++u) {
+    const int b = threadIdx.x + u * NT;
+    if (!B::valid(b)) continue;
+    const int q = b % T, j = b / T;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const long long off = (long long)(j + r * (L / R)) * row_stride + q;
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        if (q < nv[c]) dst[c][off] = to_half(v[c * E + u * R + r], inv[c]);
+    }
+  }
+}
+
 // y pass: one group of 16 kx columns of one z plane (a contiguous run of L
 // rows of 16 complex values), handled as 16 / T sets of T columns that share
 // the LDS exchange buffer (the buffer holds only T columns).  With T = 16 a
 // load instruction covers whole 128-byte rows of consecutive ky.
-template <int L, int T, int NT, bool INV>
+template <int L, int T, int NT, bool INV, int IO = 0>
 __global__ __launch_bounds__(NT) void k_ypass(float2* spec, long long comp_stride, int ncols,
-                                              const float2* __restrict__ tw) {
+                                              const float2* __restrict__ tw, Scales sc) {
   static_assert(16 % T == 0, "a y-pass block owns one group of 16 kx columns");
   constexpr int NH = 16 / T;
   constexpr int E = ColCfg<L, T, NT>::E;
@@ -604,7 +835,8 @@ __global__ __launch_bounds__(NT) void k_ypass(float2* spec, long long comp_strid
     t = nt - 1 - (int)(b / ((long long)L * nc));
   }
   const int x0 = t * 16;
-  float2* base = spec + comp * comp_stride + ((long long)t * L + kz) * L * 16;
+  const long long boff = comp * comp_stride + ((long long)t * L + kz) * L * 16;
+  float2* base = spec + boff;
   load_twiddles<L>(tw_s, tw, NT);
   float2 v[NH * E];
   using First = PlanAt<L, false, 0>;
@@ -616,10 +848,44 @@ __global__ __launch_bounds__(NT) void k_ypass(float2* spec, long long comp_strid
     nv[h] = min(T, ncols - x0 - h * T);
     ptr[h] = base + h * T;
   }
-  load_cols<L, T, NT, First::R, NH>(v, E, ptr, nv, 16);
+  if constexpr (IO == 1) {
+    // the forward pass reads what an x pass wrote (a scale per row ky of this
+    // plane), the inverse pass what a z pass wrote (a scale per ky and 8 kx)
+    __half2* hb = reinterpret_cast<__half2*>(spec) + boff;
+    const __half2* hp[NH];
+    const float* scl[NH];
+    int qoff[NH];
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+      hp[h] = hb + h * T;
+      qoff[h] = h * T;
+      scl[h] = INV ? sc.zs + comp * sc.zcs + (long long)t * L * 2 : sc.xs + comp * sc.xcs + (long long)kz * L;
+    }
+    load_cols_h<L, T, NT, First::R, NH>(v, E, hp, nv, 16, scl, INV ? 2 : 1, INV ? 1 : 0, qoff);
+  } else {
+    load_cols<L, T, NT, First::R, NH>(v, E, ptr, nv, 16);
+  }
   __syncthreads();
   col_fft<L, T, NT, NH, INV, false>(v, lds, tw_s, 1);
-  store_cols<L, T, NT, Last::R, NH>(v, E, ptr, nv, 16);
+  if constexpr (IO == 1) {
+    float m[NH];
+    cols_absmax<L, T, NT, Last::R, NH>(v, E, nv, m);
+#pragma unroll
+    for (int h = 1; h < NH; ++h) m[0] = fmaxf(m[0], m[h]);
+    block_max<NT, 1>(m);
+    const float scv = tile_scale(m[0]);
+    float inv[NH];
+    __half2* hp[NH];
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+      inv[h] = 1.0f / scv;
+      hp[h] = reinterpret_cast<__half2*>(spec) + boff + h * T;
+    }
+    store_cols_h<L, T, NT, Last::R, NH>(v, E, hp, nv, 16, inv);
+    if (threadIdx.x == 0) sc.ys[comp * sc.ycs + (long long)t * L + kz] = scv;
+  } else {
+    store_cols<L, T, NT, Last::R, NH>(v, E, ptr, nv, 16);
+  }
 }
 
 // ----------------------------------------------------------------------------
@@ -741,7 +1007,7 @@ __global__ __launch_bounds__(256) void k_ypass_mfma(float2* spec, long long comp
 }
 
 enum { Z_FWD = 0, Z_INV = 1, Z_NEWTON = 2, Z_CURL = 3, Z_CURL_FINAL = 4, Z_DIV = 5, Z_NEWTON_H0 = 6, Z_POISSON = 7,
-       Z_NEWTON_WARM = 8, Z_APPARENT = 9 };
+       Z_NEWTON_WARM = 8, Z_APPARENT = 9, Z_GRAD = 10 };
 
 template <int ZOP> struct ZComp;
 template <> struct ZComp<Z_FWD>        { static constexpr int IN = 1, OUT = 1; };
@@ -754,6 +1020,7 @@ template <> struct ZComp<Z_CURL_FINAL> { static constexpr int IN = 3, OUT = 1; }
 template <> struct ZComp<Z_DIV>        { static constexpr int IN = 3, OUT = 3; };
 template <> struct ZComp<Z_POISSON>    { static constexpr int IN = 1, OUT = 1; };
 template <> struct ZComp<Z_APPARENT>   { static constexpr int IN = 1, OUT = 1; };
+template <> struct ZComp<Z_GRAD>       { static constexpr int IN = 1, OUT = 3; };
 
 // z pass: forward z transform of the input components, the spectral operator
 // at every (kx, ky, kz) in registers, inverse z transform, store.  A block
@@ -775,8 +1042,14 @@ template <> struct ZComp<Z_APPARENT>   { static constexpr int IN = 1, OUT = 1; }
 //   Z_NEWTON_WARM: as Z_NEWTON_H0 with the previous F in place of H0, whose
 //                 divergence-free part minus that of g_N starts H:
 //                 F = P_L g_N + P_T F_prev
-template <int L, int T, int NT, int HZ, int ZOP>
-__global__ __launch_bounds__(NT) void k_zpass(ZArgs a, const float2* __restrict__ tw) {
+//   Z_GRAD      : g = -i kt phi_hat / N^3 (three output components), the field
+//                 of a potential as the curl-free projection forms it
+// IO as PassDesc::io; the half-precision forms read the forward y pass's
+// scales and write one scale per component of the block's 8 kx columns.
+template <int L, int T, int NT, int HZ, int ZOP, int IO = 0>
+__global__ __launch_bounds__(NT) void k_zpass(ZArgs a, const float2* __restrict__ tw, Scales sc) {
+  constexpr bool IN_H = IO == 1 || IO == 3, OUT_H = IO == 1 || IO == 2;
+  static_assert(!(IN_H || OUT_H) || (HZ == 1 && T == 8), "half-precision z tiles are 8 kx columns");
   constexpr int E = ColCfg<L, T, NT>::E;
   constexpr int NIN = ZComp<ZOP>::IN, NOUT = ZComp<ZOP>::OUT;
   constexpr int NV = NIN > NOUT ? NIN : NOUT;
@@ -854,7 +1127,24 @@ __global__ __launch_bounds__(NT) void k_zpass(ZArgs a, const float2* __restrict_
         }
     }
   }
-  load_cols<L, T, NT, First::R, HZ * NIN>(v, E, src, nvs, row);
+  if constexpr (IN_H) {
+    // half-precision inputs (never phi_N, which stays FP32): scale per kz of
+    // the forward y pass's tile (group, plane kz)
+    const __half2* hs[HZ * NIN];
+    const float* scl[HZ * NIN];
+    int qoff[HZ * NIN];
+#pragma unroll
+    for (int c = 0; c < NIN; ++c)
+#pragma unroll
+      for (int h = 0; h < HZ; ++h) {
+        hs[HZ * c + h] = reinterpret_cast<const __half2*>(a.spec) + c * a.comp_stride + off + h * T;
+        scl[HZ * c + h] = sc.ys + c * sc.ycs + (long long)grp * L;
+        qoff[HZ * c + h] = 0;
+      }
+    load_cols_h<L, T, NT, First::R, HZ * NIN>(v, E, hs, nvs, row, scl, 1, 0, qoff);
+  } else {
+    load_cols<L, T, NT, First::R, HZ * NIN>(v, E, src, nvs, row);
+  }
   __syncthreads();
   col_fft<L, T, NT, HZ * NIN, false, false>(v, lds, tw_s, 1);
   if (ZOP == Z_FWD) {
@@ -888,6 +1178,13 @@ __global__ __launch_bounds__(NT) void k_zpass(ZArgs a, const float2* __restrict_
           const float k2 = kx * kx + ky * ky + kzz * kzz;
           const float A = (k2 > 0.0f) ? 1.0f / k2 : 0.0f;
           v[h * E + e] = cscale(v[h * E + e], a.newton_coef * A * a.scale);
+          continue;
+        }
+        if constexpr (ZOP == Z_GRAD) {
+          const float2 g = cscale(mul_mi<false>(v[h * E + e]), a.scale);     // -i phi_hat / N^3
+          v[(0 * HZ + h) * E + e] = cscale(g, tx);
+          v[(1 * HZ + h) * E + e] = cscale(g, ty);
+          v[(2 * HZ + h) * E + e] = cscale(g, a.kt[kz]);
           continue;
         }
         if constexpr (ZOP == Z_APPARENT) {
@@ -981,11 +1278,29 @@ __global__ __launch_bounds__(NT) void k_zpass(ZArgs a, const float2* __restrict_
   // ---- inverse z transform with the reversed plan: its first stage takes the
   // elements the forward last stage produced, so no exchange is needed here.
   col_fft<L, T, NT, HZ * NOUT, true, true>(v, lds, tw_s, 1);
+  if constexpr (OUT_H) {
+    float m[NOUT], inv[NOUT];
+    __half2* hd[NOUT];
+    cols_absmax<L, T, NT, First::R, NOUT>(v, E, nvs, m);
+    block_max<NT, NOUT>(m);
+#pragma unroll
+    for (int c = 0; c < NOUT; ++c) {
+      const float scv = tile_scale(m[c]);
+      inv[c] = 1.0f / scv;
+      hd[c] = reinterpret_cast<__half2*>(a.spec) + c * a.comp_stride + off;
+      if (threadIdx.x == 0) sc.zs[c * sc.zcs + ((long long)grp * L + y) * 2 + ((x0 & 15) >> 3)] = scv;
+    }
+    store_cols_h<L, T, NT, First::R, NOUT>(v, E, hd, nvs, row, inv);
+    return;
+  }
+  // (an FP32 result of half-precision input goes to a.out: written in place
+  // it would overlap FP16 columns other blocks have still to read)
+  float2* obase = a.out ? a.out : a.spec;
   float2* dst[HZ * NOUT];
 #pragma unroll
   for (int c = 0; c < NOUT; ++c)
 #pragma unroll
-    for (int h = 0; h < HZ; ++h) dst[HZ * c + h] = a.spec + c * a.comp_stride + off + h * T;
+    for (int h = 0; h < HZ; ++h) dst[HZ * c + h] = obase + c * a.comp_stride + off + h * T;
   store_cols<L, T, NT, First::R, HZ * NOUT>(v, E, dst, nvs, row);
 }
 
@@ -1020,32 +1335,33 @@ struct Cfg {
   static constexpr int TZ = PM_TZ;
 };
 
-template <int N, int XMODE, int NC>
+template <int N, int XMODE, int NC, int IO = 0>
 hipError_t launch_x(const FftGeom& g, float2* spec, float* real, long long real_cs, int mu_mode,
-                    float inv_a0, float* fprev, double* partials, hipStream_t st, Dipole dip = Dipole{}) {
+                    float inv_a0, float* fprev, double* partials, hipStream_t st, Dipole dip = Dipole{},
+                    const float* base = nullptr) {
   using C = Cfg<N>;
   if constexpr (N == 512 || N == 1024) {
     using X = XWave<N / 2>;
     const size_t sh = sizeof(float2) * (N + (size_t)X::ROWS * X::XB);
-    hipLaunchKernelGGL((k_xpass_wave<N / 2, XMODE, NC>), dim3(N * N / X::ROWS), dim3(256), sh, st, spec,
-                       g.comp_stride, real, real_cs, g.tw, mu_mode, inv_a0, fprev, partials, dip);
+    hipLaunchKernelGGL((k_xpass_wave<N / 2, XMODE, NC, IO>), dim3(N * N / X::ROWS), dim3(256), sh, st, spec,
+                       g.comp_stride, real, real_cs, g.tw, mu_mode, inv_a0, fprev, partials, dip, base, g.sc);
     return hipGetLastError();
   } else {
     const int blocks = N * N / C::ROWS;
     const size_t sh = sizeof(float2) * ((size_t)(C::H + 1) * (NC * C::ROWS + 1) + N);
-    hipLaunchKernelGGL((k_xpass<C::H, C::ROWS, NC, kNT, XMODE>), dim3(blocks), dim3(kNT), sh, st, spec,
-                       g.comp_stride, real, real_cs, g.tw, mu_mode, inv_a0, fprev, partials, dip);
+    hipLaunchKernelGGL((k_xpass<C::H, C::ROWS, NC, kNT, XMODE, IO>), dim3(blocks), dim3(kNT), sh, st, spec,
+                       g.comp_stride, real, real_cs, g.tw, mu_mode, inv_a0, fprev, partials, dip, base, g.sc);
     return hipGetLastError();
   }
 }
 
-template <int N, bool INV>
+template <int N, bool INV, int IO = 0>
 hipError_t launch_y(const FftGeom& g, float2* spec, int ncomp, hipStream_t st) {
   using C = Cfg<N>;
   const int tiles = (C::H + 1 + 15) / 16;
   const size_t sh = sizeof(float2) * ((size_t)ColBuf<N, C::TY>::elems + N);
-  hipLaunchKernelGGL((k_ypass<N, C::TY, kNT, INV>), dim3(tiles, N, ncomp), dim3(kNT), sh, st, spec,
-                     g.comp_stride, C::H + 1, g.tw);
+  hipLaunchKernelGGL((k_ypass<N, C::TY, kNT, INV, IO>), dim3(tiles, N, ncomp), dim3(kNT), sh, st, spec,
+                     g.comp_stride, C::H + 1, g.tw, g.sc);
   return hipGetLastError();
 }
 
@@ -1063,13 +1379,14 @@ hipError_t launch_y_mfma(const FftGeom& g, float2* spec, int ncomp, hipStream_t 
   }
 }
 
-template <int N, int ZOP>
+template <int N, int ZOP, int IO = 0>
 hipError_t launch_z(const FftGeom& g, ZArgs a, hipStream_t st) {
   using C = Cfg<N>;
   const size_t sh = sizeof(float2) * ((size_t)ColBuf<N, C::TZ>::elems + N);
   a.comp_stride = g.comp_stride;
   a.ncols = C::H + 1;
-  hipLaunchKernelGGL((k_zpass<N, C::TZ, kNTZ, PM_HZ, ZOP>), dim3(z_blocks(N)), dim3(kNTZ), sh, st, a, g.tw);
+  hipLaunchKernelGGL((k_zpass<N, C::TZ, kNTZ, PM_HZ, ZOP, IO>), dim3(z_blocks(N)), dim3(kNTZ), sh, st, a, g.tw,
+                     g.sc);
   return hipGetLastError();
 }
 
@@ -1082,26 +1399,49 @@ hipError_t run_pass(const FftGeom& g, const PassDesc& d, hipStream_t st) {
       return launch_x<N, X_FWD_REAL, 3>(g, d.spec, d.real, d.real_cs, 0, 0.f, nullptr, nullptr, st);
     case PASS_X_INV_REAL:
       return launch_x<N, X_INV_REAL, 1>(g, d.spec, d.real, d.real_cs, 0, 0.f, nullptr, nullptr, st);
+    case PASS_X_INV_REAL3:
+      return launch_x<N, X_INV_REAL, 3>(g, d.spec, d.real, d.real_cs, 0, 0.f, nullptr, nullptr, st);
     case PASS_X_NU:
       if (d.fprev)
         return launch_x<N, X_FUSED_NU_KEEP, 3>(g, d.spec, nullptr, 0, d.mu_mode, d.inv_a0, d.fprev, d.partials, st);
       return launch_x<N, X_FUSED_NU, 3>(g, d.spec, nullptr, 0, d.mu_mode, d.inv_a0, nullptr, nullptr, st);
     case PASS_X_MU:
       return launch_x<N, X_FUSED_MU, 3>(g, d.spec, nullptr, 0, d.mu_mode, d.inv_a0, nullptr, nullptr, st);
+    case PASS_X_LIN_NU:
+      if (d.io == 1)
+        return d.fprev ? launch_x<N, X_LIN_NU_KEEP, 3, 1>(g, d.spec, nullptr, 0, d.mu_mode, d.inv_a0, d.fprev,
+                                                          d.partials, st, Dipole{}, d.base)
+                       : launch_x<N, X_LIN_NU, 3, 1>(g, d.spec, nullptr, 0, d.mu_mode, d.inv_a0, nullptr, nullptr,
+                                                     st, Dipole{}, d.base);
+      return d.fprev ? launch_x<N, X_LIN_NU_KEEP, 3>(g, d.spec, nullptr, 0, d.mu_mode, d.inv_a0, d.fprev,
+                                                     d.partials, st, Dipole{}, d.base)
+                     : launch_x<N, X_LIN_NU, 3>(g, d.spec, nullptr, 0, d.mu_mode, d.inv_a0, nullptr, nullptr, st,
+                                                Dipole{}, d.base);
+    case PASS_X_LIN_MU:
+      if (d.io == 1)
+        return launch_x<N, X_LIN_MU, 3, 1>(g, d.spec, nullptr, 0, d.mu_mode, d.inv_a0, nullptr, nullptr, st,
+                                           Dipole{}, d.base);
+      return launch_x<N, X_LIN_MU, 3>(g, d.spec, nullptr, 0, d.mu_mode, d.inv_a0, nullptr, nullptr, st, Dipole{},
+                                      d.base);
     case PASS_Y_FWD:
+      if (d.io == 1) return launch_y<N, false, 1>(g, d.spec, d.ncomp, st);
       return g.bf16x3 ? launch_y_mfma<N, false>(g, d.spec, d.ncomp, st) : launch_y<N, false>(g, d.spec, d.ncomp, st);
     case PASS_Y_INV:
+      if (d.io == 1) return launch_y<N, true, 1>(g, d.spec, d.ncomp, st);
       return g.bf16x3 ? launch_y_mfma<N, true>(g, d.spec, d.ncomp, st) : launch_y<N, true>(g, d.spec, d.ncomp, st);
     case PASS_Z_FWD: return launch_z<N, Z_FWD>(g, d.z, st);
     case PASS_Z_INV: return launch_z<N, Z_INV>(g, d.z, st);
     case PASS_Z_NEWTON:
+      if (d.io == 2) return launch_z<N, Z_NEWTON, 2>(g, d.z, st);
       if (d.z.with_h0 == 2) return launch_z<N, Z_NEWTON_WARM>(g, d.z, st);
       return d.z.with_h0 ? launch_z<N, Z_NEWTON_H0>(g, d.z, st) : launch_z<N, Z_NEWTON>(g, d.z, st);
-    case PASS_Z_CURL: return launch_z<N, Z_CURL>(g, d.z, st);
-    case PASS_Z_CURL_FINAL: return launch_z<N, Z_CURL_FINAL>(g, d.z, st);
-    case PASS_Z_DIV: return launch_z<N, Z_DIV>(g, d.z, st);
+    case PASS_Z_CURL: return d.io == 1 ? launch_z<N, Z_CURL, 1>(g, d.z, st) : launch_z<N, Z_CURL>(g, d.z, st);
+    case PASS_Z_CURL_FINAL:
+      return d.io == 3 ? launch_z<N, Z_CURL_FINAL, 3>(g, d.z, st) : launch_z<N, Z_CURL_FINAL>(g, d.z, st);
+    case PASS_Z_DIV: return d.io == 1 ? launch_z<N, Z_DIV, 1>(g, d.z, st) : launch_z<N, Z_DIV>(g, d.z, st);
     case PASS_Z_POISSON: return launch_z<N, Z_POISSON>(g, d.z, st);
     case PASS_Z_APPARENT: return launch_z<N, Z_APPARENT>(g, d.z, st);
+    case PASS_Z_GRAD: return launch_z<N, Z_GRAD>(g, d.z, st);
   }
   return hipErrorInvalidValue;
 }

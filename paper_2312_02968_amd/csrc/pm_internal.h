@@ -5,6 +5,17 @@
 
 namespace pm {
 
+// Scales of the half-precision spectra of the increment solve: one power of
+// two per field component and writer tile (see pm_fft.hip), in three tables
+// by the kind of pass that wrote the tile.
+struct Scales {
+  float* xs = nullptr;    // x pass: [3][N * N], one per row (row = z N + y)
+  float* ys = nullptr;    // y pass: [3][P / 16][N], one per group of 16 kx and plane
+  float* zs = nullptr;    // z pass: [3][P / 16][N][2], one per 8 kx of a ky row
+  long long xcs = 0, ycs = 0, zcs = 0;   // per-component strides
+};
+inline size_t scale_floats(int N, int P) { return 3 * ((size_t)N * N + (size_t)(P / 16) * N * 3); }
+
 // Geometry of the FFT box and its half spectrum.
 struct FftGeom {
   int N;                  // n_pad
@@ -12,11 +23,13 @@ struct FftGeom {
   long long comp_stride;  // complex entries per spectrum component (N * N * P)
   const float2* tw;       // exp(-2 pi i t / N), t < N
   int bf16x3 = 0;         // y passes with the radix-16 stage on the matrix cores (BF16x3)
+  Scales sc{};            // scale tables of the half-precision spectra
 };
 
 // Arguments of a z pass (see pm_fft.hip).
 struct ZArgs {
   float2* spec;
+  float2* out = nullptr;   // FP32 output spectrum when it differs from spec (half-precision input)
   long long comp_stride;
   int ncols;
   float2* phiN;
@@ -31,7 +44,8 @@ struct ZArgs {
 };
 
 enum PassKind {
-  PASS_X_FWD_REAL, PASS_X_FWD_REAL3, PASS_X_INV_REAL, PASS_X_NU, PASS_X_MU,
+  PASS_X_FWD_REAL, PASS_X_FWD_REAL3, PASS_X_INV_REAL, PASS_X_INV_REAL3, PASS_X_NU, PASS_X_MU,
+  PASS_X_LIN_NU, PASS_X_LIN_MU, PASS_Z_GRAD,
   PASS_Y_FWD, PASS_Y_INV,
   PASS_Z_FWD, PASS_Z_INV, PASS_Z_NEWTON, PASS_Z_CURL, PASS_Z_CURL_FINAL, PASS_Z_DIV, PASS_Z_POISSON, PASS_Z_APPARENT
 };
@@ -56,6 +70,11 @@ struct PassDesc {
   double* partials = nullptr;
   int ncomp = 1;
   ZArgs z{};
+  // storage of the spectra the pass reads and writes: 0 FP32; 1 FP16 in and
+  // out; 2 FP32 in, FP16 out; 3 FP16 in, FP32 out (the half-precision forms
+  // exist for the passes of the increment solve)
+  int io = 0;
+  const float* base = nullptr;   // PASS_X_LIN_*: the field linearised about, [3][N^3]
 };
 
 hipError_t fft_pass(const FftGeom& g, const PassDesc& d, hipStream_t st);

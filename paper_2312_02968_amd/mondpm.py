@@ -23,6 +23,8 @@ PM_F_ANALYTIC_NORM = 0x1
 PM_F_RESIDUAL = 0x2
 PM_F_WARM_START = 0x4
 PM_F_DFT_BF16X3 = 0x8
+PM_STORE_FP32 = 0
+PM_STORE_FP16 = 1
 TIMERS = ["x_fwd_real", "x_fwd_real3", "x_inv_real", "x_nu", "x_mu", "y_fwd", "y_inv", "z_fwd",
           "z_inv", "z_newton", "z_curl", "z_curl_final", "z_div", "sort", "deposit", "gather", "fill",
           "reduce"]
@@ -83,6 +85,8 @@ def lib():
         L.pm_apparent_density.argtypes = [VP, VP, VP]
         L.pm_set_external_field.argtypes = [VP, D, D, D]
         L.aqual_solve_field.argtypes = [VP, VP, VP, VP, VP, P(PmSolveInfo)]
+        L.aqual_solve_increment.argtypes = [VP, VP, VP, VP, I32, VP, VP, P(PmSolveInfo)]
+        L.pm_potential_field.argtypes = [VP, VP, VP]
         L.pm_net_param_count.argtypes = []
         L.pm_net_param_count.restype = I64
         L.pm_net_create.argtypes = [I32, I32, VP, P(VP)]
@@ -341,6 +345,27 @@ def aqual_solve_field(ctx: Ctx, rho, phi, F, H0=None, want_info=True):
                                    _ptr(F, numel=3 * R, name="F"),
                                    ctypes.byref(info) if want_info else None), "aqual_solve_field")
     return info.to_dict() if want_info else None
+
+
+def aqual_solve_increment(ctx: Ctx, d_rho, F, gM, d_phi, storage=PM_STORE_FP16, d_F=None, want_info=True):
+    """Linearised increment solve (see include/mondpm.h): d_phi from d_rho
+    about the previous F and g_M, with FP16 (default) or FP32 spectra."""
+    R = ctx.N ** 3
+    info = PmSolveInfo()
+    _check(lib().aqual_solve_increment(ctx.handle, _ptr(d_rho, numel=R, name="d_rho"),
+                                       _ptr(F, numel=3 * R, name="F"), _ptr(gM, numel=3 * R, name="gM"),
+                                       int(storage), _ptr(d_phi, numel=R, name="d_phi"),
+                                       _ptr(d_F, numel=3 * R, name="d_F"),
+                                       ctypes.byref(info) if want_info else None), "aqual_solve_increment")
+    return info.to_dict() if want_info else None
+
+
+def pm_potential_field(ctx: Ctx, phi, g):
+    """g = -i kt phi_hat on the FFT box (the field of phi as the curl-free
+    projection forms it)."""
+    R = ctx.N ** 3
+    _check(lib().pm_potential_field(ctx.handle, _ptr(phi, numel=R, name="phi"), _ptr(g, numel=3 * R, name="g")),
+           "pm_potential_field")
 
 
 def pm_net_param_count() -> int:

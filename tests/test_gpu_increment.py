@@ -1,0 +1,226 @@
+"""Parity of the linearised increment solve (Sect. 5, items (iv) and (v)) with
+the FP64 oracle, through the C ABI.
+
+The base fields F and g_M come from the oracle's base state
+(``linearised.base_state``), rounded to FP32; the oracle receives the same
+rounded values.  With FP32 spectra the increment solve is held to the
+potential's 1e-5 bar.
+
+With FP16 spectra the reference is the FP64 oracle without rounding.  The
+GPU rounds every spectrum it stores between passes (about ten roundings per
+iteration, in the mixed spaces of the three-pass transform), the oracle's
+FP16 model the four real-space increment fields.  Rounding a spectrum to a
+relative precision leaves noise that follows the signal's own spectrum,
+where real-space rounding spreads it evenly over k and the potential's
+1/k^2 weighting suppresses most of it; so the GPU's increment error is about
+five times the oracle model's (3.2e-4 against 5.7e-5 on these inputs, and a
+numpy model of the GPU's rounding points gives 3.1e-4, most of it from the
+y and z passes' outputs).  The bars: the increment's potential within FP16's
+unit roundoff 2^-11 of the exact increment and its force within 2^-10 (the
+difference weights high k, where the noise is relatively larger: measured
+4.1-5.0e-4), and the force error it causes below 1e-5 of the step's total
+force (the paper's accuracy target), with the oracle model's figures
+reported beside them.  Properties at any size:
+doubling d_rho doubles d_phi bit for bit (every step is linear and the tile
+scales are powers of two), a zero increment gives zero, and with mu = 1 the
+increment is the solve of d_rho.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import linearised as lin  # noqa: E402
+from oracle import pm as orc  # noqa: E402
+import workloads as W  # noqa: E402
+from tests.gpu_util import dev, host, oparams, rel_l2, rel_max, grid  # noqa: E402
+
+
+def _log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def M():
+    from paper_2312_02968_amd import mondpm
+    mondpm.lib()
+    return mondpm
+
+
+def _f32(a):
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def _case(mu, seed=3, n=32, npart=2000, base_iters=8):
+    """Cloud of 2000 particles in a 32^3 region (64^3 box), its density, the
+    density change of one drift by the velocities, and the oracle's base."""
+    w = W.random_cloud(seed, n, npart, mu=mu, vmax=0.5)
+    p = oparams(w["params"])
+    pos = w["pos"].astype(np.float64)
+    m = w["mass"].astype(np.float64)
+    rho = _f32(orc.deposit(p, pos, m))
+    drho = _f32(orc.deposit(p, pos + w["vel"].astype(np.float64), m) - rho)
+    b = lin.base_state(p, rho, max_iters=base_iters)
+    b32 = dict(b, F=_f32(b["F"]), gM=_f32(b["gM"]))
+    return w, p, rho, drho, b32
+
+
+@pytest.fixture(scope="module", params=[orc.MU_STANDARD, orc.MU_DEEP], ids=["standard", "deep"])
+def case(request):
+    return _case(request.param)
+
+
+def _ctx(M, w, K, resid=True):
+    prm = dict(w["params"], iters=K, flags=M.PM_F_RESIDUAL if resid else 0)
+    return M.pm_create(prm, 0)
+
+
+def _gpu_increment(M, ctx, drho, b, storage, d_F=None):
+    N = ctx.N
+    out = grid(N)
+    info = M.aqual_solve_increment(ctx, dev(drho), dev(b["F"]), dev(b["gM"]), out, storage=storage, d_F=d_F)
+    return host(out).reshape(N, N, N), info
+
+
+@pytest.mark.parametrize("K", [1, 2, 3])
+def test_fp32_increment_matches_oracle(M, case, K):
+    w, p, rho, drho, b = case
+    _log("increment fp32", p.mu, K)
+    ref, res = lin.incremental_solve(p, b, drho, K)
+    ctx = _ctx(M, w, K)
+    got, info = _gpu_increment(M, ctx, drho, b, M.PM_STORE_FP32)
+    e2, em = rel_l2(got, ref), rel_max(got, ref)
+    _log(f"  d_phi rel L2 {e2:.2e}, rel max {em:.2e}")
+    assert e2 < 1e-5 and em < 1e-5
+    # forces of the increment (central differences of d_phi, as the gather forms them)
+    assert rel_l2(orc.fd_gradient(p, got), orc.fd_gradient(p, ref)) < 1e-5
+    assert len(info["residuals"]) == K - 1
+    for k in range(K - 1):
+        assert abs(info["residuals"][k] - res[k]) <= 1e-3 * res[k] + 1e-9
+    ctx.close()
+
+
+def test_fp32_increment_returns_dF(M, case):
+    w, p, rho, drho, b = case
+    K = 3
+    _, _, inc = lin.incremental_solve(p, b, drho, K, keep_fields=True)
+    ctx = _ctx(M, w, K)
+    N = ctx.N
+    dF = torch.zeros(3 * N ** 3, dtype=torch.float32, device="cuda")
+    _gpu_increment(M, ctx, drho, b, M.PM_STORE_FP32, d_F=dF)
+    assert rel_l2(host(dF).reshape(3, N, N, N), inc["dF"]) < 1e-5
+    # without the residual the last dF is written straight from the x pass
+    ctx2 = _ctx(M, w, K, resid=False)
+    dF2 = torch.zeros_like(dF)
+    _gpu_increment(M, ctx2, drho, b, M.PM_STORE_FP32, d_F=dF2)
+    assert rel_l2(host(dF2).reshape(3, N, N, N), inc["dF"]) < 1e-5
+    ctx.close()
+    ctx2.close()
+
+
+@pytest.mark.parametrize("K", [2, 4])
+def test_fp16_increment_within_the_fp16_bound(M, case, K):
+    w, p, rho, drho, b = case
+    ref, res = lin.incremental_solve(p, b, drho, K)
+    half, _ = lin.incremental_solve(p, b, drho, K, store=lin.to_half)
+    e_oracle = rel_l2(half, ref)
+    ctx = _ctx(M, w, K)
+    got, info = _gpu_increment(M, ctx, drho, b, M.PM_STORE_FP16)
+    e_gpu = rel_l2(got, ref)
+    f_gpu = rel_l2(orc.fd_gradient(p, got), orc.fd_gradient(p, ref))
+    f_oracle = rel_l2(orc.fd_gradient(p, half), orc.fd_gradient(p, ref))
+    g_total = orc.fd_gradient(p, b["phi"] + ref)
+    f_step = np.linalg.norm(orc.fd_gradient(p, got - ref)) / np.linalg.norm(g_total)
+    _log(f"increment fp16 mu={p.mu} K={K}: d_phi {e_gpu:.2e} (oracle's FP16 model {e_oracle:.2e}), "
+         f"increment force {f_gpu:.2e} (oracle {f_oracle:.2e}), against the step's force {f_step:.2e}")
+    assert e_gpu <= 2.0 ** -11 and f_gpu <= 2.0 ** -10
+    assert f_step < 1e-5
+    assert len(info["residuals"]) == K - 1
+    for k in range(K - 1):
+        assert abs(info["residuals"][k] - res[k]) <= 2e-2 * res[k] + 1e-6
+    ctx.close()
+
+
+@pytest.mark.parametrize("storage", [0, 1], ids=["fp32", "fp16"])
+def test_increment_is_linear_bit_for_bit(M, case, storage):
+    w, p, rho, drho, b = case
+    ctx = _ctx(M, w, 3)
+    a, _ = _gpu_increment(M, ctx, drho, b, storage)
+    a2, _ = _gpu_increment(M, ctx, 2.0 * drho, b, storage)
+    assert np.array_equal(a2, 2.0 * a)
+    z, info = _gpu_increment(M, ctx, 0.0 * drho, b, storage)
+    assert not z.any() and np.isfinite(info["residuals"]).all()
+    ctx.close()
+
+
+def test_newton_increment_is_the_solve_of_the_density_change(M):
+    # with mu = 1 the solve is linear in rho, so the increment is the solve
+    # of d_rho itself (one nu evaluation: the curl-free part of g_N)
+    w, p, rho, drho, b = _case(orc.MU_NEWTON, seed=4, base_iters=2)
+    ctx = _ctx(M, w, 2)
+    ref, _ = orc.aqual_solve(orc.Params(**{**p.__dict__, "iters": 1}), drho)
+    for storage, bar in ((M.PM_STORE_FP32, 1e-5), (M.PM_STORE_FP16, 2.0 ** -11)):
+        got, _ = _gpu_increment(M, ctx, drho, b, storage)
+        e = rel_l2(got, ref)
+        _log(f"newton increment storage={storage}: {e:.2e}")
+        assert e < bar
+    ctx.close()
+
+
+def test_potential_field_is_the_base_gM(M, case):
+    w, p, rho, drho, b = case
+    N = p.n_pad
+    phi = _f32(b["phi"])
+    ctx = _ctx(M, w, 1)
+    g = torch.zeros(3 * N ** 3, dtype=torch.float32, device="cuda")
+    M.pm_potential_field(ctx, dev(phi), g)
+    got = host(g).reshape(3, N, N, N)
+    _, kt = orc.wavevectors(p)
+    ph = orc.fft3(phi)
+    ref = np.stack([orc.ifft3_real(-1j * k * ph) for k in (kt[None, None, :], kt[None, :, None], kt[:, None, None])])
+    assert rel_l2(got, ref) < 1e-5
+    # and that is the base state's g_M, the field of the same phi
+    assert rel_l2(got, b["gM"]) < 1e-5
+    ctx.close()
+
+
+def test_increment_full_size_properties(M):
+    """256^3 region in the 512^3 box (the benchmark's grid): FP16 against FP32
+    spectra and bit-exact linearity, about the GPU's own base fields."""
+    w = W.isothermal_sphere(seed=0, N=1 << 18)
+    K = 2
+    prm = dict(w["params"], iters=6, flags=M.PM_F_RESIDUAL)
+    ctx = M.pm_create(prm, len(w["mass"]))
+    N = ctx.N
+    R = N ** 3
+    pos = torch.from_numpy(w["pos"]).cuda()
+    mass = torch.from_numpy(w["mass"]).cuda()
+    vel = torch.from_numpy(w["vel"]).cuda()
+    rho = grid(N)
+    M.pm_deposit(ctx, pos, mass, rho)
+    phi = grid(N)
+    F = torch.zeros(3 * R, dtype=torch.float32, device="cuda")
+    M.aqual_solve_field(ctx, rho, phi, F)
+    gM = torch.zeros_like(F)
+    M.pm_potential_field(ctx, phi, gM)
+    rho1 = grid(N)
+    M.pm_deposit(ctx, pos + float(w["dt"]) * vel, mass, rho1)
+    drho = rho1 - rho
+    ctx.close()
+    ctx = M.pm_create(dict(w["params"], iters=K, flags=M.PM_F_RESIDUAL), 0)
+    out32, out16, out16b = grid(N), grid(N), grid(N)
+    M.aqual_solve_increment(ctx, drho, F, gM, out32, storage=M.PM_STORE_FP32)
+    M.aqual_solve_increment(ctx, drho, F, gM, out16, storage=M.PM_STORE_FP16)
+    M.aqual_solve_increment(ctx, 2.0 * drho, F, gM, out16b, storage=M.PM_STORE_FP16)
+    a32, a16, a16b = host(out32), host(out16), host(out16b)
+    assert np.isfinite(a16).all()
+    e = rel_l2(a16, a32)
+    _log(f"full size: FP16 against FP32 spectra, d_phi rel L2 {e:.2e}")
+    assert e < 1e-3
+    assert np.array_equal(a16b, 2.0 * a16)
+    ctx.close()

@@ -229,3 +229,16 @@ def test_accumulated_half_increments_drift_slowly():
     g64 = pm.smooth_accel(p, b64["phi"], pos)
     g16 = pm.smooth_accel(p, b16["phi"], pos)
     assert 0.0 < np.linalg.norm(g16 - g64) < 1e-6 * np.linalg.norm(g64)
+
+
+def test_base_gM_is_the_field_of_the_potential(cloud):
+    # the last projection gives phi_hat = i At kt . g and g_M = -i kt phi_hat,
+    # so the base g_M is the spectral field of the base potential: the GPU
+    # forms the base of the second linearisation that way from phi
+    p, rho, _, b = cloud
+    _, kt = pm.wavevectors(p)
+    ph = pm.fft3(b["phi"])
+    g = np.stack([pm.ifft3_real(-1j * k * ph) for k in (kt[None, None, :], kt[None, :, None], kt[:, None, None])])
+    assert np.linalg.norm(g - b["gM"]) <= 1e-12 * np.linalg.norm(b["gM"])
+    # it is not the central-difference field (the projections use the true k)
+    assert np.linalg.norm(-pm.fd_gradient(p, b["phi"]) - b["gM"]) > 1e-3 * np.linalg.norm(b["gM"])
