@@ -478,7 +478,7 @@ static pm_status run_solve(pm_ctx* c, const float* rho, const float* H0, float* 
     d.z.with_h0 = warm ? 2 : (start ? 1 : 0);
     d.io = io ? 2 : 0;
     HIPCHK(pass(c, d));
-    HIPCHK(reduce_partials(c->partials, z_blocks(N), c->dacc, c->st));
+    HIPCHK(reduce_partials(c->partials, z_blocks_io(N, d.io), c->dacc, c->st));
     HIPCHK(pass(c, spec3(PASS_Y_INV)));
   }
   int k_done = 0;

@@ -43,6 +43,7 @@
 namespace pm {
 
 int z_blocks(int N);
+int z_blocks_io(int N, int io);
 
 // Offset of element k of spectrum row `row` (row = kz * N + ky) in the
 // grouped layout; NN = N * N.
@@ -702,7 +703,7 @@ __device__ __forceinline__ void load_twiddles(float2* tw_s, const float2* __rest
 
 // Loads the first-stage inputs (radix R) of column q = b mod T of each
 // component c from src[c] + i * row_stride + q; zero for q >= nv[c].
-template <int L, int T, int NT, int R, int NC>
+template <int L, int T, int NT, int R, int NC, int CS = 1>
 __device__ __forceinline__ void load_cols(float2* v, int E, const float2* const* src, const int* nv,
                                           long long row_stride) {
   using B = Bfly<L, T, NT, R>;
@@ -713,7 +714,7 @@ __device__ __forceinline__ void load_cols(float2* v, int E, const float2* const*
     const int q = b % T, j = b / T;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const long long off = (long long)(j + r * (L / R)) * row_stride + q;
+      const long long off = (long long)(j + r * (L / R)) * row_stride + q * CS;
 #pragma unroll
       for (int c = 0; c < NC; ++c)
         v[c * E + u * R + r] = (q < nv[c]) ? src[c][off] : make_float2(0.0f, 0.0f);
@@ -721,7 +722,7 @@ __device__ __forceinline__ void load_cols(float2* v, int E, const float2* const*
   }
 }
 
-template <int L, int T, int NT, int R, int NC>
+template <int L, int T, int NT, int R, int NC, int CS = 1>
 __device__ __forceinline__ void store_cols(const float2* v, int E, float2* const* dst, const int* nv,
                                            long long row_stride) {
   using B = Bfly<L, T, NT, R>;
@@ -732,7 +733,7 @@ __device__ __forceinline__ void store_cols(const float2* v, int E, float2* const
     const int q = b % T, j = b / T;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const long long off = (long long)(j + r * (L / R)) * row_stride + q;
+      const long long off = (long long)(j + r * (L / R)) * row_stride + q * CS;
 #pragma unroll
       for (int c = 0; c < NC; ++c)
         if (q < nv[c]) dst[c][off] = v[c * E + u * R + r];
@@ -740,13 +741,19 @@ __device__ __forceinline__ void store_cols(const float2* v, int E, float2* const
   }
 }
 
-// Half-precision forms of load_cols / store_cols.  Element (row i, column q)
-// of set c is src[c][i * row_stride + q] times the scale
-// scl[c][i * srs + ((q + qoff[c]) >> 3) * sq].
-template <int L, int T, int NT, int R, int NC>
-__device__ __forceinline__ void load_cols_h(float2* v, int E, const __half2* const* src, const int* nv,
-                                            long long row_stride, const float* const* scl, int srs, int sq,
-                                            const int* qoff) {
+// Half-precision column pairs.  A block's 16 kx columns are two sets, the
+// even and the odd columns (column 2 q + h of the group is element q of set
+// h), so that one 8-byte access carries the pair q of both sets: the 64-byte
+// FP16 row of a group is read with the same 8 bytes per lane as an FP32 tile
+// of 8 columns.  Pair p covers sets 2 p and 2 p + 1; element (row i, pair q)
+// is at src[p][i * row_stride + 2 q] and is scaled by scl[p][i].
+struct alignas(8) HalfPair {
+  __half2 a, b;
+};
+
+template <int L, int T, int NT, int R, int NP>
+__device__ __forceinline__ void load_pairs_h(float2* v, int E, const __half2* const* src, const int* nvalid,
+                                             long long row_stride, const float* const* scl) {
   using B = Bfly<L, T, NT, R>;
 #pragma unroll
   for (int u = 0; u < B::BPT; ++u) {
@@ -756,11 +763,49 @@ __device__ __forceinline__ void load_cols_h(float2* v, int E, const __half2* con
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int i = j + r * (L / R);
-      const long long off = (long long)i * row_stride + q;
+      const long long off = (long long)i * row_stride + 2 * q;
 #pragma unroll
-      for (int c = 0; c < NC; ++c)
-        v[c * E + u * R + r] = (q < nv[c]) ? from_half(src[c][off], scl[c][i * srs + ((q + qoff[c]) >> 3) * sq])
-                                           : make_float2(0.0f, 0.0f);
+      for (int p = 0; p < NP; ++p) {
+        const float sc = scl[p][i];
+        float2 e0 = make_float2(0.0f, 0.0f), e1 = e0;
+        if (2 * q + 1 < nvalid[p]) {
+          const HalfPair hp = *reinterpret_cast<const HalfPair*>(src[p] + off);
+          e0 = from_half(hp.a, sc);
+          e1 = from_half(hp.b, sc);
+        } else if (2 * q < nvalid[p]) {
+          e0 = from_half(src[p][off], sc);
+        }
+        v[(2 * p) * E + u * R + r] = e0;
+        v[(2 * p + 1) * E + u * R + r] = e1;
+      }
+    }
+  }
+}
+
+template <int L, int T, int NT, int R, int NP>
+__device__ __forceinline__ void store_pairs_h(const float2* v, int E, __half2* const* dst, const int* nvalid,
+                                              long long row_stride, const float* inv) {
+  using B = Bfly<L, T, NT, R>;
+#pragma unroll
+  for (int u = 0; u < B::BPT; ++u) {
+    const int b = threadIdx.x + u * NT;
+    if (!B::valid(b)) continue;
+    const int q = b % T, j = b / T;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const long long off = (long long)(j + r * (L / R)) * row_stride + 2 * q;
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        const float2 e0 = v[(2 * p) * E + u * R + r], e1 = v[(2 * p + 1) * E + u * R + r];
+        if (2 * q + 1 < nvalid[p]) {
+          HalfPair hp;
+          hp.a = to_half(e0, inv[p]);
+          hp.b = to_half(e1, inv[p]);
+          *reinterpret_cast<HalfPair*>(dst[p] + off) = hp;
+        } else if (2 * q < nvalid[p]) {
+          dst[p][off] = to_half(e0, inv[p]);
+        }
+      }
     }
   }
 }
@@ -781,25 +826,6 @@ __device__ __forceinline__ void cols_absmax(const float2* v, int E, const int* n
 #pragma unroll
       for (int c = 0; c < NC; ++c)
         if (q < nv[c]) m[c] = fmaxf(m[c], amax2(v[c * E + u * R + r]));
-  }
-}
-
-template <int L, int T, int NT, int R, int NC>
-__device__ __forceinline__ void store_cols_h(const float2* v, int E, __half2* const* dst, const int* nv,
-                                             long long row_stride, const float* inv) {
-  using B = Bfly<L, T, NT, R>;
-#pragma unroll
-  for (int u = 0; u < B::BPT; ++u) {
-    const int b = threadIdx.x + u * NT;
-    if (!B::valid(b)) continue;
-    const int q = b % T, j = b / T;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const long long off = (long long)(j + r * (L / R)) * row_stride + q;
-#pragma unroll
-      for (int c = 0; c < NC; ++c)
-        if (q < nv[c]) dst[c][off] = to_half(v[c * E + u * R + r], inv[c]);
-    }
   }
 }
 
@@ -849,41 +875,36 @@ __global__ __launch_bounds__(NT) void k_ypass(float2* spec, long long comp_strid
     ptr[h] = base + h * T;
   }
   if constexpr (IO == 1) {
-    // the forward pass reads what an x pass wrote (a scale per row ky of this
-    // plane), the inverse pass what a z pass wrote (a scale per ky and 8 kx)
+    // FP16: the group's even and odd columns as the two sets (T = 8), one
+    // scale per row read from the writer's table (the forward pass reads what
+    // an x pass wrote, a scale per row ky of this plane; the inverse pass
+    // what a z pass wrote, a scale per (group, ky)), staged in LDS
+    static_assert(T == 8 && NH == 2, "half-precision y tiles are two interleaved sets of 8 columns");
+    __shared__ float s_in[L];
+    const float* scl_g = INV ? sc.zs + comp * sc.zcs + (long long)t * L : sc.xs + comp * sc.xcs + (long long)kz * L;
+    for (int i = threadIdx.x; i < L; i += NT) s_in[i] = scl_g[i];
+    __syncthreads();
     __half2* hb = reinterpret_cast<__half2*>(spec) + boff;
-    const __half2* hp[NH];
-    const float* scl[NH];
-    int qoff[NH];
-#pragma unroll
-    for (int h = 0; h < NH; ++h) {
-      hp[h] = hb + h * T;
-      qoff[h] = h * T;
-      scl[h] = INV ? sc.zs + comp * sc.zcs + (long long)t * L * 2 : sc.xs + comp * sc.xcs + (long long)kz * L;
-    }
-    load_cols_h<L, T, NT, First::R, NH>(v, E, hp, nv, 16, scl, INV ? 2 : 1, INV ? 1 : 0, qoff);
-  } else {
-    load_cols<L, T, NT, First::R, NH>(v, E, ptr, nv, 16);
-  }
-  __syncthreads();
-  col_fft<L, T, NT, NH, INV, false>(v, lds, tw_s, 1);
-  if constexpr (IO == 1) {
-    float m[NH];
-    cols_absmax<L, T, NT, Last::R, NH>(v, E, nv, m);
-#pragma unroll
-    for (int h = 1; h < NH; ++h) m[0] = fmaxf(m[0], m[h]);
+    const __half2* hsrc[1] = {hb};
+    const float* scl[1] = {s_in};
+    const int nvalid[1] = {min(16, ncols - x0)};
+    int nvs[2] = {(nvalid[0] + 1) / 2, nvalid[0] / 2};
+    load_pairs_h<L, T, NT, First::R, 1>(v, E, hsrc, nvalid, 16, scl);
+    __syncthreads();
+    col_fft<L, T, NT, NH, INV, false>(v, lds, tw_s, 1);
+    float m[2];
+    cols_absmax<L, T, NT, Last::R, 2>(v, E, nvs, m);
+    m[0] = fmaxf(m[0], m[1]);
     block_max<NT, 1>(m);
     const float scv = tile_scale(m[0]);
-    float inv[NH];
-    __half2* hp[NH];
-#pragma unroll
-    for (int h = 0; h < NH; ++h) {
-      inv[h] = 1.0f / scv;
-      hp[h] = reinterpret_cast<__half2*>(spec) + boff + h * T;
-    }
-    store_cols_h<L, T, NT, Last::R, NH>(v, E, hp, nv, 16, inv);
+    const float inv[1] = {1.0f / scv};
+    __half2* hdst[1] = {hb};
+    store_pairs_h<L, T, NT, Last::R, 1>(v, E, hdst, nvalid, 16, inv);
     if (threadIdx.x == 0) sc.ys[comp * sc.ycs + (long long)t * L + kz] = scv;
   } else {
+    load_cols<L, T, NT, First::R, NH>(v, E, ptr, nv, 16);
+    __syncthreads();
+    col_fft<L, T, NT, NH, INV, false>(v, lds, tw_s, 1);
     store_cols<L, T, NT, Last::R, NH>(v, E, ptr, nv, 16);
   }
 }
@@ -1049,7 +1070,14 @@ template <> struct ZComp<Z_GRAD>       { static constexpr int IN = 1, OUT = 3; }
 template <int L, int T, int NT, int HZ, int ZOP, int IO = 0>
 __global__ __launch_bounds__(NT) void k_zpass(ZArgs a, const float2* __restrict__ tw, Scales sc) {
   constexpr bool IN_H = IO == 1 || IO == 3, OUT_H = IO == 1 || IO == 2;
-  static_assert(!(IN_H || OUT_H) || (HZ == 1 && T == 8), "half-precision z tiles are 8 kx columns");
+  // With half-precision spectra the block owns a whole group of 16 kx as its
+  // even and odd columns (two interleaved sets of 8; column 2 q + h is
+  // element q of set h): CS is the column stride of a set, hoff(h) its first
+  // column.
+  constexpr bool IL = IO != 0;
+  static_assert(!IL || (HZ == 2 && T == 8), "half-precision z tiles are two interleaved sets of 8 columns");
+  constexpr int CS = IL ? 2 : 1;
+  auto hoff = [](int h) { return IL ? h : h * T; };
   constexpr int E = ColCfg<L, T, NT>::E;
   constexpr int NIN = ZComp<ZOP>::IN, NOUT = ZComp<ZOP>::OUT;
   constexpr int NV = NIN > NOUT ? NIN : NOUT;
@@ -1075,8 +1103,9 @@ __global__ __launch_bounds__(NT) void k_zpass(ZArgs a, const float2* __restrict_
   const long long off = ((long long)(x0 >> 4) * L * L + y) * 16 + (x0 & 15);
   load_twiddles<L>(tw_s, tw, NT);
   int nvh[HZ];
+  const int nvalid = min(16, a.ncols - x0);           // valid columns of an interleaved group
 #pragma unroll
-  for (int h = 0; h < HZ; ++h) nvh[h] = min(T, a.ncols - x0 - h * T);
+  for (int h = 0; h < HZ; ++h) nvh[h] = IL ? (nvalid + 1 - h) / 2 : min(T, a.ncols - x0 - h * T);
 
   float2 v[HZ * NV * E];
   using First = PlanAt<L, false, 0>;
@@ -1093,11 +1122,11 @@ __global__ __launch_bounds__(NT) void k_zpass(ZArgs a, const float2* __restrict_
                           ? (c == 0 ? a.phiN + off : a.spec + (c - 1) * a.comp_stride + off)
                           : a.spec + c * a.comp_stride + off;
 #pragma unroll
-    for (int h = 0; h < HZ; ++h) src[HZ * c + h] = p + h * T;
+    for (int h = 0; h < HZ; ++h) src[HZ * c + h] = p + hoff(h);
   }
   float2* dst1[HZ];
 #pragma unroll
-  for (int h = 0; h < HZ; ++h) dst1[h] = a.spec + off + h * T;
+  for (int h = 0; h < HZ; ++h) dst1[h] = a.spec + off + hoff(h);
   if (ZOP == Z_INV) {
     load_cols<L, T, NT, First::R, HZ>(v, E, src, nvs, row);
     __syncthreads();
@@ -1123,27 +1152,30 @@ __global__ __launch_bounds__(NT) void k_zpass(ZArgs a, const float2* __restrict_
           const int kz = j + r * (L / RLP);
           const bool ok = BLP::valid(b) && q < nvh[h];
           php[(h * BLP::BPT + u) * RLP + r] =
-              ok ? a.phiN[(long long)kz * row + off + h * T + q] : make_float2(0.0f, 0.0f);
+              ok ? a.phiN[(long long)kz * row + off + hoff(h) + q * CS] : make_float2(0.0f, 0.0f);
         }
     }
   }
   if constexpr (IN_H) {
-    // half-precision inputs (never phi_N, which stays FP32): scale per kz of
-    // the forward y pass's tile (group, plane kz)
-    const __half2* hs[HZ * NIN];
-    const float* scl[HZ * NIN];
-    int qoff[HZ * NIN];
+    // half-precision inputs (never phi_N, which stays FP32), one scale per kz
+    // from the forward y pass's tiles (group, plane kz), staged in LDS
+    __shared__ float s_in[NIN * L];
 #pragma unroll
     for (int c = 0; c < NIN; ++c)
+      for (int i = threadIdx.x; i < L; i += NT) s_in[c * L + i] = sc.ys[c * sc.ycs + (long long)grp * L + i];
+    __syncthreads();
+    const __half2* hs[NIN];
+    const float* scl[NIN];
+    int nval[NIN];
 #pragma unroll
-      for (int h = 0; h < HZ; ++h) {
-        hs[HZ * c + h] = reinterpret_cast<const __half2*>(a.spec) + c * a.comp_stride + off + h * T;
-        scl[HZ * c + h] = sc.ys + c * sc.ycs + (long long)grp * L;
-        qoff[HZ * c + h] = 0;
-      }
-    load_cols_h<L, T, NT, First::R, HZ * NIN>(v, E, hs, nvs, row, scl, 1, 0, qoff);
+    for (int c = 0; c < NIN; ++c) {
+      hs[c] = reinterpret_cast<const __half2*>(a.spec) + c * a.comp_stride + off;
+      scl[c] = s_in + c * L;
+      nval[c] = nvalid;
+    }
+    load_pairs_h<L, T, NT, First::R, NIN>(v, E, hs, nval, row, scl);
   } else {
-    load_cols<L, T, NT, First::R, HZ * NIN>(v, E, src, nvs, row);
+    load_cols<L, T, NT, First::R, HZ * NIN, CS>(v, E, src, nvs, row);
   }
   __syncthreads();
   col_fft<L, T, NT, HZ * NIN, false, false>(v, lds, tw_s, 1);
@@ -1164,7 +1196,7 @@ __global__ __launch_bounds__(NT) void k_zpass(ZArgs a, const float2* __restrict_
     const int q = b % T, j = b / T;
 #pragma unroll
     for (int h = 0; h < HZ; ++h) {
-      const int kxi = x0 + h * T + q;
+      const int kxi = x0 + hoff(h) + q * CS;
       const bool inb = q < nvh[h];
       const float kx = a.kv[kxi < L ? kxi : 0];
       const float tx = (kxi < L / 2) ? a.kt[kxi] : 0.0f;
@@ -1201,7 +1233,7 @@ __global__ __launch_bounds__(NT) void k_zpass(ZArgs a, const float2* __restrict_
           const float k2 = kx * kx + ky * ky + kzz * kzz;
           const float A = (k2 > 0.0f) ? 1.0f / k2 : 0.0f;
           const float2 ph = cscale(*v0, a.newton_coef * A);     // phi_N hat (raw DFT)
-          if (inb) a.phiN[(long long)kz * row + off + h * T + q] = ph;
+          if (inb) a.phiN[(long long)kz * row + off + hoff(h) + q * CS] = ph;
           const float kpz = a.kap[kz];
           const float2 g = cscale(mul_mi<false>(ph), a.scale);
           float2 o0 = cscale(g, kpx), o1 = cscale(g, kapy), o2 = cscale(g, kpz);
@@ -1279,18 +1311,22 @@ __global__ __launch_bounds__(NT) void k_zpass(ZArgs a, const float2* __restrict_
   // elements the forward last stage produced, so no exchange is needed here.
   col_fft<L, T, NT, HZ * NOUT, true, true>(v, lds, tw_s, 1);
   if constexpr (OUT_H) {
-    float m[NOUT], inv[NOUT];
+    float m[HZ * NOUT], inv[NOUT];
     __half2* hd[NOUT];
-    cols_absmax<L, T, NT, First::R, NOUT>(v, E, nvs, m);
+    int nval[NOUT];
+    cols_absmax<L, T, NT, First::R, HZ * NOUT>(v, E, nvs, m);
+#pragma unroll
+    for (int c = 0; c < NOUT; ++c) m[c] = fmaxf(m[2 * c], m[2 * c + 1]);
     block_max<NT, NOUT>(m);
 #pragma unroll
     for (int c = 0; c < NOUT; ++c) {
       const float scv = tile_scale(m[c]);
       inv[c] = 1.0f / scv;
       hd[c] = reinterpret_cast<__half2*>(a.spec) + c * a.comp_stride + off;
-      if (threadIdx.x == 0) sc.zs[c * sc.zcs + ((long long)grp * L + y) * 2 + ((x0 & 15) >> 3)] = scv;
+      nval[c] = nvalid;
+      if (threadIdx.x == 0) sc.zs[c * sc.zcs + (long long)grp * L + y] = scv;
     }
-    store_cols_h<L, T, NT, First::R, NOUT>(v, E, hd, nvs, row, inv);
+    store_pairs_h<L, T, NT, First::R, NOUT>(v, E, hd, nval, row, inv);
     return;
   }
   // (an FP32 result of half-precision input goes to a.out: written in place
@@ -1300,8 +1336,8 @@ __global__ __launch_bounds__(NT) void k_zpass(ZArgs a, const float2* __restrict_
 #pragma unroll
   for (int c = 0; c < NOUT; ++c)
 #pragma unroll
-    for (int h = 0; h < HZ; ++h) dst[HZ * c + h] = obase + c * a.comp_stride + off + h * T;
-  store_cols<L, T, NT, First::R, HZ * NOUT>(v, E, dst, nvs, row);
+    for (int h = 0; h < HZ; ++h) dst[HZ * c + h] = obase + c * a.comp_stride + off + hoff(h);
+  store_cols<L, T, NT, First::R, HZ * NOUT, CS>(v, E, dst, nvs, row);
 }
 
 // Sum of partials[0..n) into out[0] (FP64), one block.
@@ -1358,9 +1394,10 @@ hipError_t launch_x(const FftGeom& g, float2* spec, float* real, long long real_
 template <int N, bool INV, int IO = 0>
 hipError_t launch_y(const FftGeom& g, float2* spec, int ncomp, hipStream_t st) {
   using C = Cfg<N>;
+  constexpr int TY = IO ? 8 : C::TY;                 // FP16: two interleaved sets of 8 columns
   const int tiles = (C::H + 1 + 15) / 16;
-  const size_t sh = sizeof(float2) * ((size_t)ColBuf<N, C::TY>::elems + N);
-  hipLaunchKernelGGL((k_ypass<N, C::TY, kNT, INV, IO>), dim3(tiles, N, ncomp), dim3(kNT), sh, st, spec,
+  const size_t sh = sizeof(float2) * ((size_t)ColBuf<N, TY>::elems + N);
+  hipLaunchKernelGGL((k_ypass<N, TY, kNT, INV, IO>), dim3(tiles, N, ncomp), dim3(kNT), sh, st, spec,
                      g.comp_stride, C::H + 1, g.tw, g.sc);
   return hipGetLastError();
 }
@@ -1382,11 +1419,18 @@ hipError_t launch_y_mfma(const FftGeom& g, float2* spec, int ncomp, hipStream_t 
 template <int N, int ZOP, int IO = 0>
 hipError_t launch_z(const FftGeom& g, ZArgs a, hipStream_t st) {
   using C = Cfg<N>;
-  const size_t sh = sizeof(float2) * ((size_t)ColBuf<N, C::TZ>::elems + N);
   a.comp_stride = g.comp_stride;
   a.ncols = C::H + 1;
-  hipLaunchKernelGGL((k_zpass<N, C::TZ, kNTZ, PM_HZ, ZOP, IO>), dim3(z_blocks(N)), dim3(kNTZ), sh, st, a, g.tw,
-                     g.sc);
+  if constexpr (IO != 0) {
+    // half-precision spectra: a block owns a whole group of 16 kx
+    const size_t sh = sizeof(float2) * ((size_t)ColBuf<N, 8>::elems + N);
+    hipLaunchKernelGGL((k_zpass<N, 8, kNTZ, 2, ZOP, IO>), dim3(z_blocks_io(N, IO)), dim3(kNTZ), sh, st, a, g.tw,
+                       g.sc);
+  } else {
+    const size_t sh = sizeof(float2) * ((size_t)ColBuf<N, C::TZ>::elems + N);
+    hipLaunchKernelGGL((k_zpass<N, C::TZ, kNTZ, PM_HZ, ZOP, IO>), dim3(z_blocks(N)), dim3(kNTZ), sh, st, a, g.tw,
+                       g.sc);
+  }
   return hipGetLastError();
 }
 
@@ -1458,6 +1502,10 @@ int x_blocks(int N) {
 int z_blocks(int N) {
   const int H = N / 2;
   return ((H + 1 + 15) / 16) * (16 / (PM_TZ * PM_HZ)) * N;
+}
+int z_blocks_io(int N, int io) {
+  const int H = N / 2;
+  return io ? ((H + 1 + 15) / 16) * N : z_blocks(N);
 }
 
 hipError_t fft_pass(const FftGeom& g, const PassDesc& d, hipStream_t st) {

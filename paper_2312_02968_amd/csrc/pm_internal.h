@@ -81,6 +81,7 @@ hipError_t fft_pass(const FftGeom& g, const PassDesc& d, hipStream_t st);
 hipError_t reduce_partials(const double* partials, int n, double* out, hipStream_t st);
 int x_blocks(int N);
 int z_blocks(int N);
+int z_blocks_io(int N, int io);   // z-pass blocks with half-precision spectra (io != 0)
 
 // ---------------------------------------------------------------------------
 // particles
