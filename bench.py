@@ -268,6 +268,36 @@ def solver_vs_poisson(w, reps=5):
             "paper": "15-42x a standard Poisson solver (Python with FFTW, Intel Core i7-9750H)"}
 
 
+def cpu_full_step(w):
+    """One complete FP64 oracle step of the workload (deposit, K-iteration
+    solve, kick and drift), each phase timed; with ORACLE_FFT_WORKERS set
+    before the oracle is imported, the number of FFT threads.  Checks the
+    extrapolation of cpu_baseline's bounded sample."""
+    import numpy as np
+    from oracle import pm as orc
+    p = orc.Params.from_dict(w["params"])
+    pos = w["pos"].astype(np.float64)
+    vel = w["vel"].astype(np.float64)
+    mass = w["mass"].astype(np.float64)
+    dt = float(w["dt"])
+    out = {"workload": w["workload"], "workers": orc.WORKERS, "cpu": host_cpu_model()}
+    t0 = time.perf_counter()
+    rho = orc.deposit(p, pos, mass)
+    out["deposit_s"] = round(time.perf_counter() - t0, 2)
+    print(f"cpu full step: deposit {out['deposit_s']} s", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    phi, _ = orc.aqual_solve(p, rho)
+    out["solve_s"] = round(time.perf_counter() - t0, 2)
+    del rho
+    print(f"cpu full step: solve ({p.iters} iterations) {out['solve_s']} s", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    orc.interp_push(p, phi, pos, vel, dt, dt)
+    out["gather_push_s"] = round(time.perf_counter() - t0, 2)
+    out["step_s"] = round(out["deposit_s"] + out["solve_s"] + out["gather_push_s"], 2)
+    out["steps_per_s"] = 1.0 / out["step_s"]
+    return out
+
+
 def increment_bytes(N, K, half):
     """Algorithmic HBM bytes of one increment solve (aqual_solve_increment,
     fixed K, no residual) by the same counting as pass_bytes: complex entries
@@ -474,13 +504,17 @@ def cpu_baseline(w, n_sample=4096):
     d1, _ = timed(lambda: orc.deposit(p, pos[idx[:n_sample]], mass[idx[:n_sample]]))
     d2, rho = timed(lambda: orc.deposit(p, pos[idx], mass[idx] * (N / (2 * n_sample))))
     t_dep = fit(d1, d2)
+    print(f"cpu baseline: deposit samples {d1:.1f} s, {d2:.1f} s", file=sys.stderr, flush=True)
     t_newton, (_, gN) = timed(lambda: orc.newton_potential(p, rho))
+    print(f"cpu baseline: Newton solve {t_newton:.1f} s", file=sys.stderr, flush=True)
     del rho
     t0 = time.perf_counter()
     gM = orc.apply_nu(p, gN)
     gh, phih = orc.project_curl_free(p, np.stack([orc.fft3(gM[c]) for c in range(3)]))
     t_last_a = time.perf_counter() - t0
     t_last_b, phi = timed(lambda: orc.ifft3_real(phih))
+    print(f"cpu baseline: nu, transforms and curl-free projection {t_last_a + t_last_b:.1f} s", file=sys.stderr,
+          flush=True)
     t0 = time.perf_counter()
     gM = np.stack([orc.ifft3_real(gh[c]) for c in range(3)])
     del gh
@@ -492,6 +526,7 @@ def cpu_baseline(w, n_sample=4096):
     del Hh
     F = gN + H
     t_rest = time.perf_counter() - t0
+    print(f"cpu baseline: rest of the iteration {t_rest:.1f} s", file=sys.stderr, flush=True)
     del H, F, gN
     g1, _ = timed(lambda: orc.interp_push(p, phi, pos[idx[:n_sample]], vel[idx[:n_sample]], 0.1, 0.1))
     g2, _ = timed(lambda: orc.interp_push(p, phi, pos[idx], vel[idx], 0.1, 0.1))
@@ -535,6 +570,9 @@ def main():
     ap.add_argument("--dft", choices=("fp32", "bf16x3"), default="fp32",
                     help="arithmetic of the y passes' radix-16 stage: FP32 butterflies (default) or "
                          "BF16x3 dense DFT-16 products on the matrix cores (PM_F_DFT_BF16X3)")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="only time one complete FP64 oracle step of the workload (no GPU; set "
+                         "ORACLE_FFT_WORKERS for the FFT threads) and the bounded-sample baseline")
     ap.add_argument("--launch", choices=("graph", "eager"), default="graph",
                     help="time replays of the step recorded as a HIP graph (default) or eager pm_step calls")
     a = ap.parse_args()
@@ -547,6 +585,13 @@ def main():
         return
     if a.fft_compare:
         fft_compare()
+        return
+    if a.cpu_full:
+        w = make_workload(a.workload)
+        rec = {"full_step": cpu_full_step(w)}
+        print("cpu baseline sample", file=sys.stderr, flush=True)
+        rec["sample_baseline"] = cpu_baseline(w)
+        print(json.dumps(rec), flush=True)
         return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the path has no multi-GPU "
