@@ -175,74 +175,83 @@ __device__ __forceinline__ void block_fft(float2* buf, int QS, int IS, const flo
 // mode: 0 standard mu(x) = x / sqrt(1 + x^2), 1 deep MOND mu(x) = x, 2 Newton.
 // ---------------------------------------------------------------------------
 
-// Ratio |g_M| / |F| = nu(y) with y = |F| / a0; zero vector -> 0 (caller
-// multiplies F by the ratio).  Standard: nu(y) = sqrt(1/2 + 1/2 sqrt(1 + 4/y^2))
-// for y >= 1 and the equal form sqrt((y + sqrt(y^2 + 4)) / (2 y)) below 1, so
-// that neither 4/y^2 nor y^2 overflows.
-__device__ __forceinline__ float nu_ratio(int mode, float Fm, float inv_a0) {
-  if (mode == 2) return 1.0f;
-  if (!(Fm > 0.0f)) return 0.0f;
-  const float y = Fm * inv_a0;
-  if (mode == 1) return rsqrtf(y);
-  if (y >= 1.0f) {
-    const float t = 1.0f / y;
-    return sqrtf(0.5f * (1.0f + sqrtf(fmaf(4.0f * t, t, 1.0f))));
+// The equations are evaluated with the hardware square root, reciprocal and
+// reciprocal square root (about one ulp each), a fraction of the
+// instructions of the correctly rounded library forms: the x passes that
+// apply them are bound by their vector instructions.  Every value stays
+// within a few ulp.  A squared magnitude below kTinySq (|F| below 1e-18 in
+// the field's units) counts as zero, where the library forms would meet
+// denormals; nu F there is below 1e-9 sqrt(a0).
+constexpr float kTinySq = 1e-36f;
+__device__ __forceinline__ float hw_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float hw_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float hw_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
+// nu(y), y = |F| / a0, and its logarithmic slope s = y nu'(y) / nu(y), from
+// m2 = |F|^2.  Standard: with z = 2 / y = 2 a0 / |F| and h = sqrt(1 + z^2),
+// nu^2 = 1/2 + sqrt(1/4 + 1/y^2) = (1 + h) / 2 and
+// s = -1 / (2 nu^2 y^2 sqrt(1/4 + 1/y^2)) = -z^2 / (2 h (1 + h)), evaluated
+// as -(z / h) (z / (2 (1 + h))); beyond z = 1e18, h = z to FP32 precision.
+// Deep MOND: nu = sqrt(a0 / |F|), s = -1/2.  Newton: nu = 1, s = 0.  Zero
+// vector: nu = 0 (the caller multiplies F by nu), s = 0.
+__device__ __forceinline__ float nu_of_sq(int mode, float m2, float a0, float* slope = nullptr) {
+  if (mode == 2) {
+    if (slope) *slope = 0.0f;
+    return 1.0f;
   }
-  return sqrtf((y + sqrtf(fmaf(y, y, 4.0f))) / (2.0f * y));
+  if (!(m2 > kTinySq)) {
+    if (slope) *slope = 0.0f;
+    return 0.0f;
+  }
+  const float r = hw_rsq(m2);                        // 1 / |F|
+  if (mode == 1) {
+    if (slope) *slope = -0.5f;
+    return hw_sqrt(a0 * r);
+  }
+  const float z = 2.0f * a0 * r;
+  const float h = (z < 1e18f) ? hw_sqrt(fmaf(z, z, 1.0f)) : z;
+  if (slope) *slope = -(z * hw_rcp(h)) * (z * hw_rcp(2.0f * (1.0f + h)));
+  return hw_sqrt(0.5f * (1.0f + h));
 }
 
-// Ratio |F| / |g_M| = mu(x) with x = |g_M| / a0.
-__device__ __forceinline__ float mu_ratio(int mode, float gm, float inv_a0) {
-  if (mode == 2) return 1.0f;
-  const float x = gm * inv_a0;
-  if (mode == 1) return x;
-  if (x >= 1.0f) {
-    const float t = 1.0f / x;
-    return rsqrtf(fmaf(t, t, 1.0f));
+// mu(x), x = |g_M| / a0, and its logarithmic slope x mu'(x) / mu(x), from
+// m2 = |g_M|^2.  Standard: with q = x^2, mu = x / sqrt(1 + x^2) =
+// sqrt(q / (1 + q)) and the slope 1 / (1 + q); beyond q = 1e30, mu = 1 and the
+// slope 0 to FP32 precision.  Deep MOND: mu = x, slope 1.  Newton: 1, 0.
+__device__ __forceinline__ float mu_of_sq(int mode, float m2, float inv_a0, float* slope = nullptr) {
+  if (mode == 2) {
+    if (slope) *slope = 0.0f;
+    return 1.0f;
   }
-  return x * rsqrtf(fmaf(x, x, 1.0f));
-}
-
-// Logarithmic slopes y nu'(y) / nu(y) and x mu'(x) / mu(x) of the same
-// functions, for the linearisations of Eqs. inverse and interpolation about
-// a field A (Sect. 5, item (v)):  f(|A|/a0) (dA + s (A . dA) / |A|^2 A).
-// Standard nu: s = -1 / (2 nu^2 y^2 sqrt(1/4 + 1/y^2)), written for y >= 1
-// as -t^2 / (nu^2 sqrt(1 + 4 t^2)), t = 1/y, with nu^2 = (1 + sqrt(1 + 4
-// t^2)) / 2, and for y < 1 as -1 / ((y + sqrt(y^2 + 4)) sqrt(1 + y^2/4));
-// deep MOND -1/2; Newton 0.  Standard mu: 1 / (1 + x^2); deep MOND 1;
-// Newton 0.
-__device__ __forceinline__ float nu_logslope(int mode, float y) {
-  if (mode == 2) return 0.0f;
-  if (mode == 1) return -0.5f;
-  if (y >= 1.0f) {
-    const float t = 1.0f / y;
-    const float q = sqrtf(fmaf(4.0f * t, t, 1.0f));
-    return -(t * t) / (0.5f * (1.0f + q) * q);
+  if (mode == 1) {
+    if (slope) *slope = 1.0f;
+    return hw_sqrt(m2) * inv_a0;
   }
-  return -1.0f / ((y + sqrtf(fmaf(y, y, 4.0f))) * sqrtf(fmaf(0.25f * y, y, 1.0f)));
-}
-
-__device__ __forceinline__ float mu_logslope(int mode, float x) {
-  if (mode == 2) return 0.0f;
-  if (mode == 1) return 1.0f;
-  return 1.0f / fmaf(x, x, 1.0f);
+  const float q = m2 * inv_a0 * inv_a0;
+  if (!(q < 1e30f)) {
+    if (slope) *slope = 0.0f;
+    return 1.0f;
+  }
+  const float w = hw_rcp(1.0f + q);
+  if (slope) *slope = w;
+  return hw_sqrt(q * w);
 }
 
 // d <- the linearised map of Eq. inverse (MU = false: nu about A = F) or of
-// Eq. interpolation (MU = true: mu about A = g_M) applied to d; zero where
-// A = 0, where the maps have no derivative.
+// Eq. interpolation (MU = true: mu about A = g_M) applied to d:
+// f(|A|/a0) (d + s (A . d) / |A|^2 A) with s the logarithmic slope; zero
+// where A = 0, where the maps have no derivative (Sect. 5, item (v)).
 template <bool MU>
-__device__ __forceinline__ void linearised(int mode, float inv_a0, float A0, float A1, float A2, float& d0,
-                                           float& d1, float& d2) {
+__device__ __forceinline__ void linearised(int mode, float a0, float inv_a0, float A0, float A1, float A2,
+                                           float& d0, float& d1, float& d2) {
   const float am2 = A0 * A0 + A1 * A1 + A2 * A2;
-  if (!(am2 > 0.0f)) {
+  if (!(am2 > kTinySq)) {
     d0 = d1 = d2 = 0.0f;
     return;
   }
-  const float am = sqrtf(am2);
-  const float f = MU ? mu_ratio(mode, am, inv_a0) : nu_ratio(mode, am, inv_a0);
-  const float sl = MU ? mu_logslope(mode, am * inv_a0) : nu_logslope(mode, am * inv_a0);
-  const float c = sl * (A0 * d0 + A1 * d1 + A2 * d2) / am2;
+  float sl;
+  const float f = MU ? mu_of_sq(mode, am2, inv_a0, &sl) : nu_of_sq(mode, am2, a0, &sl);
+  const float c = sl * (A0 * d0 + A1 * d1 + A2 * d2) * hw_rcp(am2);
   d0 = f * fmaf(c, A0, d0);
   d1 = f * fmaf(c, A1, d1);
   d2 = f * fmaf(c, A2, d2);

@@ -242,6 +242,7 @@ __global__ __launch_bounds__(NT) void k_xpass(float2* spec, long long comp_strid
 
   if constexpr (XK::fused || XK::lin) {
     double acc = 0.0;
+    const float a0 = inv_a0 > 0.0f ? 1.0f / inv_a0 : 0.0f;
     for (int b = threadIdx.x; b < ROWS * H; b += NT) {
       const int r = b % ROWS, m = b / ROWS;
       float2 v0 = lds[m * IS + r], v1 = lds[m * IS + ROWS + r], v2 = lds[m * IS + 2 * ROWS + r];
@@ -262,17 +263,17 @@ __global__ __launch_bounds__(NT) void k_xpass(float2* spec, long long comp_strid
         const float2 b0 = *reinterpret_cast<const float2*>(base + e);
         const float2 b1 = *reinterpret_cast<const float2*>(base + cs + e);
         const float2 b2 = *reinterpret_cast<const float2*>(base + 2 * cs + e);
-        linearised<XK::mu>(mu_mode, inv_a0, b0.x, b1.x, b2.x, v0.x, v1.x, v2.x);
-        linearised<XK::mu>(mu_mode, inv_a0, b0.y, b1.y, b2.y, v0.y, v1.y, v2.y);
+        linearised<XK::mu>(mu_mode, a0, inv_a0, b0.x, b1.x, b2.x, v0.x, v1.x, v2.x);
+        linearised<XK::mu>(mu_mode, a0, inv_a0, b0.y, b1.y, b2.y, v0.y, v1.y, v2.y);
       } else {
         {
-          const float m0 = sqrtf(v0.x * v0.x + v1.x * v1.x + v2.x * v2.x);
-          const float f = !XK::mu ? nu_ratio(mu_mode, m0, inv_a0) : mu_ratio(mu_mode, m0, inv_a0);
+          const float m2 = v0.x * v0.x + v1.x * v1.x + v2.x * v2.x;
+          const float f = !XK::mu ? nu_of_sq(mu_mode, m2, a0) : mu_of_sq(mu_mode, m2, inv_a0);
           v0.x *= f; v1.x *= f; v2.x *= f;
         }
         {
-          const float m1 = sqrtf(v0.y * v0.y + v1.y * v1.y + v2.y * v2.y);
-          const float f = !XK::mu ? nu_ratio(mu_mode, m1, inv_a0) : mu_ratio(mu_mode, m1, inv_a0);
+          const float m2 = v0.y * v0.y + v1.y * v1.y + v2.y * v2.y;
+          const float f = !XK::mu ? nu_of_sq(mu_mode, m2, a0) : mu_of_sq(mu_mode, m2, inv_a0);
           v0.y *= f; v1.y *= f; v2.y *= f;
         }
       }
@@ -434,13 +435,16 @@ __device__ __forceinline__ void fft512_wave(float2* v, float2* xb, int j, const 
 // values j2; after the second, lane s + 8 m holds the 4 values j1 of q1 = m
 // and of q1 = m + 4, so the two radix-4 DFTs leave X[lane + 32 (h + 2 q2)]
 // in v[4 h + q2], which a register permutation puts back at r = h + 2 q2.
-// xb: the row's 272-entry LDS row; tw_s: the 512-entry table w_512^t.
+// xb: the row's 272-entry LDS row; twl: the block's twiddles of the two
+// stages in lane order, w_256^(j s) at twl[32 s + j] and w_32^(j1 q1) at
+// twl[256 + 4 q1 + j1] (consecutive lanes read consecutive entries, where
+// the strided w_512^t table costs bank conflicts).
 template <bool INV>
-__device__ __forceinline__ void fft256_lane32(float2* v, float2* xb, int j, const float2* tw_s) {
+__device__ __forceinline__ void fft256_lane32(float2* v, float2* xb, int j, const float2* twl) {
   Dft<8, INV>::run(v);
 #pragma unroll
   for (int s = 1; s < 8; ++s) {
-    float2 w = tw_s[2 * j * s];                          // w_256^(j s)
+    float2 w = twl[32 * s + j];                          // w_256^(j s)
     if (INV) w.y = -w.y;
     v[s] = cmul(v[s], w);
   }
@@ -454,7 +458,7 @@ __device__ __forceinline__ void fft256_lane32(float2* v, float2* xb, int j, cons
   Dft<8, INV>::run(v);
 #pragma unroll
   for (int q = 1; q < 8; ++q) {
-    float2 w = tw_s[16 * hi * q];                        // w_32^(j1 q1)
+    float2 w = twl[256 + 4 * q + hi];                    // w_32^(j1 q1)
     if (INV) w.y = -w.y;
     v[q] = cmul(v[q], w);
   }
@@ -489,11 +493,23 @@ struct XWave {
   static constexpr int G = 64 / LANES;              // rows per wave
   static constexpr int ROWS = 4 * G;                // rows per block (4 waves)
   static constexpr int XB = H + H / 16;             // padded LDS row (xpad)
+  static constexpr bool L32 = (H == 256 && LANES == 32);
+  static constexpr int TWL = L32 ? 256 + 32 : 0;    // lane-ordered twiddles of fft256_lane32
   template <bool INV>
-  __device__ __forceinline__ static void fft(float2* v, float2* xb, int j, const float2* tw_s) {
+  __device__ __forceinline__ static void fft(float2* v, float2* xb, int j, const float2* tw_s,
+                                             const float2* twl) {
     if constexpr (H == 256 && LANES == 16) fft256_group<INV>(v, xb, j, tw_s);
-    else if constexpr (H == 256) fft256_lane32<INV>(v, xb, j, tw_s);
+    else if constexpr (H == 256) fft256_lane32<INV>(v, xb, j, twl);
     else fft512_wave<INV>(v, xb, j, tw_s);
+  }
+  // fills the lane-ordered twiddles from the w_N^t table (block-wide)
+  __device__ __forceinline__ static void fill_twl(float2* twl, const float2* __restrict__ tw) {
+    if constexpr (L32) {
+      for (int t = threadIdx.x; t < TWL; t += 256) {
+        if (t < 256) twl[t] = tw[2 * (t & 31) * (t >> 5)];           // w_256^(j s), j = t % 32, s = t / 32
+        else twl[t] = tw[16 * ((t - 256) & 3) * ((t - 256) >> 2)];  // w_32^(j1 q1)
+      }
+    }
   }
 };
 
@@ -521,8 +537,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(XWaves<H, X
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = lane / LANES, j = lane % LANES;
   float2* xb = lds + N + (wave * X::G + g) * X::XB;
+  float2* twl = lds + N + X::ROWS * X::XB;
   const long long row = (long long)blockIdx.x * X::ROWS + wave * X::G + g;
   for (int t = threadIdx.x; t < N; t += 256) tw_s[t] = tw[t];
+  X::fill_twl(twl, tw);
   __syncthreads();
 
   float2 v[NC][RG];
@@ -573,14 +591,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(XWaves<H, X
       }
     }
 #pragma unroll
-    for (int c = 0; c < NC; ++c) X::template fft<true>(v[c], xb, j, tw_s);
+    for (int c = 0; c < NC; ++c) X::template fft<true>(v[c], xb, j, tw_s, twl);
   }
 
   if constexpr (XK::fused || XK::lin) {
     double acc = 0.0;
+    const float a0 = inv_a0 > 0.0f ? 1.0f / inv_a0 : 0.0f;
 #pragma unroll
     for (int r = 0; r < RG; ++r) {
-      float2 a0 = v[0][r], a1 = v[1][r], a2 = v[2][r];
+      float2 e0 = v[0][r], e1 = v[1][r], e2 = v[2][r];
       const long long e = row * N + 2 * (j + LANES * r);
       const long long cs = (long long)N * N * N;
       if (XK::keep) {
@@ -588,28 +607,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(XWaves<H, X
         float2* f1 = reinterpret_cast<float2*>(fprev + cs + e);
         float2* f2 = reinterpret_cast<float2*>(fprev + 2 * cs + e);
         const float2 p0 = *f0, p1 = *f1, p2 = *f2;
-        const double d0 = (double)a0.x - p0.x, d1 = (double)a1.x - p1.x, d2 = (double)a2.x - p2.x;
-        const double e0 = (double)a0.y - p0.y, e1 = (double)a1.y - p1.y, e2 = (double)a2.y - p2.y;
-        acc += d0 * d0 + d1 * d1 + d2 * d2 + e0 * e0 + e1 * e1 + e2 * e2;
-        *f0 = a0; *f1 = a1; *f2 = a2;
+        const double d0 = (double)e0.x - p0.x, d1 = (double)e1.x - p1.x, d2 = (double)e2.x - p2.x;
+        const double g0 = (double)e0.y - p0.y, g1 = (double)e1.y - p1.y, g2 = (double)e2.y - p2.y;
+        acc += d0 * d0 + d1 * d1 + d2 * d2 + g0 * g0 + g1 * g1 + g2 * g2;
+        *f0 = e0; *f1 = e1; *f2 = e2;
       }
       if constexpr (XK::lin) {
         const float2 b0 = *reinterpret_cast<const float2*>(base + e);
         const float2 b1 = *reinterpret_cast<const float2*>(base + cs + e);
         const float2 b2 = *reinterpret_cast<const float2*>(base + 2 * cs + e);
-        linearised<XK::mu>(mu_mode, inv_a0, b0.x, b1.x, b2.x, a0.x, a1.x, a2.x);
-        linearised<XK::mu>(mu_mode, inv_a0, b0.y, b1.y, b2.y, a0.y, a1.y, a2.y);
-        v[0][r] = a0;
-        v[1][r] = a1;
-        v[2][r] = a2;
+        linearised<XK::mu>(mu_mode, a0, inv_a0, b0.x, b1.x, b2.x, e0.x, e1.x, e2.x);
+        linearised<XK::mu>(mu_mode, a0, inv_a0, b0.y, b1.y, b2.y, e0.y, e1.y, e2.y);
+        v[0][r] = e0;
+        v[1][r] = e1;
+        v[2][r] = e2;
       } else {
-        const float m0 = sqrtf(a0.x * a0.x + a1.x * a1.x + a2.x * a2.x);
-        const float m1 = sqrtf(a0.y * a0.y + a1.y * a1.y + a2.y * a2.y);
-        const float f0 = !XK::mu ? nu_ratio(mu_mode, m0, inv_a0) : mu_ratio(mu_mode, m0, inv_a0);
-        const float f1 = !XK::mu ? nu_ratio(mu_mode, m1, inv_a0) : mu_ratio(mu_mode, m1, inv_a0);
-        v[0][r] = make_float2(a0.x * f0, a0.y * f1);
-        v[1][r] = make_float2(a1.x * f0, a1.y * f1);
-        v[2][r] = make_float2(a2.x * f0, a2.y * f1);
+        const float m0 = e0.x * e0.x + e1.x * e1.x + e2.x * e2.x;
+        const float m1 = e0.y * e0.y + e1.y * e1.y + e2.y * e2.y;
+        const float f0 = !XK::mu ? nu_of_sq(mu_mode, m0, a0) : mu_of_sq(mu_mode, m0, inv_a0);
+        const float f1 = !XK::mu ? nu_of_sq(mu_mode, m1, a0) : mu_of_sq(mu_mode, m1, inv_a0);
+        v[0][r] = make_float2(e0.x * f0, e0.y * f1);
+        v[1][r] = make_float2(e1.x * f0, e1.y * f1);
+        v[2][r] = make_float2(e2.x * f0, e2.y * f1);
       }
     }
     if (XK::keep) {
@@ -633,7 +652,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(XWaves<H, X
 
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
-    X::template fft<false>(v[c], xb, j, tw_s);
+    X::template fft<false>(v[c], xb, j, tw_s, twl);
     // split: X[k] = E + W^k O, E = (Zk + conj Zm)/2, O = -i (Zk - conj Zm)/2
     if constexpr (IO == 1) {
       float2 o[RG];
@@ -1208,7 +1227,7 @@ __global__ __launch_bounds__(NT) void k_zpass(ZArgs a, const float2* __restrict_
         if constexpr (ZOP == Z_POISSON) {
           const float kzz = a.kv[kz];
           const float k2 = kx * kx + ky * ky + kzz * kzz;
-          const float A = (k2 > 0.0f) ? 1.0f / k2 : 0.0f;
+          const float A = (k2 > 0.0f) ? hw_rcp(k2) : 0.0f;
           v[h * E + e] = cscale(v[h * E + e], a.newton_coef * A * a.scale);
           continue;
         }
@@ -1231,7 +1250,7 @@ __global__ __launch_bounds__(NT) void k_zpass(ZArgs a, const float2* __restrict_
         if (ZOP == Z_NEWTON || ZOP == Z_NEWTON_H0 || ZOP == Z_NEWTON_WARM) {
           const float kzz = a.kv[kz];
           const float k2 = kx * kx + ky * ky + kzz * kzz;
-          const float A = (k2 > 0.0f) ? 1.0f / k2 : 0.0f;
+          const float A = (k2 > 0.0f) ? hw_rcp(k2) : 0.0f;
           const float2 ph = cscale(*v0, a.newton_coef * A);     // phi_N hat (raw DFT)
           if (inb) a.phiN[(long long)kz * row + off + hoff(h) + q * CS] = ph;
           const float kpz = a.kap[kz];
@@ -1243,7 +1262,7 @@ __global__ __launch_bounds__(NT) void k_zpass(ZArgs a, const float2* __restrict_
             // of F_prev - g_N: h - kt At (kt . h)
             const float tz = a.kt[kz];
             const float t2 = tx * tx + ty * ty + tz * tz;
-            const float At = (t2 > 0.0f) ? 1.0f / t2 : 0.0f;
+            const float At = (t2 > 0.0f) ? hw_rcp(t2) : 0.0f;
             float2 h0 = v[(1 * HZ + h) * E + e], h1 = v[(2 * HZ + h) * E + e], h2 = v[(3 * HZ + h) * E + e];
             if (ZOP == Z_NEWTON_WARM) {
               // o_c = g_N hat (already divided by N^3); bring F_prev to the same units
@@ -1268,7 +1287,7 @@ __global__ __launch_bounds__(NT) void k_zpass(ZArgs a, const float2* __restrict_
         } else {
           const float tz = a.kt[kz];
           const float t2 = tx * tx + ty * ty + tz * tz;
-          const float At = (t2 > 0.0f) ? 1.0f / t2 : 0.0f;
+          const float At = (t2 > 0.0f) ? hw_rcp(t2) : 0.0f;
           const float2 g0 = *v0, g1 = *v1, g2 = *v2;
           if constexpr (ZOP == Z_DIV) {
             const float2 ph = php[(h * BLP::BPT + u) * RLP + r];
@@ -1378,7 +1397,7 @@ hipError_t launch_x(const FftGeom& g, float2* spec, float* real, long long real_
   using C = Cfg<N>;
   if constexpr (N == 512 || N == 1024) {
     using X = XWave<N / 2>;
-    const size_t sh = sizeof(float2) * (N + (size_t)X::ROWS * X::XB);
+    const size_t sh = sizeof(float2) * (N + (size_t)X::ROWS * X::XB + X::TWL);
     hipLaunchKernelGGL((k_xpass_wave<N / 2, XMODE, NC, IO>), dim3(N * N / X::ROWS), dim3(256), sh, st, spec,
                        g.comp_stride, real, real_cs, g.tw, mu_mode, inv_a0, fprev, partials, dip, base, g.sc);
     return hipGetLastError();
