@@ -94,7 +94,10 @@ typedef struct {
                         (paper: 4, giving 251 cells at sigma = 1)            */
   int32_t  iters;    /* K: evaluations of nu per solve (paper: 4), 1..64     */
   double   tol;      /* 0: exactly K iterations.  > 0: stop at iteration k
-                        once r_{k-1} <= tol (K is the maximum)               */
+                        once r_{k-1} <= tol (K is the maximum); decided on
+                        the device: all K iterations are enqueued and those
+                        after the stop return at once, so the host never
+                        waits and the solve can be captured in a graph   */
   uint32_t flags;    /* PM_F_*                                               */
 } pm_params;
 
@@ -148,8 +151,8 @@ pm_status pm_deposit(pm_ctx* ctx, const float* pos, const float* mass, int64_t N
  * g_M, H = divergence-free part of F' - g_N.  phi comes from the last
  * projection.  rho: device float [n_pad^3] (read); H0: device float
  * [3][n_pad^3] or NULL; phi: device float [n_pad^3] (written).  rho and phi
- * may be the same buffer.  info (host) may be NULL; when given, or when
- * tol > 0, the call synchronises and fills it.  With iters = 1, no H0 and no
+ * may be the same buffer.  info (host) may be NULL; when given, the call
+ * synchronises and fills it (iterations done, residuals, status).  With iters = 1, no H0 and no
  * warm start the result is quasi-linear MOND (the equivalent system for
  * QuMOND in Sect. 2): g_M = curl-free part of nu(|g_N|/a0) g_N. */
 pm_status aqual_solve(pm_ctx* ctx, const float* rho, const float* H0, float* phi,
@@ -182,7 +185,7 @@ pm_status interp_push(pm_ctx* ctx, const float* phi, float* pos, float* vel, int
 
 /* One PM step: deposit at r, solve, kick by dt, drift by dt (pos, vel in
  * place; the flow scheme's alternation with one fixed phase).  info may be
- * NULL (then nothing synchronises in fixed-K mode). */
+ * NULL (then nothing synchronises, in either mode). */
 pm_status pm_step(pm_ctx* ctx, float* pos, float* vel, const float* mass, int64_t N,
                   double dt, pm_solve_info* info);
 
@@ -193,8 +196,9 @@ pm_status pm_step(pm_ctx* ctx, float* pos, float* vel, const float* mass, int64_
  * and keeps the graph in the context (replacing an earlier one; pm_destroy
  * frees it).  pm_step_replay launches it count times on the stream; each
  * replay is one pm_step on the captured buffers, which the caller keeps alive
- * and in place.  PM_E_INVAL if the context was created on the null stream,
- * has tol > 0 (that mode synchronises), has event timing on, or has
+ * and in place; with tol > 0 each replay stops its solve where the residual
+ * test does, on the device.  PM_E_INVAL if the context was created on the
+ * null stream, has event timing on, or has
  * PM_F_WARM_START before its first solve (capture after one pm_step so the
  * recorded solve starts warm); on a capture error no graph is kept. */
 pm_status pm_step_capture(pm_ctx* ctx, float* pos, float* vel, const float* mass, int64_t N,

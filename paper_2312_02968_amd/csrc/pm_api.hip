@@ -43,6 +43,7 @@ struct pm_ctx {
   float* fprev = nullptr;     // previous F for the residual and the warm start (optional)
   bool have_F = false;        // fprev holds the last F of a solve
   float* scales = nullptr;    // scale tables of the increment solve's half-precision spectra
+  int* ctl = nullptr;         // tolerance-mode control words (see tol_check)
   double* partials = nullptr;
   double* dacc = nullptr;     // [0] |g_N|^2 sum, [1..64] residual sums, [80..89] diagnostics
   double hacc[128] = {};      // host copy of dacc
@@ -220,6 +221,7 @@ static size_t carve(pm_ctx* c, Carver& cv) {
   c->phi = cv.take<float>(R);
   c->fprev = (need_residual(c->p) || (c->p.flags & PM_F_WARM_START)) ? cv.take<float>(3 * R) : nullptr;
   c->scales = cv.take<float>(scale_floats((int)N, c->P));
+  c->ctl = cv.take<int>(16);
   c->partials = cv.take<double>((size_t)c->npartials);
   c->dacc = cv.take<double>(128);
   c->tw = cv.take<float2>(N);
@@ -467,9 +469,18 @@ static pm_status run_solve(pm_ctx* c, const float* rho, const float* H0, float* 
     HIPCHK(pass(c, d));
     HIPCHK(pass(c, pdesc(PASS_Y_FWD, c->spec, 3)));
   }
+  // Tolerance mode: every iteration up to K is enqueued and gated on the
+  // device (run0: while iterating, run1: the stopping iteration's final
+  // projection, run01: both), so the host never waits.
+  const bool dev_tol = p.tol > 0.0;
+  const Gate run0 = dev_tol ? Gate{c->ctl, 1} : Gate{};
+  const Gate run1 = dev_tol ? Gate{c->ctl, 2} : Gate{};
+  const Gate run01 = dev_tol ? Gate{c->ctl, 3} : Gate{};
+  if (dev_tol) HIPCHK(fill_zero(reinterpret_cast<float*>(c->ctl), 4, c->st));
   auto spec3 = [&](PassKind k) {
     PassDesc d = pdesc(k, c->spec, 3);
     d.io = io;
+    d.gate = run0;
     return d;
   };
   {
@@ -496,31 +507,26 @@ static pm_status run_solve(pm_ctx* c, const float* rho, const float* H0, float* 
       d.partials = c->partials;
       HIPCHK(pass(c, d));
     }
-    bool final_it = (k == K);
-    if (resid && k >= 2) {
-      HIPCHK(reduce_partials(c->partials, x_blocks(N), c->dacc + (k - 1), c->st));
-      if (p.tol > 0.0) {
-        HIPCHK(hipMemcpyAsync(c->hacc, c->dacc, 128 * sizeof(double), hipMemcpyDeviceToHost, c->st));
-        HIPCHK(hipStreamSynchronize(c->st));
-        const double gn = sqrt(c->hacc[0] / N3);
-        const double r = gn > 0.0 ? sqrt(c->hacc[k - 1]) / gn : 0.0;
-        if (!isfinite(r)) {
-          loc.status = PM_E_NONFINITE;
-          final_it = true;
-        } else if (r <= p.tol) {
-          final_it = true;
-        }
-      }
-    }
+    if (resid && k >= 2) HIPCHK(reduce_partials(c->partials, x_blocks(N), c->dacc + (k - 1), c->st, run0));
+    if (dev_tol) HIPCHK(tol_check(c->ctl, c->dacc, k, K, p.tol, N3, c->st));
     k_done = k;
-    HIPCHK(pass(c, spec3(PASS_Y_FWD)));
-    if (final_it) {
+    {
+      PassDesc d = spec3(PASS_Y_FWD);
+      d.gate = run01;
+      HIPCHK(pass(c, d));
+    }
+    if (dev_tol || k == K) {
+      // the last projection, to phi: in the tolerance mode enqueued every
+      // iteration and run by the one in which the iteration stops
       PassDesc d = pdesc(PASS_Z_CURL_FINAL, c->spec);
       d.z = zargs(c);
       d.io = io ? 3 : 0;
       d.z.out = fin;
+      d.gate = run1;
       HIPCHK(pass(c, d));
-      break;
+      if (!dev_tol) break;
+      HIPCHK(gate_advance(c->ctl, c->st));
+      if (k == K) break;
     }
     {
       PassDesc d = spec3(PASS_Z_CURL);
@@ -557,9 +563,15 @@ static pm_status run_solve(pm_ctx* c, const float* rho, const float* H0, float* 
     HIPCHK(pass(c, d));
   }
 
-  if (want_info || p.tol > 0.0) {
+  if (want_info) {
     HIPCHK(hipMemcpyAsync(c->hacc, c->dacc, 128 * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    int hctl[4] = {0, 0, 0, 0};
+    if (dev_tol) HIPCHK(hipMemcpyAsync(hctl, c->ctl, 4 * sizeof(int), hipMemcpyDeviceToHost, c->st));
     HIPCHK(hipStreamSynchronize(c->st));
+    if (dev_tol) {
+      k_done = hctl[1];
+      if (hctl[2]) loc.status = PM_E_NONFINITE;
+    }
     loc.iterations = k_done;
     loc.gN_norm = sqrt(c->hacc[0] / N3);
     if (resid) {
@@ -805,7 +817,6 @@ pm_status pm_step_capture(pm_ctx* c, float* pos, float* vel, const float* mass, 
   if (s != PM_OK) return s;
   if (n > 0 && (!pos || !vel || !mass)) return inval("NULL buffer");
   if (!c->st) return inval("capture needs the context to run on a created stream, not the null stream");
-  if (c->p.tol > 0.0) return inval("tolerance mode reads the residual on the host and cannot be captured");
   if (c->timing) return inval("switch event timing off before capturing");
   if ((c->p.flags & PM_F_WARM_START) && !c->have_F)
     return inval("warm start: run one pm_step before capturing, so the captured solve starts warm");

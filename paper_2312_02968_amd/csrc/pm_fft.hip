@@ -80,6 +80,8 @@ __device__ __forceinline__ float2 from_half(__half2 h, float scale) {
 __device__ __forceinline__ __half2 to_half(float2 v, float inv) { return __floats2half2_rn(v.x * inv, v.y * inv); }
 __device__ __forceinline__ float amax2(float2 v) { return fmaxf(fabsf(v.x), fabsf(v.y)); }
 
+__device__ __forceinline__ bool gated_off(const Gate& g) { return g.ctl && !((g.mask >> *g.ctl) & 1); }
+
 // Block-wide maximum of m[0..NC) (every thread gets the result).
 template <int NT, int NC>
 __device__ __forceinline__ void block_max(float* m) {
@@ -192,7 +194,8 @@ __global__ __launch_bounds__(NT) void k_xpass(float2* spec, long long comp_strid
                                               float* real, long long real_comp_stride,
                                               const float2* __restrict__ tw, int mu_mode, float inv_a0,
                                               float* fprev, double* partials, Dipole dip,
-                                              const float* __restrict__ base, Scales sc) {
+                                              const float* __restrict__ base, Scales sc, Gate gate) {
+  if (gated_off(gate)) return;
   using XK = XKind<XMODE>;
   constexpr int S = NC * ROWS;
   constexpr int IS = S + 1;
@@ -527,7 +530,9 @@ template <int H, int XMODE, int NC, int IO = 0>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(XWaves<H, XMODE>::value))) void k_xpass_wave(float2* spec, long long comp_stride, float* real,
                                                     long long real_comp_stride, const float2* __restrict__ tw,
                                                     int mu_mode, float inv_a0, float* fprev, double* partials,
-                                                    Dipole dip, const float* __restrict__ base, Scales sc) {
+                                                    Dipole dip, const float* __restrict__ base, Scales sc,
+                                                    Gate gate) {
+  if (gated_off(gate)) return;
   using X = XWave<H>;
   using XK = XKind<XMODE>;
   constexpr int N = X::N, LANES = X::LANES, RG = X::RG;
@@ -854,7 +859,8 @@ __device__ __forceinline__ void cols_absmax(const float2* v, int E, const int* n
 // load instruction covers whole 128-byte rows of consecutive ky.
 template <int L, int T, int NT, bool INV, int IO = 0>
 __global__ __launch_bounds__(NT) void k_ypass(float2* spec, long long comp_stride, int ncols,
-                                              const float2* __restrict__ tw, Scales sc) {
+                                              const float2* __restrict__ tw, Scales sc, Gate gate) {
+  if (gated_off(gate)) return;
   static_assert(16 % T == 0, "a y-pass block owns one group of 16 kx columns");
   constexpr int NH = 16 / T;
   constexpr int E = ColCfg<L, T, NT>::E;
@@ -956,7 +962,8 @@ __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
 
 template <int L, bool INV>
 __global__ __launch_bounds__(256) void k_ypass_mfma(float2* spec, long long comp_stride, int ncols,
-                                                    const float2* __restrict__ tw) {
+                                                    const float2* __restrict__ tw, Gate gate) {
+  if (gated_off(gate)) return;
   constexpr int M = L / 16;
   constexpr int TPW = M / 4;                       // n1 values per wave
   constexpr int RS = 17;                           // LDS row of the 16 columns, padded
@@ -1087,7 +1094,8 @@ template <> struct ZComp<Z_GRAD>       { static constexpr int IN = 1, OUT = 3; }
 // IO as PassDesc::io; the half-precision forms read the forward y pass's
 // scales and write one scale per component of the block's 8 kx columns.
 template <int L, int T, int NT, int HZ, int ZOP, int IO = 0>
-__global__ __launch_bounds__(NT) void k_zpass(ZArgs a, const float2* __restrict__ tw, Scales sc) {
+__global__ __launch_bounds__(NT) void k_zpass(ZArgs a, const float2* __restrict__ tw, Scales sc, Gate gate) {
+  if (gated_off(gate)) return;
   constexpr bool IN_H = IO == 1 || IO == 3, OUT_H = IO == 1 || IO == 2;
   // With half-precision spectra the block owns a whole group of 16 kx as its
   // even and odd columns (two interleaved sets of 8; column 2 q + h is
@@ -1361,7 +1369,8 @@ __global__ __launch_bounds__(NT) void k_zpass(ZArgs a, const float2* __restrict_
 
 // Sum of partials[0..n) into out[0] (FP64), one block.
 __global__ __launch_bounds__(1024) void k_reduce_partials(const double* __restrict__ partials, int n,
-                                                          double* out) {
+                                                          double* out, Gate gate) {
+  if (gated_off(gate)) return;
   __shared__ double red[16];
   double acc = 0.0;
   for (int i = threadIdx.x; i < n; i += 1024) acc += partials[i];
@@ -1399,13 +1408,15 @@ hipError_t launch_x(const FftGeom& g, float2* spec, float* real, long long real_
     using X = XWave<N / 2>;
     const size_t sh = sizeof(float2) * (N + (size_t)X::ROWS * X::XB + X::TWL);
     hipLaunchKernelGGL((k_xpass_wave<N / 2, XMODE, NC, IO>), dim3(N * N / X::ROWS), dim3(256), sh, st, spec,
-                       g.comp_stride, real, real_cs, g.tw, mu_mode, inv_a0, fprev, partials, dip, base, g.sc);
+                       g.comp_stride, real, real_cs, g.tw, mu_mode, inv_a0, fprev, partials, dip, base, g.sc,
+                       g.gate);
     return hipGetLastError();
   } else {
     const int blocks = N * N / C::ROWS;
     const size_t sh = sizeof(float2) * ((size_t)(C::H + 1) * (NC * C::ROWS + 1) + N);
     hipLaunchKernelGGL((k_xpass<C::H, C::ROWS, NC, kNT, XMODE, IO>), dim3(blocks), dim3(kNT), sh, st, spec,
-                       g.comp_stride, real, real_cs, g.tw, mu_mode, inv_a0, fprev, partials, dip, base, g.sc);
+                       g.comp_stride, real, real_cs, g.tw, mu_mode, inv_a0, fprev, partials, dip, base, g.sc,
+                       g.gate);
     return hipGetLastError();
   }
 }
@@ -1417,7 +1428,7 @@ hipError_t launch_y(const FftGeom& g, float2* spec, int ncomp, hipStream_t st) {
   const int tiles = (C::H + 1 + 15) / 16;
   const size_t sh = sizeof(float2) * ((size_t)ColBuf<N, TY>::elems + N);
   hipLaunchKernelGGL((k_ypass<N, TY, kNT, INV, IO>), dim3(tiles, N, ncomp), dim3(kNT), sh, st, spec,
-                     g.comp_stride, C::H + 1, g.tw, g.sc);
+                     g.comp_stride, C::H + 1, g.tw, g.sc, g.gate);
   return hipGetLastError();
 }
 
@@ -1428,7 +1439,7 @@ hipError_t launch_y_mfma(const FftGeom& g, float2* spec, int ncomp, hipStream_t 
     constexpr size_t xe = (size_t)N * 17 > (size_t)M * 260 ? (size_t)N * 17 : (size_t)M * 260;
     const int tiles = (N / 2 + 1 + 15) / 16;
     hipLaunchKernelGGL((k_ypass_mfma<N, INV>), dim3(tiles, N, ncomp), dim3(256), sizeof(float2) * (xe + N), st,
-                       spec, g.comp_stride, N / 2 + 1, g.tw);
+                       spec, g.comp_stride, N / 2 + 1, g.tw, g.gate);
     return hipGetLastError();
   } else {
     return hipErrorInvalidValue;
@@ -1444,11 +1455,11 @@ hipError_t launch_z(const FftGeom& g, ZArgs a, hipStream_t st) {
     // half-precision spectra: a block owns a whole group of 16 kx
     const size_t sh = sizeof(float2) * ((size_t)ColBuf<N, 8>::elems + N);
     hipLaunchKernelGGL((k_zpass<N, 8, kNTZ, 2, ZOP, IO>), dim3(z_blocks_io(N, IO)), dim3(kNTZ), sh, st, a, g.tw,
-                       g.sc);
+                       g.sc, g.gate);
   } else {
     const size_t sh = sizeof(float2) * ((size_t)ColBuf<N, C::TZ>::elems + N);
     hipLaunchKernelGGL((k_zpass<N, C::TZ, kNTZ, PM_HZ, ZOP, IO>), dim3(z_blocks(N)), dim3(kNTZ), sh, st, a, g.tw,
-                       g.sc);
+                       g.sc, g.gate);
   }
   return hipGetLastError();
 }
@@ -1527,7 +1538,9 @@ int z_blocks_io(int N, int io) {
   return io ? ((H + 1 + 15) / 16) * N : z_blocks(N);
 }
 
-hipError_t fft_pass(const FftGeom& g, const PassDesc& d, hipStream_t st) {
+hipError_t fft_pass(const FftGeom& g0, const PassDesc& d, hipStream_t st) {
+  FftGeom g = g0;
+  g.gate = d.gate;
   switch (g.N) {
     case 16: return run_pass<16>(g, d, st);
     case 32: return run_pass<32>(g, d, st);
@@ -1540,8 +1553,41 @@ hipError_t fft_pass(const FftGeom& g, const PassDesc& d, hipStream_t st) {
   return hipErrorInvalidValue;
 }
 
-hipError_t reduce_partials(const double* partials, int n, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(1024), 0, st, partials, n, out);
+hipError_t reduce_partials(const double* partials, int n, double* out, hipStream_t st, Gate gate) {
+  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(1024), 0, st, partials, n, out, gate);
+  return hipGetLastError();
+}
+
+__global__ void k_tol_check(int* ctl, const double* __restrict__ acc, int k, int kmax, double tol, double n3) {
+  if (threadIdx.x != 0 || ctl[0] != 0) return;
+  bool stop = (k >= kmax);
+  if (k >= 2) {
+    const double gn = sqrt(acc[0] / n3);
+    const double r = gn > 0.0 ? sqrt(acc[k - 1]) / gn : 0.0;
+    if (!isfinite(r)) {
+      ctl[2] = 1;
+      stop = true;
+    } else if (r <= tol) {
+      stop = true;
+    }
+  }
+  if (stop) {
+    ctl[1] = k;
+    ctl[0] = 1;
+  }
+}
+
+__global__ void k_gate_advance(int* ctl) {
+  if (threadIdx.x == 0 && ctl[0] == 1) ctl[0] = 2;
+}
+
+hipError_t tol_check(int* ctl, const double* acc, int k, int kmax, double tol, double n3, hipStream_t st) {
+  hipLaunchKernelGGL(k_tol_check, dim3(1), dim3(64), 0, st, ctl, acc, k, kmax, tol, n3);
+  return hipGetLastError();
+}
+
+hipError_t gate_advance(int* ctl, hipStream_t st) {
+  hipLaunchKernelGGL(k_gate_advance, dim3(1), dim3(64), 0, st, ctl);
   return hipGetLastError();
 }
 

@@ -16,6 +16,16 @@ struct Scales {
 };
 inline size_t scale_floats(int N, int P) { return 3 * ((size_t)N * N + (size_t)(P / 16) * N * 3); }
 
+// Device-side gate of a launch: with ctl set, the kernel runs only when bit
+// *ctl of mask is set (every block reads the same word and returns at once
+// otherwise).  The tolerance mode of the solve enqueues every iteration up to
+// its cap and lets these gates skip the ones after convergence, so it needs
+// no host round trip and can be captured in a graph.
+struct Gate {
+  const int* ctl = nullptr;
+  int mask = 0;
+};
+
 // Geometry of the FFT box and its half spectrum.
 struct FftGeom {
   int N;                  // n_pad
@@ -24,6 +34,7 @@ struct FftGeom {
   const float2* tw;       // exp(-2 pi i t / N), t < N
   int bf16x3 = 0;         // y passes with the radix-16 stage on the matrix cores (BF16x3)
   Scales sc{};            // scale tables of the half-precision spectra
+  Gate gate{};            // gate of the current launch (set by fft_pass from PassDesc)
 };
 
 // Arguments of a z pass (see pm_fft.hip).
@@ -75,10 +86,19 @@ struct PassDesc {
   // exist for the passes of the increment solve)
   int io = 0;
   const float* base = nullptr;   // PASS_X_LIN_*: the field linearised about, [3][N^3]
+  Gate gate{};
 };
 
 hipError_t fft_pass(const FftGeom& g, const PassDesc& d, hipStream_t st);
-hipError_t reduce_partials(const double* partials, int n, double* out, hipStream_t st);
+hipError_t reduce_partials(const double* partials, int n, double* out, hipStream_t st, Gate gate = Gate{});
+// Tolerance mode on the device.  ctl[0]: 0 iterating, 1 converged in this
+// iteration (the final projection runs), 2 finished; ctl[1]: iterations done;
+// ctl[2]: 1 if a residual was not finite.  tol_check (k >= 1): when ctl[0] is
+// 0, records k and sets ctl[0] = 1 if k = kmax, or if k >= 2 and
+// r_(k-1) = sqrt(acc[k-1]) / sqrt(acc[0] / n3) is at most tol or not finite.
+// gate_advance: ctl[0] 1 -> 2.
+hipError_t tol_check(int* ctl, const double* acc, int k, int kmax, double tol, double n3, hipStream_t st);
+hipError_t gate_advance(int* ctl, hipStream_t st);
 int x_blocks(int N);
 int z_blocks(int N);
 int z_blocks_io(int N, int io);   // z-pass blocks with half-precision spectra (io != 0)
