@@ -570,9 +570,10 @@ def main():
     ap.add_argument("--dft", choices=("fp32", "bf16x3"), default="fp32",
                     help="arithmetic of the y passes' radix-16 stage: FP32 butterflies (default) or "
                          "BF16x3 dense DFT-16 products on the matrix cores (PM_F_DFT_BF16X3)")
-    ap.add_argument("--cpu-full", action="store_true",
-                    help="only time one complete FP64 oracle step of the workload (no GPU; set "
-                         "ORACLE_FFT_WORKERS for the FFT threads) and the bounded-sample baseline")
+    ap.add_argument("--cpu-full", nargs="?", const="both", choices=("both", "sample"),
+                    help="only time one complete FP64 oracle step of the workload and the bounded-sample "
+                         "baseline ('sample': the baseline alone); no GPU; ORACLE_FFT_WORKERS sets the "
+                         "FFT threads")
     ap.add_argument("--launch", choices=("graph", "eager"), default="graph",
                     help="time replays of the step recorded as a HIP graph (default) or eager pm_step calls")
     a = ap.parse_args()
@@ -588,7 +589,7 @@ def main():
         return
     if a.cpu_full:
         w = make_workload(a.workload)
-        rec = {"full_step": cpu_full_step(w)}
+        rec = {"full_step": cpu_full_step(w)} if a.cpu_full == "both" else {}
         print("cpu baseline sample", file=sys.stderr, flush=True)
         rec["sample_baseline"] = cpu_baseline(w)
         print(json.dumps(rec), flush=True)
