@@ -419,6 +419,7 @@ def main(argv=None):
     ap.add_argument("--train-n", type=int, default=TRAIN_N, help="network size (half the FFT box) for training")
     ap.add_argument("--init", default=None, help="start training from these parameters")
     ap.add_argument("--seed0", type=int, default=0, help="first training seed")
+    ap.add_argument("--tol", type=float, default=1e-4, help="eval: residual of the tolerance-mode comparison")
     a = ap.parse_args(argv)
     log = lambda s: print(s, flush=True)  # noqa: E731
     torch.cuda.init()
@@ -441,7 +442,7 @@ def main(argv=None):
         M.pm_net_set_params(net, v)
         res = {"results": []}
         for w in held_out_inputs(a.eval_n, a.eval_count):
-            r = compare_starts(w, net)
+            r = compare_starts(w, net, tol=a.tol)
             log(json.dumps(r))
             res["results"].append(r)
         res["summary"] = summarize(res["results"])
