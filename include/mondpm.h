@@ -321,11 +321,12 @@ pm_status pm_potential_field(pm_ctx* ctx, const float* phi, float* g);
  * average pooling, nearest 2x upsampling with skip concatenation, a 1x1x1
  * head to 3 channels) predicts H from the Newton field.  H fills the whole
  * periodic box (about half of it lies outside the physical region), so the
- * network sees the whole box at half resolution, n = n_pad / 2 voxels per
- * axis, each the mean of a 2x2x2 block of cells, with periodic convolutions:
+ * network sees the whole box at half (or quarter) resolution, n = n_pad / f
+ * voxels per axis with f = 2 (or 4), each the mean of an f^3 block of cells,
+ * with periodic convolutions:
  *         g_c = block mean of g_N,  rms = sqrt(mean |g_c|^2),
  *         x = [g_c / rms, log10(|g_c| / a0 + 1e-30)],
- *         H0 = rms * net(x), each value repeated over its 2x2x2 block;
+ *         H0 = rms * net(x), each value repeated over its f^3 block;
  * aqual_solve then starts from the divergence-free part of H0.  Operands are
  * BF16 on the matrix cores with FP32 accumulation; parameters are FP32.
  * Parameter vector (pm_net_param_count floats): for each layer in the order
@@ -337,8 +338,8 @@ pm_status pm_potential_field(pm_ctx* ctx, const float* phi, float* g);
  * stream given to pm_net_create. */
 typedef struct pm_net pm_net;
 int64_t   pm_net_param_count(void);
-/* n: voxels per axis (power of two, 8..512; n_pad / 2 of the contexts it is
- * used with); max_batch: slots for training pairs (1..64).  Parameters start
+/* n: voxels per axis (power of two, 8..512; n_pad / 2 or n_pad / 4 of the
+ * contexts it is used with); max_batch: slots for training pairs (1..64).  Parameters start
  * at zero; set them with pm_net_set_params.  Synchronises. */
 pm_status pm_net_create(int32_t n, int32_t max_batch, void* stream, pm_net** out);
 pm_status pm_net_destroy(pm_net* net);

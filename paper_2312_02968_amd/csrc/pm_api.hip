@@ -1171,7 +1171,8 @@ static pm_status check_slot(pm_net* m, int32_t slot) {
 
 static pm_status check_pair(pm_ctx* c, pm_net* m) {
   if (!c || !m) return inval("NULL argument");
-  if (c->N != 2 * m->b.n) return inval("net size n must be half the context's n_pad");
+  if (c->N != 2 * m->b.n && c->N != 4 * m->b.n)
+    return inval("net size n must be a half or a quarter of the context's n_pad");
   return PM_OK;
 }
 
@@ -1181,7 +1182,7 @@ pm_status pm_net_input(pm_ctx* c, pm_net* m, const float* phiN, int32_t slot) {
   if (s != PM_OK) return s;
   if (!phiN) return inval("phiN is NULL");
   const double s_px = c->p.box / c->p.n;
-  HIPCHK(net::features(m->b, slot, phiN, 0.5 / s_px, c->p.a0, c->st));
+  HIPCHK(net::features(m->b, slot, phiN, 0.5 / s_px, c->p.a0, c->N / m->b.n, c->st));
   return PM_OK;
 }
 
@@ -1191,7 +1192,7 @@ pm_status pm_net_target(pm_ctx* c, pm_net* m, const float* phiN, const float* F,
   if (s != PM_OK) return s;
   if (!phiN || !F) return inval("phiN and F are required");
   const double s_px = c->p.box / c->p.n;
-  HIPCHK(net::target_from_field(m->b, slot, phiN, F, 0.5 / s_px, c->st));
+  HIPCHK(net::target_from_field(m->b, slot, phiN, F, 0.5 / s_px, c->N / m->b.n, c->st));
   return PM_OK;
 }
 
@@ -1297,8 +1298,8 @@ pm_status pm_net_forward(pm_ctx* c, pm_net* m, const float* phiN, float* H0) {
   if (s != PM_OK) return s;
   if (!phiN || !H0) return inval("phiN and H0 are required");
   const double s_px = c->p.box / c->p.n;
-  HIPCHK(net::features(m->b, 0, phiN, 0.5 / s_px, c->p.a0, c->st));
+  HIPCHK(net::features(m->b, 0, phiN, 0.5 / s_px, c->p.a0, c->N / m->b.n, c->st));
   HIPCHK(net::forward(m->b, 1, c->st));
-  HIPCHK(net::start_field(m->b, H0, c->st));
+  HIPCHK(net::start_field(m->b, H0, c->N / m->b.n, c->st));
   return PM_OK;
 }

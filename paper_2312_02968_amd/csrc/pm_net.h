@@ -69,12 +69,13 @@ hipError_t adam(const Buffers& b, float lr, float beta1, float beta2, float eps,
 // Input of one slot from the Newton potential phiN [N^3]: g_N = -D phi_N
 // (central differences), its block means g_c, rms = sqrt(mean |g_c|^2), and
 // the channels [g_c / rms, log10(|g_c| / a0 + 1e-30)].
-hipError_t features(const Buffers& b, int slot, const float* phiN, double inv_2s, double a0, hipStream_t st);
+// fb: box cells per network voxel along an axis (n_pad / n), 2 or 4
+hipError_t features(const Buffers& b, int slot, const float* phiN, double inv_2s, double a0, int fb, hipStream_t st);
 // Training target of one slot: block mean of (F - g_N) / rms (F: [3][N^3]).
-hipError_t target_from_field(const Buffers& b, int slot, const float* phiN, const float* F, double inv_2s,
+hipError_t target_from_field(const Buffers& b, int slot, const float* phiN, const float* F, double inv_2s, int fb,
                              hipStream_t st);
 // H0 [3][N^3]: rms * yhat of slot 0 repeated over each 2 x 2 x 2 block.
-hipError_t start_field(const Buffers& b, float* H0, hipStream_t st);
+hipError_t start_field(const Buffers& b, float* H0, int fb, hipStream_t st);
 // Test helpers: FP32 [4][n^3] (device) -> input channels of a slot.
 hipError_t set_input(const Buffers& b, int slot, const float* x4, hipStream_t st);
 // and back: the 4 input channels of a slot as FP32 [4][n^3] (device).

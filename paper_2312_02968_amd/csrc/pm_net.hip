@@ -603,49 +603,54 @@ __device__ __forceinline__ void dphi(const float* __restrict__ phi, int x, int y
   d[2] = (phi[(int64_t)((z + 1) & m) * NN + yr + x] - phi[(int64_t)((z - 1) & m) * NN + yr + x]) * inv_2s;
 }
 
-// Block mean of g_N = -D phi_N over the 2 x 2 x 2 cells of coarse voxel (X, Y, Z).
+// Block mean of g_N = -D phi_N over the FB^3 cells of coarse voxel (X, Y, Z)
+// (FB = N / n: 2, or 4 for the quarter-resolution network).
+template <int FB>
 __device__ __forceinline__ void coarse_gN(const float* __restrict__ phi, int X, int Y, int Z, int N, float inv_2s,
                                           float* g) {
   g[0] = g[1] = g[2] = 0.0f;
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
+  for (int k = 0; k < FB * FB * FB; ++k) {
     float d[3];
-    dphi(phi, 2 * X + (k & 1), 2 * Y + ((k >> 1) & 1), 2 * Z + (k >> 2), N, inv_2s, d);
+    dphi(phi, FB * X + k % FB, FB * Y + (k / FB) % FB, FB * Z + k / (FB * FB), N, inv_2s, d);
     g[0] -= d[0];
     g[1] -= d[1];
     g[2] -= d[2];
   }
-  g[0] *= 0.125f;
-  g[1] *= 0.125f;
-  g[2] *= 0.125f;
+  constexpr float w = 1.0f / (FB * FB * FB);
+  g[0] *= w;
+  g[1] *= w;
+  g[2] *= w;
 }
 
-// coarse voxel index v of an n^3 grid (n = N / 2) -> (X, Y, Z)
+// coarse voxel index v of an n^3 grid (n = N / FB) -> (X, Y, Z)
 __device__ __forceinline__ void coarse_xyz(int64_t v, int n, int& X, int& Y, int& Z) {
   X = (int)(v % n);
   Y = (int)((v / n) % n);
   Z = (int)(v / ((int64_t)n * n));
 }
 
+template <int FB>
 __global__ __launch_bounds__(NT) void k_feat_sumsq(const float* __restrict__ phi, int n, float inv_2s, double* part) {
   double acc[1] = {0.0};
-  const int N = 2 * n;
+  const int N = FB * n;
   const int64_t nvox = (int64_t)n * n * n;
   for (int64_t v = blockIdx.x * (int64_t)NT + threadIdx.x; v < nvox; v += (int64_t)gridDim.x * NT) {
     int X, Y, Z;
     coarse_xyz(v, n, X, Y, Z);
     float g[3];
-    coarse_gN(phi, X, Y, Z, N, inv_2s, g);
+    coarse_gN<FB>(phi, X, Y, Z, N, inv_2s, g);
     acc[0] += (double)g[0] * g[0] + (double)g[1] * g[1] + (double)g[2] * g[2];
   }
   block_reduce_store<1>(acc, part);
 }
 
 // x[v] = [g_c / rms, log10(|g_c| / a0 + 1e-30), 0 ...]
+template <int FB>
 __global__ __launch_bounds__(NT) void k_feat_write(const float* __restrict__ phi, int n, float inv_2s, float inv_a0,
                                                    const double* __restrict__ sumsq, double* rms_out,
                                                    bf16* __restrict__ x) {
-  const int N = 2 * n;
+  const int N = FB * n;
   const int64_t nvox = (int64_t)n * n * n;
   const double rms = sqrt(*sumsq / (double)nvox);
   const float scale = rms > 0.0 ? (float)(1.0 / rms) : 0.0f;
@@ -654,7 +659,7 @@ __global__ __launch_bounds__(NT) void k_feat_write(const float* __restrict__ phi
     int X, Y, Z;
     coarse_xyz(v, n, X, Y, Z);
     float g[3];
-    coarse_gN(phi, X, Y, Z, N, inv_2s, g);
+    coarse_gN<FB>(phi, X, Y, Z, N, inv_2s, g);
     const float mag = sqrtf(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
     uint4 o0 = make_uint4(0u, 0u, 0u, 0u), o1 = make_uint4(0u, 0u, 0u, 0u);
     bf16* e = reinterpret_cast<bf16*>(&o0);
@@ -668,19 +673,20 @@ __global__ __launch_bounds__(NT) void k_feat_write(const float* __restrict__ phi
 }
 
 // target[c][v] = block mean of (F[c] - g_N[c]) = (F[c] + D_c phi_N), over rms
+template <int FB>
 __global__ __launch_bounds__(NT) void k_target(const float* __restrict__ phi, const float* __restrict__ F, int n,
                                                float inv_2s, const double* __restrict__ rms, float* __restrict__ t) {
-  const int N = 2 * n;
+  const int N = FB * n;
   const int64_t nvox = (int64_t)n * n * n, cs = (int64_t)N * N * N;
   const double r = *rms;
-  const float inv = r > 0.0 ? (float)(0.125 / r) : 0.0f;
+  const float inv = r > 0.0 ? (float)(1.0 / (FB * FB * FB * r)) : 0.0f;
   for (int64_t v = blockIdx.x * (int64_t)NT + threadIdx.x; v < nvox; v += (int64_t)gridDim.x * NT) {
     int X, Y, Z;
     coarse_xyz(v, n, X, Y, Z);
     float h[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int x = 2 * X + (k & 1), y = 2 * Y + ((k >> 1) & 1), z = 2 * Z + (k >> 2);
+    for (int k = 0; k < FB * FB * FB; ++k) {
+      const int x = FB * X + k % FB, y = FB * Y + (k / FB) % FB, z = FB * Z + k / (FB * FB);
       float d[3];
       dphi(phi, x, y, z, N, inv_2s, d);
       const int64_t j = ((int64_t)z * N + y) * N + x;
@@ -693,14 +699,15 @@ __global__ __launch_bounds__(NT) void k_target(const float* __restrict__ phi, co
 }
 
 // H0[c][j] = rms * yhat[c][parent(j)] for every cell j of the N^3 box
+template <int FB>
 __global__ __launch_bounds__(NT) void k_start(const float* __restrict__ yhat, const double* __restrict__ rms, int n,
                                               float* __restrict__ H0) {
-  const int N = 2 * n;
+  const int N = FB * n;
   const int64_t nvox = (int64_t)n * n * n, cs = (int64_t)N * N * N;
   const float r = (float)*rms;
   for (int64_t j = blockIdx.x * (int64_t)NT + threadIdx.x; j < cs; j += (int64_t)gridDim.x * NT) {
     const int x = (int)(j % N), y = (int)((j / N) % N), z = (int)(j / ((int64_t)N * N));
-    const int64_t v = ((int64_t)(z >> 1) * n + (y >> 1)) * n + (x >> 1);
+    const int64_t v = ((int64_t)(z / FB) * n + (y / FB)) * n + (x / FB);
 #pragma unroll
     for (int c = 0; c < 3; ++c) H0[c * cs + j] = r * yhat[c * nvox + v];
   }
@@ -943,31 +950,49 @@ hipError_t adam(const Buffers& b, float lr, float beta1, float beta2, float eps,
   return pack_weights(b, st);
 }
 
-hipError_t features(const Buffers& b, int slot, const float* phiN, double inv_2s, double a0, hipStream_t st) {
+hipError_t features(const Buffers& b, int slot, const float* phiN, double inv_2s, double a0, int fb, hipStream_t st) {
   const int n = b.n;
   const int64_t nvox = level_voxels(n, 0);
   const int nb = grid_for(nvox);
-  if (nb > b.dpartial_count) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_feat_sumsq, dim3(nb), dim3(NT), 0, st, phiN, n, (float)inv_2s, b.dpartial);
+  if (nb > b.dpartial_count || (fb != 2 && fb != 4)) return hipErrorInvalidValue;
+  if (fb == 2)
+    hipLaunchKernelGGL(k_feat_sumsq<2>, dim3(nb), dim3(NT), 0, st, phiN, n, (float)inv_2s, b.dpartial);
+  else
+    hipLaunchKernelGGL(k_feat_sumsq<4>, dim3(nb), dim3(NT), 0, st, phiN, n, (float)inv_2s, b.dpartial);
   NETCHK(launched("k_feat_sumsq"));
   hipLaunchKernelGGL(k_reduce_d, dim3(1), dim3(NT), 0, st, b.dpartial, nb, 1, b.sums + slot);
   NETCHK(launched("k_reduce_d"));
-  hipLaunchKernelGGL(k_feat_write, dim3(nb), dim3(NT), 0, st, phiN, n, (float)inv_2s, (float)(1.0 / a0),
-                     b.sums + slot, b.rms + slot, b.x + (int64_t)slot * nvox * 16);
+  if (fb == 2)
+    hipLaunchKernelGGL(k_feat_write<2>, dim3(nb), dim3(NT), 0, st, phiN, n, (float)inv_2s, (float)(1.0 / a0),
+                       b.sums + slot, b.rms + slot, b.x + (int64_t)slot * nvox * 16);
+  else
+    hipLaunchKernelGGL(k_feat_write<4>, dim3(nb), dim3(NT), 0, st, phiN, n, (float)inv_2s, (float)(1.0 / a0),
+                       b.sums + slot, b.rms + slot, b.x + (int64_t)slot * nvox * 16);
   return launched("k_feat_write");
 }
 
-hipError_t target_from_field(const Buffers& b, int slot, const float* phiN, const float* F, double inv_2s,
+hipError_t target_from_field(const Buffers& b, int slot, const float* phiN, const float* F, double inv_2s, int fb,
                              hipStream_t st) {
   const int64_t nvox = level_voxels(b.n, 0);
-  hipLaunchKernelGGL(k_target, dim3(grid_for(nvox)), dim3(NT), 0, st, phiN, F, b.n, (float)inv_2s, b.rms + slot,
-                     b.target + (int64_t)slot * 3 * nvox);
+  if (fb == 2)
+    hipLaunchKernelGGL(k_target<2>, dim3(grid_for(nvox)), dim3(NT), 0, st, phiN, F, b.n, (float)inv_2s, b.rms + slot,
+                       b.target + (int64_t)slot * 3 * nvox);
+  else if (fb == 4)
+    hipLaunchKernelGGL(k_target<4>, dim3(grid_for(nvox)), dim3(NT), 0, st, phiN, F, b.n, (float)inv_2s, b.rms + slot,
+                       b.target + (int64_t)slot * 3 * nvox);
+  else
+    return hipErrorInvalidValue;
   return launched("k_target");
 }
 
-hipError_t start_field(const Buffers& b, float* H0, hipStream_t st) {
-  const int64_t cells = level_voxels(b.n, 0) * 8;
-  hipLaunchKernelGGL(k_start, dim3(grid_for(cells)), dim3(NT), 0, st, b.yhat, b.rms, b.n, H0);
+hipError_t start_field(const Buffers& b, float* H0, int fb, hipStream_t st) {
+  const int64_t cells = level_voxels(b.n, 0) * fb * fb * fb;
+  if (fb == 2)
+    hipLaunchKernelGGL(k_start<2>, dim3(grid_for(cells)), dim3(NT), 0, st, b.yhat, b.rms, b.n, H0);
+  else if (fb == 4)
+    hipLaunchKernelGGL(k_start<4>, dim3(grid_for(cells)), dim3(NT), 0, st, b.yhat, b.rms, b.n, H0);
+  else
+    return hipErrorInvalidValue;
   return launched("k_start");
 }
 

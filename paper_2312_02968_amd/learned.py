@@ -104,18 +104,20 @@ def training_sample(seed, n=TRAIN_N):
     return W.mixture_training_sample(seed, n=n, a_range=(2.0 * f, 8.0 * f))
 
 
-def make_dataset(net, count, seed0=0, log=print):
+def make_dataset(net, count, seed0=0, log=print, fb=2):
     """count pairs as device tensors X [count, 4 n^3] (BF16: the network reads
-    its input in BF16, so nothing is lost) and Y [count, 3 n^3] (FP32).  4096
-    pairs at n = 128 take 172 GB of device memory."""
+    its input in BF16, so nothing is lost) and Y [count, 3 n^3] (FP32), n the
+    network size; the region is fb n / 2 cells per axis (its FFT box fb n).
+    4096 pairs at n = 128 take 172 GB of device memory."""
     n = net.n
+    region = fb * n // 2
     X = torch.empty(count, 4 * n ** 3, device="cuda", dtype=torch.bfloat16)
     Y = torch.empty(count, 3 * n ** 3, device="cuda")
     xin = torch.empty(4 * n ** 3, device="cuda")
-    maker = PairMaker(n, 1 << 18)
+    maker = PairMaker(region, 1 << 18)
     t0 = time.time()
     for i in range(count):
-        w = training_sample(seed0 + i, n)
+        w = training_sample(seed0 + i, region)
         maker.pair(net, 0, w)
         M.pm_net_get_input(net, 0, xin)
         X[i] = xin.to(torch.bfloat16)
@@ -416,7 +418,9 @@ def main(argv=None):
     ap.add_argument("--eval-n", type=int, default=256)
     ap.add_argument("--eval-count", type=int, default=16)
     ap.add_argument("--out", default=None, help="JSON file for the results")
-    ap.add_argument("--train-n", type=int, default=TRAIN_N, help="network size (half the FFT box) for training")
+    ap.add_argument("--train-n", type=int, default=TRAIN_N, help="region size (half the FFT box) for training")
+    ap.add_argument("--factor", type=int, choices=(2, 4), default=2,
+                    help="box cells per network voxel along an axis (2: half resolution, 4: quarter)")
     ap.add_argument("--init", default=None, help="start training from these parameters")
     ap.add_argument("--seed0", type=int, default=0, help="first training seed")
     ap.add_argument("--tol", type=float, default=1e-4, help="eval: residual of the tolerance-mode comparison")
@@ -424,12 +428,12 @@ def main(argv=None):
     log = lambda s: print(s, flush=True)  # noqa: E731
     torch.cuda.init()
     if a.cmd == "train":
-        net = M.Net(a.train_n, a.batch)
+        net = M.Net(2 * a.train_n // a.factor, a.batch)
         M.pm_net_set_params(net, load_params(a.init) if a.init else init_params(0))
-        X, Y = make_dataset(net, a.pairs, seed0=a.seed0, log=log)
+        X, Y = make_dataset(net, a.pairs, seed0=a.seed0, log=log, fb=a.factor)
         hist = train(net, X, Y, a.epochs, batch=a.batch, lr=a.lr, log=log)
         save_params(a.weights, M.pm_net_get_params(net))
-        res = {"pairs": a.pairs, "epochs": a.epochs, "n": a.train_n, "loss": hist}
+        res = {"pairs": a.pairs, "epochs": a.epochs, "n": a.train_n, "factor": a.factor, "loss": hist}
     elif a.cmd == "time":
         res = {"timings": [time_network(a.eval_n, 1), time_network(TRAIN_N, a.batch)]}
         log(json.dumps(res))
@@ -438,7 +442,7 @@ def main(argv=None):
         log(json.dumps(res))
     else:
         v = load_params(a.weights)
-        net = M.Net(a.eval_n, 1)
+        net = M.Net(2 * a.eval_n // a.factor, 1)
         M.pm_net_set_params(net, v)
         res = {"results": []}
         for w in held_out_inputs(a.eval_n, a.eval_count):

@@ -176,12 +176,14 @@ def _cloud_rho(n, seed=3, N=300):
     return p, rho.astype(np.float32)
 
 
-def test_newton_potential_features_and_target():
-    n = 16
-    p, rho32 = _cloud_rho(n)
+@pytest.mark.parametrize("fb", [2, 4])
+def test_newton_potential_features_and_target(fb):
+    # fb: box cells per network voxel along an axis (half or quarter resolution)
+    p, rho32 = _cloud_rho(16)
     p = dict(p, iters=3, flags=M.PM_F_RESIDUAL)
     op = oparams(p)
     N = p["n_pad"]
+    n = N // fb
     ctx = M.pm_create(p, 0)
     net = M.Net(n, 2)
     rho = dev(rho32)
@@ -192,7 +194,7 @@ def test_newton_potential_features_and_target():
 
     M.pm_net_input(ctx, net, phiN, 1)
     x = host(M.pm_net_get_input(net, 1, torch.empty(4 * n ** 3, device="cuda"))).reshape(4, n, n, n)
-    xo, rms_o = ol.net_input(op, gN_o)
+    xo, rms_o = ol.net_input(op, gN_o, fb)
     assert abs(M.pm_net_get_rms(net, 1) - rms_o) < 1e-5 * rms_o
     # stored in BF16: within one BF16 step of the rounded FP64 value
     assert np.all(np.abs(x - xo) <= 2.0 ** -7 * np.abs(xo) + 1e-4)
@@ -206,17 +208,18 @@ def test_newton_potential_features_and_target():
     assert rel_l2(host(F).reshape(3, N, N, N), Fo) < 1e-4
     M.pm_net_target(ctx, net, phiN, F, 1)
     t = host(M.pm_net_get_target(net, 1, torch.empty(3 * n ** 3, device="cuda"))).reshape(3, n, n, n)
-    to = ol.target(op, io.H, rms_o)
+    to = ol.target(op, io.H, rms_o, fb)
     assert rel_l2(t, to) < 1e-3
     net.close()
     ctx.close()
 
 
-def test_learned_start_field_and_solve():
-    n = 16
-    p, rho32 = _cloud_rho(n, seed=5)
+@pytest.mark.parametrize("fb", [2, 4])
+def test_learned_start_field_and_solve(fb):
+    p, rho32 = _cloud_rho(16, seed=5)
     op = oparams(p)
     N = p["n_pad"]
+    n = N // fb
     v32, po = gpu_params(4)
     ctx = M.pm_create(p, 0)
     net = M.Net(n, 1)
@@ -227,12 +230,12 @@ def test_learned_start_field_and_solve():
     H0 = torch.empty(3 * N ** 3, device="cuda")
     M.pm_net_forward(ctx, net, phiN, H0)
     _, gN_o = orc.newton_potential(op, rho32.astype(np.float64))
-    xo, rms_o = ol.net_input(op, gN_o)
+    xo, rms_o = ol.net_input(op, gN_o, fb)
     yo, _ = cn.forward(po, xo, bf16=True, periodic=True)
-    H0o = ol.start_field(op, yo, rms_o)
+    H0o = ol.start_field(op, yo, rms_o, fb)
     H0g = host(H0).reshape(3, N, N, N)
     assert rel_l2(H0g, H0o) < 2e-2
-    assert np.array_equal(H0g, ol.fine(ol.coarse(H0g)))      # constant over 2 x 2 x 2 blocks
+    assert np.array_equal(H0g, ol.fine(ol.coarse(H0g, fb), fb))      # constant over fb^3 blocks
     # the solve from this start against the oracle's solve from its own start
     phi = grid(N)
     M.aqual_solve(ctx, rho, phi, H0=H0)

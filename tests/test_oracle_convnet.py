@@ -203,3 +203,24 @@ def test_net_input_and_start_field():
     assert H0.shape == (3, 16, 16, 16)
     assert np.allclose(H0[:, 5, 9, 14], rms * y[:, 2, 4, 7])
     assert np.allclose(ol.target(p, H0, rms), y)
+
+
+def test_net_input_and_start_field_at_quarter_resolution():
+    # f = 4: the network sees the box averaged over 4 x 4 x 4 blocks
+    p = pm.Params(n=8, n_pad=16, box=8.0, a0=2.0)
+    rng = np.random.default_rng(9)
+    gN = rng.standard_normal((3, 16, 16, 16))
+    x, rms = ol.net_input(p, gN, f=4)
+    assert x.shape == (4, 4, 4, 4)
+    gc = np.zeros((3, 4, 4, 4))
+    for Z in range(4):
+        for Y in range(4):
+            for X in range(4):
+                gc[:, Z, Y, X] = gN[:, 4 * Z:4 * Z + 4, 4 * Y:4 * Y + 4, 4 * X:4 * X + 4].sum(axis=(1, 2, 3)) / 64.0
+    assert rms == pytest.approx(math.sqrt((gc ** 2).sum() / 4 ** 3))
+    assert np.allclose(x[:3], gc / rms)
+    y = rng.standard_normal((3, 4, 4, 4))
+    H0 = ol.start_field(p, y, rms, f=4)
+    assert H0.shape == (3, 16, 16, 16)
+    assert np.allclose(H0[:, 5, 9, 14], rms * y[:, 1, 2, 3])
+    assert np.allclose(ol.target(p, H0, rms, f=4), y)
