@@ -31,6 +31,15 @@ from paper_2312_02968_amd import mondpm as M  # noqa: E402
 import workloads as W  # noqa: E402
 
 WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "learned_start.npy")
+# the same network at quarter resolution (voxels of 4^3 cells): cheaper to run
+# and, trained the same way, the better start; the default of the comparison
+WEIGHTS_Q4 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "learned_start_q4.npy")
+DEFAULT_FACTOR = 4
+
+
+def weights_for(factor):
+    """The committed weights of the network at this block factor."""
+    return WEIGHTS_Q4 if factor == 4 else WEIGHTS
 TRAIN_N = 128
 TARGET_ITERS = 12          # the long solve that defines the training target
 
@@ -414,17 +423,19 @@ def main(argv=None):
     ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--batch", type=int, default=4)
     ap.add_argument("--lr", type=float, default=3e-4)
-    ap.add_argument("--weights", default=WEIGHTS)
+    ap.add_argument("--weights", default=None, help="network parameters (default: the committed ones for --factor)")
     ap.add_argument("--eval-n", type=int, default=256)
     ap.add_argument("--eval-count", type=int, default=16)
     ap.add_argument("--out", default=None, help="JSON file for the results")
     ap.add_argument("--train-n", type=int, default=TRAIN_N, help="region size (half the FFT box) for training")
-    ap.add_argument("--factor", type=int, choices=(2, 4), default=2,
+    ap.add_argument("--factor", type=int, choices=(2, 4), default=DEFAULT_FACTOR,
                     help="box cells per network voxel along an axis (2: half resolution, 4: quarter)")
     ap.add_argument("--init", default=None, help="start training from these parameters")
     ap.add_argument("--seed0", type=int, default=0, help="first training seed")
     ap.add_argument("--tol", type=float, default=1e-4, help="eval: residual of the tolerance-mode comparison")
     a = ap.parse_args(argv)
+    if a.weights is None:
+        a.weights = weights_for(a.factor)
     log = lambda s: print(s, flush=True)  # noqa: E731
     torch.cuda.init()
     if a.cmd == "train":

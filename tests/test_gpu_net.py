@@ -267,8 +267,9 @@ def test_net_forward_shift_equivariance_at_full_size():
     net.close()
 
 
+@pytest.mark.parametrize("fb", [2, 4], ids=["half", "quarter"])
 @pytest.mark.parametrize("case", ["mixture_256", "isothermal_256"])
-def test_trained_network_gains_over_the_zero_start(case):
+def test_trained_network_gains_over_the_zero_start(case, fb):
     # What the committed network buys at the size it was fine-tuned for
     # (256^3 grid, 512^3 box): the potential error after 1 and 2 iterations
     # from its start against the zero start's, both measured against a
@@ -288,8 +289,8 @@ def test_trained_network_gains_over_the_zero_start(case):
     ref = grid(N)
     M.aqual_solve(ctx, rho, ref)
     ctx.close()
-    net = M.Net(N // 2, 1)
-    M.pm_net_set_params(net, L.load_params(L.WEIGHTS))
+    net = M.Net(N // fb, 1)
+    M.pm_net_set_params(net, L.load_params(L.weights_for(fb)))
     c1 = M.pm_create(dict(p, iters=1), 0)
     phiN = grid(N)
     H0 = torch.empty(3 * N ** 3, device="cuda")
