@@ -224,3 +224,41 @@ def test_increment_full_size_properties(M):
     assert e < 1e-3
     assert np.array_equal(a16b, 2.0 * a16)
     ctx.close()
+
+
+def test_increment_1024_box_properties(M):
+    """The 1024^3 box (512^3 region): the 64-lane x pass and the 1024-point
+    column passes in their FP16 forms, FP16 against FP32 spectra and
+    bit-exact linearity, about the GPU's own base fields."""
+    w = W.random_cloud(21, 512, 1 << 16)
+    prm = dict(w["params"], iters=4, flags=M.PM_F_RESIDUAL)
+    ctx = M.pm_create(prm, len(w["mass"]))
+    N = ctx.N
+    assert N == 1024
+    R = N ** 3
+    pos = torch.from_numpy(w["pos"]).cuda()
+    mass = torch.from_numpy(w["mass"]).cuda()
+    vel = torch.from_numpy(w["vel"]).cuda()
+    rho = grid(N)
+    M.pm_deposit(ctx, pos, mass, rho)
+    phi = grid(N)
+    F = torch.zeros(3 * R, dtype=torch.float32, device="cuda")
+    M.aqual_solve_field(ctx, rho, phi, F)
+    gM = torch.zeros_like(F)
+    M.pm_potential_field(ctx, phi, gM)
+    del phi
+    rho1 = grid(N)
+    M.pm_deposit(ctx, pos + 4.0 * vel, mass, rho1)
+    drho = rho1 - rho
+    del rho, rho1
+    ctx.close()
+    ctx = M.pm_create(dict(w["params"], iters=2, flags=M.PM_F_RESIDUAL), 0)
+    out32, out16 = grid(N), grid(N)
+    M.aqual_solve_increment(ctx, drho, F, gM, out32, storage=M.PM_STORE_FP32)
+    M.aqual_solve_increment(ctx, drho, F, gM, out16, storage=M.PM_STORE_FP16)
+    e = float(torch.linalg.vector_norm((out16 - out32).double()) / torch.linalg.vector_norm(out32.double()))
+    _log(f"1024 box: FP16 against FP32 spectra, d_phi rel L2 {e:.2e}")
+    assert torch.isfinite(out16).all() and e < 1e-3
+    M.aqual_solve_increment(ctx, 2.0 * drho, F, gM, out32, storage=M.PM_STORE_FP16)
+    assert torch.equal(out32, 2.0 * out16)
+    ctx.close()
