@@ -390,6 +390,17 @@ pm_status pm_net_train_step(pm_net* net, int32_t batch, float lr, double* loss);
  * (device float [3][n_pad^3], overwritten).  Uses slot 0. */
 pm_status pm_net_forward(pm_ctx* ctx, pm_net* net, const float* phiN, float* H0);
 
+/* aqual_solve from the learned start in one call: the solve's own Newton
+ * spectrum gives phi_N for the network's features (no second Newton solve),
+ * the network runs on slot 0, and its coarse output enters the forward x
+ * transform directly, each value expanded over its block (no
+ * full-resolution H0 is written or read).  The same result as
+ * pm_newton_potential, pm_net_forward and aqual_solve with that H0.  rho,
+ * phi: device float [n_pad^3] (phi is written and may not be the context's
+ * internal grid); info and tol as in aqual_solve.  The network's slot 0 and
+ * the context's internal potential grid are overwritten. */
+pm_status aqual_solve_learned(pm_ctx* ctx, pm_net* net, const float* rho, float* phi, pm_solve_info* info);
+
 /* Last HIP error string seen by the library (host, static storage). */
 const char* pm_last_error(void);
 

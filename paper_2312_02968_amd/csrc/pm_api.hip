@@ -434,7 +434,7 @@ struct Increment {
 };
 
 static pm_status run_solve(pm_ctx* c, const float* rho, const float* H0, float* phi_out, pm_solve_info* info,
-                           bool want_info, const Increment* inc = nullptr) {
+                           bool want_info, const Increment* inc = nullptr, const net::Buffers* learned = nullptr) {
   const pm_params& p = c->p;
   const int N = c->N;
   const long long R = (long long)N * N * N;
@@ -458,9 +458,32 @@ static pm_status run_solve(pm_ctx* c, const float* rho, const float* H0, float* 
     HIPCHK(pass(c, d));
     HIPCHK(pass(c, pdesc(PASS_Y_FWD, c->phiN, 1)));
   }
+  // learned start: the Newton potential for the network's features from the
+  // spectrum just formed (a Poisson z pass into the work buffer, phiN kept),
+  // the network, and its coarse output expanded in the forward x pass in
+  // place of a full-resolution H0
+  if (learned) {
+    PassDesc z = pdesc(PASS_Z_POISSON, c->phiN);
+    z.z = zargs(c);
+    z.z.spec = c->phiN;
+    z.z.out = c->spec;
+    HIPCHK(pass(c, z));
+    HIPCHK(pass(c, pdesc(PASS_Y_INV, c->spec, 1)));
+    PassDesc x = pdesc(PASS_X_INV_REAL, c->spec);
+    x.real = c->phi;
+    HIPCHK(pass(c, x));
+    const double s_px = c->p.box / c->p.n;
+    const int fb = N / learned->n;
+    HIPCHK(net::features(*learned, 0, c->phi, 0.5 / s_px, c->p.a0, fb, c->st));
+    HIPCHK(net::forward(*learned, 1, c->st));
+    PassDesc d = pdesc(PASS_X_FWD_COARSE3, c->spec);
+    d.co = Coarse{learned->yhat, learned->rms, learned->n, fb};
+    HIPCHK(pass(c, d));
+    HIPCHK(pass(c, pdesc(PASS_Y_FWD, c->spec, 3)));
+  }
   // warm start: F0 = P_L g_N + P_T F_prev from the last F of the previous solve
   const bool keep_F = !inc && (p.flags & PM_F_WARM_START) != 0;
-  const bool warm = keep_F && c->have_F && !H0;
+  const bool warm = keep_F && c->have_F && !H0 && !learned;
   const float* start = inc ? nullptr : (H0 ? H0 : (warm ? c->fprev : nullptr));
   if (start) {
     PassDesc d = pdesc(PASS_X_FWD_REAL3, c->spec);
@@ -486,7 +509,7 @@ static pm_status run_solve(pm_ctx* c, const float* rho, const float* H0, float* 
   {
     PassDesc d = pdesc(PASS_Z_NEWTON, c->spec);
     d.z = zargs(c);
-    d.z.with_h0 = warm ? 2 : (start ? 1 : 0);
+    d.z.with_h0 = warm ? 2 : ((start || learned) ? 1 : 0);
     d.io = io ? 2 : 0;
     HIPCHK(pass(c, d));
     HIPCHK(reduce_partials(c->partials, z_blocks_io(N, d.io), c->dacc, c->st));
@@ -1291,6 +1314,16 @@ pm_status pm_net_train_step(pm_net* m, int32_t batch, float lr, double* loss) {
   pm_status s = pm_net_backward(m, batch, loss);
   if (s != PM_OK) return s;
   return pm_net_adam(m, lr);
+}
+
+pm_status aqual_solve_learned(pm_ctx* c, pm_net* m, const float* rho, float* phi, pm_solve_info* info) {
+  pm_status s = check_pair(c, m);
+  if (s != PM_OK) return s;
+  if (!rho || !phi) return inval("rho and phi are required");
+  if (phi == c->phi) return inval("phi is the context's internal grid");
+  s = run_solve(c, rho, nullptr, phi, info, info != nullptr, nullptr, &m->b);
+  if (s == PM_OK && info) info->bounds_flag = 0;
+  return s;
 }
 
 pm_status pm_net_forward(pm_ctx* c, pm_net* m, const float* phiN, float* H0) {

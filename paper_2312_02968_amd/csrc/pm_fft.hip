@@ -106,15 +106,27 @@ __device__ __forceinline__ void block_max(float* m) {
 // ----------------------------------------------------------------------------
 // XMODE.  X_LIN_*: the increment solve's linearised equations (pm_device.h,
 // linearised) about the base field `base` in place of nu / mu.
+// X_FWD_COARSE: as X_FWD_REAL with the rows expanded from a Coarse field.
 enum { X_FWD_REAL = 0, X_INV_REAL = 1, X_FUSED_NU = 2, X_FUSED_MU = 3, X_FUSED_NU_KEEP = 4, X_LIN_NU = 5,
-       X_LIN_NU_KEEP = 6, X_LIN_MU = 7 };
+       X_LIN_NU_KEEP = 6, X_LIN_MU = 7, X_FWD_COARSE = 8 };
 template <int XMODE>
 struct XKind {
   static constexpr bool fused = XMODE == X_FUSED_NU || XMODE == X_FUSED_NU_KEEP || XMODE == X_FUSED_MU;
   static constexpr bool lin = XMODE == X_LIN_NU || XMODE == X_LIN_NU_KEEP || XMODE == X_LIN_MU;
   static constexpr bool keep = XMODE == X_FUSED_NU_KEEP || XMODE == X_LIN_NU_KEEP;
   static constexpr bool mu = XMODE == X_FUSED_MU || XMODE == X_LIN_MU;
+  static constexpr bool from_real = XMODE == X_FWD_REAL || XMODE == X_FWD_COARSE;
 };
+
+// Element m of row `row` (two grid points, x = 2m and 2m + 1) of component c
+// of a Coarse field on the N^3 box: both points lie in one voxel (f >= 2).
+__device__ __forceinline__ float2 coarse_pair(const Coarse& co, int c, long long row, int m, int N) {
+  const long long z = row / N, y = row % N;
+  const long long n = co.n;
+  const long long v = ((z / co.f) * n + y / co.f) * n + (2 * m) / co.f;
+  const float val = (float)*co.rms * co.y[c * n * n * n + v];
+  return make_float2(val, val);
+}
 
 // r2c split: LDS holds Z = FFT_H(x[2m] + i x[2m+1]) for each sequence; turn
 // it into X[k], k = 0..H (X[H] goes to element H, one past the complex data).
@@ -194,7 +206,7 @@ __global__ __launch_bounds__(NT) void k_xpass(float2* spec, long long comp_strid
                                               float* real, long long real_comp_stride,
                                               const float2* __restrict__ tw, int mu_mode, float inv_a0,
                                               float* fprev, double* partials, Dipole dip,
-                                              const float* __restrict__ base, Scales sc, Gate gate) {
+                                              const float* __restrict__ base, Scales sc, Gate gate, Coarse co) {
   if (gated_off(gate)) return;
   using XK = XKind<XMODE>;
   constexpr int S = NC * ROWS;
@@ -208,7 +220,13 @@ __global__ __launch_bounds__(NT) void k_xpass(float2* spec, long long comp_strid
   const __half2* spec_h = reinterpret_cast<const __half2*>(spec);
 
   // ---- load
-  if (XMODE == X_FWD_REAL) {
+  if (XMODE == X_FWD_COARSE) {
+    for (int b = threadIdx.x; b < S * H; b += NT) {
+      const int q = b / H, m = b % H;
+      const int c = q / ROWS, r = q % ROWS;
+      lds[m * IS + q] = coarse_pair(co, c, row0 + r, m, N);
+    }
+  } else if (XMODE == X_FWD_REAL) {
     for (int b = threadIdx.x; b < S * H; b += NT) {
       const int q = b / H, m = b % H;
       const int c = q / ROWS, r = q % ROWS;
@@ -238,7 +256,7 @@ __global__ __launch_bounds__(NT) void k_xpass(float2* spec, long long comp_strid
   }
   __syncthreads();
 
-  if (XMODE != X_FWD_REAL) {
+  if (!XK::from_real) {
     c2r_merge<H, S, NT>(lds, IS, tw_s);
     block_fft<H, S, NT, true, true>(lds, 1, IS, tw_s, 2);
   }
@@ -531,7 +549,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(XWaves<H, X
                                                     long long real_comp_stride, const float2* __restrict__ tw,
                                                     int mu_mode, float inv_a0, float* fprev, double* partials,
                                                     Dipole dip, const float* __restrict__ base, Scales sc,
-                                                    Gate gate) {
+                                                    Gate gate, Coarse co) {
   if (gated_off(gate)) return;
   using X = XWave<H>;
   using XK = XKind<XMODE>;
@@ -551,7 +569,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(XWaves<H, X
   float2 v[NC][RG];
   const int pl = (lane & ~(LANES - 1)) | ((LANES - j) & (LANES - 1));   // lane of the partner elements
 
-  if (XMODE == X_FWD_REAL) {
+  if (XMODE == X_FWD_COARSE) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int r = 0; r < RG; ++r) v[c][r] = coarse_pair(co, c, row, j + LANES * r, N);
+  } else if (XMODE == X_FWD_REAL) {
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       const float2* src = reinterpret_cast<const float2*>(real + c * real_comp_stride + row * N);
@@ -1402,21 +1425,21 @@ struct Cfg {
 template <int N, int XMODE, int NC, int IO = 0>
 hipError_t launch_x(const FftGeom& g, float2* spec, float* real, long long real_cs, int mu_mode,
                     float inv_a0, float* fprev, double* partials, hipStream_t st, Dipole dip = Dipole{},
-                    const float* base = nullptr) {
+                    const float* base = nullptr, Coarse co = Coarse{}) {
   using C = Cfg<N>;
   if constexpr (N == 512 || N == 1024) {
     using X = XWave<N / 2>;
     const size_t sh = sizeof(float2) * (N + (size_t)X::ROWS * X::XB + X::TWL);
     hipLaunchKernelGGL((k_xpass_wave<N / 2, XMODE, NC, IO>), dim3(N * N / X::ROWS), dim3(256), sh, st, spec,
                        g.comp_stride, real, real_cs, g.tw, mu_mode, inv_a0, fprev, partials, dip, base, g.sc,
-                       g.gate);
+                       g.gate, co);
     return hipGetLastError();
   } else {
     const int blocks = N * N / C::ROWS;
     const size_t sh = sizeof(float2) * ((size_t)(C::H + 1) * (NC * C::ROWS + 1) + N);
     hipLaunchKernelGGL((k_xpass<C::H, C::ROWS, NC, kNT, XMODE, IO>), dim3(blocks), dim3(kNT), sh, st, spec,
                        g.comp_stride, real, real_cs, g.tw, mu_mode, inv_a0, fprev, partials, dip, base, g.sc,
-                       g.gate);
+                       g.gate, co);
     return hipGetLastError();
   }
 }
@@ -1471,6 +1494,10 @@ hipError_t run_pass(const FftGeom& g, const PassDesc& d, hipStream_t st) {
       return launch_x<N, X_FWD_REAL, 1>(g, d.spec, d.real, d.real_cs, 0, 0.f, nullptr, nullptr, st, d.dip);
     case PASS_X_FWD_REAL3:
       return launch_x<N, X_FWD_REAL, 3>(g, d.spec, d.real, d.real_cs, 0, 0.f, nullptr, nullptr, st);
+    case PASS_X_FWD_COARSE3:
+      if (!d.co.y || !d.co.rms || d.co.f < 2 || d.co.n * d.co.f != N) return hipErrorInvalidValue;
+      return launch_x<N, X_FWD_COARSE, 3>(g, d.spec, nullptr, 0, 0, 0.f, nullptr, nullptr, st, Dipole{}, nullptr,
+                                          d.co);
     case PASS_X_INV_REAL:
       return launch_x<N, X_INV_REAL, 1>(g, d.spec, d.real, d.real_cs, 0, 0.f, nullptr, nullptr, st);
     case PASS_X_INV_REAL3:

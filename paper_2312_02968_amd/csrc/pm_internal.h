@@ -55,7 +55,7 @@ struct ZArgs {
 };
 
 enum PassKind {
-  PASS_X_FWD_REAL, PASS_X_FWD_REAL3, PASS_X_INV_REAL, PASS_X_INV_REAL3, PASS_X_NU, PASS_X_MU,
+  PASS_X_FWD_REAL, PASS_X_FWD_REAL3, PASS_X_FWD_COARSE3, PASS_X_INV_REAL, PASS_X_INV_REAL3, PASS_X_NU, PASS_X_MU,
   PASS_X_LIN_NU, PASS_X_LIN_MU, PASS_Z_GRAD,
   PASS_Y_FWD, PASS_Y_INV,
   PASS_Z_FWD, PASS_Z_INV, PASS_Z_NEWTON, PASS_Z_CURL, PASS_Z_CURL_FINAL, PASS_Z_DIV, PASS_Z_POISSON, PASS_Z_APPARENT
@@ -67,6 +67,17 @@ enum PassKind {
 // added to the density as the forward real x pass loads it.
 struct Dipole {
   float x = 0.f, y = 0.f, z = 0.f;
+};
+
+// A three-component field given on a coarse grid of n^3 voxels, each value
+// repeated over the f^3 box cells of its voxel and scaled by *rms (the
+// learned start's network output, read by PASS_X_FWD_COARSE3 in place of a
+// full-resolution H0).
+struct Coarse {
+  const float* y = nullptr;     // [3][n^3]
+  const double* rms = nullptr;
+  int n = 0;
+  int f = 0;
 };
 
 struct PassDesc {
@@ -86,6 +97,7 @@ struct PassDesc {
   // exist for the passes of the increment solve)
   int io = 0;
   const float* base = nullptr;   // PASS_X_LIN_*: the field linearised about, [3][N^3]
+  Coarse co{};                   // PASS_X_FWD_COARSE3
   Gate gate{};
 };
 

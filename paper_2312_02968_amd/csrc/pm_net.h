@@ -30,7 +30,7 @@ int64_t bias_offset(int layer);
 
 // Device buffers of one network (owned by the C ABI's pm_net).
 struct Buffers {
-  int n = 0;          // voxels per axis at level 1 (half the FFT box)
+  int n = 0;          // voxels per axis at level 1 (half or a quarter of the FFT box)
   int max_batch = 0;
   float* params = nullptr;   // FP32 master parameters [P]
   float* grads = nullptr;    // [P]
@@ -74,7 +74,7 @@ hipError_t features(const Buffers& b, int slot, const float* phiN, double inv_2s
 // Training target of one slot: block mean of (F - g_N) / rms (F: [3][N^3]).
 hipError_t target_from_field(const Buffers& b, int slot, const float* phiN, const float* F, double inv_2s, int fb,
                              hipStream_t st);
-// H0 [3][N^3]: rms * yhat of slot 0 repeated over each 2 x 2 x 2 block.
+// H0 [3][N^3]: rms * yhat of slot 0 repeated over each fb x fb x fb block.
 hipError_t start_field(const Buffers& b, float* H0, int fb, hipStream_t st);
 // Test helpers: FP32 [4][n^3] (device) -> input channels of a slot.
 hipError_t set_input(const Buffers& b, int slot, const float* x4, hipStream_t st);

@@ -202,14 +202,14 @@ def rejected(info):
     return len(r) >= 2 and not (r[1] < r[0])
 
 
-def learned_solve_tol(ctx, net, rho, phiN, H0, phi):
+def learned_solve_tol(ctx, net, rho, phi):
     """The learned path in tolerance mode, with the plain iteration as the
-    fallback: Newton potential, network, solve from the learned start; if that
-    solve is rejected, solve again from H = 0.  Returns (info, fell_back);
-    the time of both solves counts against the learned start."""
-    M.pm_newton_potential(ctx, rho, phiN)
-    M.pm_net_forward(ctx, net, phiN, H0)
-    info = M.aqual_solve(ctx, rho, phi, H0=H0)
+    fallback: the solve from the learned start (aqual_solve_learned: features
+    from the solve's own Newton spectrum, network, coarse start expanded in the
+    first transform); if that solve is rejected, solve again from H = 0.
+    Returns (info, fell_back); the time of both solves counts against the
+    learned start."""
+    info = M.aqual_solve_learned(ctx, net, rho, phi)
     if rejected(info):
         return M.aqual_solve(ctx, rho, phi), True
     return info, False
@@ -266,15 +266,13 @@ def compare_starts(w, net, K_plain=4, K_ref=30, tol=1e-4, max_iters=30, reps=3):
     t_plain = min(_timed(lambda: M.aqual_solve(cp, rho, phi, want_info=False))[0] for _ in range(reps))
     cp.close()
     if K_star is not None:
+        # the learned path in one call; its start costs what it adds to a
+        # plain solve with the same number of iterations
         cl = ctx_for(iters=K_star)
-
-        def learned_path():
-            M.pm_newton_potential(cl, rho, phiN)
-            M.pm_net_forward(cl, net, phiN, H0)
-            M.aqual_solve(cl, rho, phi, H0=H0, want_info=False)
-        t_learned = min(_timed(learned_path)[0] for _ in range(reps))
-        t_net = min(_timed(lambda: (M.pm_newton_potential(cl, rho, phiN),
-                                    M.pm_net_forward(cl, net, phiN, H0)))[0] for _ in range(reps))
+        t_learned = min(_timed(lambda: M.aqual_solve_learned(cl, net, rho, phi, want_info=False))[0]
+                        for _ in range(reps))
+        t_same = min(_timed(lambda: M.aqual_solve(cl, rho, phi, want_info=False))[0] for _ in range(reps))
+        t_net = t_learned - t_same
         cl.close()
     else:
         t_learned = t_net = None
@@ -287,13 +285,13 @@ def compare_starts(w, net, K_plain=4, K_ref=30, tol=1e-4, max_iters=30, reps=3):
     ct = ctx_for(iters=max_iters, tol=tol)
     phi_l = torch.empty_like(rho)
     ip = M.aqual_solve(ct, rho, phi)
-    il_raw = M.aqual_solve(ct, rho, phi_l, H0=H0)
-    il, fallback = learned_solve_tol(ct, net, rho, phiN, H0, phi_l)
+    il_raw = M.aqual_solve_learned(ct, net, rho, phi_l)
+    il, fallback = learned_solve_tol(ct, net, rho, phi_l)
     fp_diff = float(torch.linalg.vector_norm(phi_l - phi)) / float(torch.linalg.vector_norm(phi))
     t_tol_plain = min(_timed(lambda: M.aqual_solve(ct, rho, phi, want_info=False))[0] for _ in range(reps))
 
     def learned_tol():
-        learned_solve_tol(ct, net, rho, phiN, H0, phi_l)
+        learned_solve_tol(ct, net, rho, phi_l)
     t_tol_learned = min(_timed(learned_tol)[0] for _ in range(reps))
     ct.close()
     c1.close()

@@ -87,6 +87,7 @@ def lib():
         L.aqual_solve_field.argtypes = [VP, VP, VP, VP, VP, P(PmSolveInfo)]
         L.aqual_solve_increment.argtypes = [VP, VP, VP, VP, I32, VP, VP, P(PmSolveInfo)]
         L.pm_potential_field.argtypes = [VP, VP, VP]
+        L.aqual_solve_learned.argtypes = [VP, VP, VP, VP, P(PmSolveInfo)]
         L.pm_net_param_count.argtypes = []
         L.pm_net_param_count.restype = I64
         L.pm_net_create.argtypes = [I32, I32, VP, P(VP)]
@@ -366,6 +367,16 @@ def pm_potential_field(ctx: Ctx, phi, g):
     R = ctx.N ** 3
     _check(lib().pm_potential_field(ctx.handle, _ptr(phi, numel=R, name="phi"), _ptr(g, numel=3 * R, name="g")),
            "pm_potential_field")
+
+
+def aqual_solve_learned(ctx: Ctx, net, rho, phi, want_info=True):
+    """aqual_solve from the learned start of net in one call (see
+    include/mondpm.h)."""
+    info = PmSolveInfo()
+    _check(lib().aqual_solve_learned(ctx.handle, net.handle, _ptr(rho, numel=ctx.N ** 3, name="rho"),
+                                     _ptr(phi, numel=ctx.N ** 3, name="phi"),
+                                     ctypes.byref(info) if want_info else None), "aqual_solve_learned")
+    return info.to_dict() if want_info else None
 
 
 def pm_net_param_count() -> int:

@@ -334,9 +334,8 @@ def test_learned_start_falls_back_to_the_zero_start(weights):
     net = M.Net(N // 2, 1)
     v = np.full(M.pm_net_param_count(), np.nan if weights == "nan" else 0.0, dtype=np.float32)
     M.pm_net_set_params(net, v)
-    phiN, phi = grid(N), grid(N)
-    H0 = torch.empty(3 * N ** 3, device="cuda")
-    info, fell_back = L.learned_solve_tol(ctx, net, rho, phiN, H0, phi)
+    phi = grid(N)
+    info, fell_back = L.learned_solve_tol(ctx, net, rho, phi)
     assert info["status"] == M.PM_OK
     if weights == "nan":
         assert fell_back
@@ -344,5 +343,32 @@ def test_learned_start_falls_back_to_the_zero_start(weights):
     else:
         assert not fell_back
         assert rel_l2(host(phi), host(phi_plain)) < 1e-6
+    net.close()
+    ctx.close()
+
+
+@pytest.mark.parametrize("fb", [2, 4])
+def test_one_call_learned_solve_equals_the_separate_calls(fb):
+    # aqual_solve_learned forms the features from the solve's own Newton
+    # spectrum and expands the network's coarse output inside the first
+    # transform; pm_newton_potential, pm_net_forward and aqual_solve with the
+    # full-resolution H0 run the same arithmetic step by step
+    w = W.random_cloud(6, 32, 500, mu=W.MU_STANDARD)
+    p = dict(w["params"], iters=3, flags=M.PM_F_RESIDUAL)
+    N = p["n_pad"]
+    v32, _ = gpu_params(7)
+    ctx = M.pm_create(p, 500)
+    rho = grid(N)
+    M.pm_deposit(ctx, dev(w["pos"]), dev(w["mass"]), rho)
+    net = M.Net(N // fb, 1)
+    M.pm_net_set_params(net, v32)
+    phiN, phi_sep, phi_one = grid(N), grid(N), grid(N)
+    H0 = torch.empty(3 * N ** 3, device="cuda")
+    M.pm_newton_potential(ctx, rho, phiN)
+    M.pm_net_forward(ctx, net, phiN, H0)
+    info_sep = M.aqual_solve(ctx, rho, phi_sep, H0=H0)
+    info_one = M.aqual_solve_learned(ctx, net, rho, phi_one)
+    assert torch.equal(phi_one, phi_sep)
+    assert info_one["residuals"] == info_sep["residuals"]
     net.close()
     ctx.close()
