@@ -64,33 +64,41 @@ def measured_traffic(kernel, workload):
     return t["kernels"][kernel]["bytes_per_launch"]
 
 
-_X_MODES = {0: "x_fwd_real", 1: "x_inv_real", 2: "x_nu", 3: "x_mu", 4: "x_nu"}
+_X_MODES = {0: "x_fwd_real", 1: "x_inv_real", 2: "x_nu", 3: "x_mu", 4: "x_nu_keep", 5: "x_lin_nu", 6: "x_lin_nu_keep",
+            7: "x_lin_mu", 8: "x_fwd_coarse3"}
 _Z_OPS = {0: "z_fwd", 1: "z_inv", 2: "z_newton", 3: "z_curl", 4: "z_curl_final", 5: "z_div", 6: "z_newton",
-          7: "z_poisson", 8: "z_newton", 9: "z_apparent"}
+          7: "z_poisson", 8: "z_newton", 9: "z_apparent", 10: "z_grad"}
 
 
 def timer_name(kernel):
     """The library's timer name for an FFT-pass kernel symbol as rocprofv3
-    prints it (the timers of the roofline record); other kernels keep their
-    base name."""
+    prints it (the timers of the roofline record); passes that read or write
+    FP16 spectra get the suffix "_h", torch's own kernels the prefix "torch:",
+    other kernels keep their base name."""
     import re
+    if "at::native::" in kernel:
+        m3 = re.search(r"at::native::([A-Za-z0-9_]+)", kernel)
+        return "torch:" + m3.group(1)
     m = re.search(r"(k_[a-z0-9_]+)<([^>]*)>", kernel)
     if not m:
         m2 = re.search(r"(k_[a-z0-9_]+|__amd_rocclr_[A-Za-z]+)", kernel)
         return m2.group(1) if m2 else kernel.split("(")[0].strip()
     base, args = m.group(1), [t.strip() for t in m.group(2).split(",")]
-    if base in ("k_ypass", "k_ypass_mfma"):
-        return "y_inv" if args[-1] == "true" else "y_fwd"
-    if base == "k_xpass_wave":              # <H, XMODE, NC>
-        mode, nc = int(args[1]), int(args[2])
-    elif base == "k_xpass":                 # <H, ROWS, NC, NT, XMODE>
-        mode, nc = int(args[4]), int(args[2])
-    elif base == "k_zpass":                 # <L, T, NT, HZ, ZOP>
-        return _Z_OPS.get(int(args[4]), base)
+    half = lambda name, io: name + "_h" if int(io) else name
+    if base == "k_ypass":                   # <L, T, NT, INV, IO>
+        return half("y_inv" if args[3] == "true" else "y_fwd", args[4])
+    if base == "k_ypass_mfma":              # <L, INV>
+        return "y_inv" if args[1] == "true" else "y_fwd"
+    if base == "k_xpass_wave":              # <H, XMODE, NC, IO>
+        mode, nc, io = int(args[1]), int(args[2]), args[3]
+    elif base == "k_xpass":                 # <H, ROWS, NC, NT, XMODE, IO>
+        mode, nc, io = int(args[4]), int(args[2]), args[5]
+    elif base == "k_zpass":                 # <L, T, NT, HZ, ZOP, IO>
+        return half(_Z_OPS.get(int(args[4]), base), args[5])
     else:
         return base
     name = _X_MODES.get(mode, base)
-    return name + "3" if name == "x_fwd_real" and nc == 3 else name
+    return half(name + "3" if name == "x_fwd_real" and nc == 3 else name, io)
 
 
 def _counter_means(path, counter, K=None):
