@@ -301,6 +301,7 @@ __global__ __launch_bounds__(kNT) void k_deposit_reduce(const int* __restrict__ 
 #pragma unroll
       for (int nb = 0; nb < 27; ++nb) sum += v[nb];
       for (int nb = 0; nb < 27; ++nb) {
+        if (sq0[nb] + 1 >= sq1[nb]) continue;        // at most one piece: added above
         const int dx = nb % 3 - 1, dy = (nb / 3) % 3 - 1, dz = nb / 9 - 1;
         const int lx = cx - dx * kTile + EXT, ly = cy - dy * kTile + EXT, lz = cz - dz * kTile + EXT;
         if (lx < 0 || lx >= TE || ly < 0 || ly >= TE || lz < 0 || lz >= TE) continue;
