@@ -258,12 +258,19 @@ __global__ __launch_bounds__(256) void k_compact(const int* __restrict__ flag, c
 }
 
 // Each listed tile: rho += the staged halo boxes of the pieces of its 27
-// neighbouring tiles, two cells per thread.  The first piece of every
+// neighbouring tiles, one cell per thread.  The first piece of every
 // neighbour is read at once (27 independent loads, those outside a
 // neighbour's box predicated off); further pieces of a neighbour (dense tiles
-// only) follow.  The order of the additions is fixed.
+// only) follow, eight loads in flight.  The order of the additions is fixed.
+// The owners of the densest tiles set the kernel's length, so a block keeps
+// as many of their loads in flight as it can.
+#ifndef PM_RED_NT
+#define PM_RED_NT 512
+#endif
+constexpr int kRedNT = PM_RED_NT;
+static_assert(512 % kRedNT == 0, "a reduce block covers the 512 cells of a tile");
 template <int EXT>
-__global__ __launch_bounds__(kNT) void k_deposit_reduce(const int* __restrict__ list, const int* __restrict__ nlist,
+__global__ __launch_bounds__(kRedNT) void k_deposit_reduce(const int* __restrict__ list, const int* __restrict__ nlist,
                                                         const int* __restrict__ pc_off, int nt, int N,
                                                         const float* __restrict__ stage, int cap, float* rho) {
   constexpr int TE = kTile + 2 * EXT;
@@ -283,8 +290,8 @@ __global__ __launch_bounds__(kNT) void k_deposit_reduce(const int* __restrict__ 
     }
     __syncthreads();
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int cell = threadIdx.x + h * kNT;       // 512 cells of the tile
+    for (int h = 0; h < 512 / kRedNT; ++h) {
+      const int cell = threadIdx.x + h * kRedNT;    // 512 cells of the tile
       const int cx = cell & 7, cy = (cell >> 3) & 7, cz = cell >> 6;
       float v[27];
       static_for<0, 27>([&](auto NBc) {
@@ -305,18 +312,17 @@ __global__ __launch_bounds__(kNT) void k_deposit_reduce(const int* __restrict__ 
         const int dx = nb % 3 - 1, dy = (nb / 3) % 3 - 1, dz = nb / 9 - 1;
         const int lx = cx - dx * kTile + EXT, ly = cy - dy * kTile + EXT, lz = cz - dz * kTile + EXT;
         if (lx < 0 || lx >= TE || ly < 0 || ly >= TE || lz < 0 || lz >= TE) continue;
-        // four independent loads in flight, summed in a fixed order
+        // eight independent loads in flight, summed in a fixed order
         const float* src = stage + (lz * TE + ly) * TE + lx;
-        float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+        float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        const int q1 = sq1[nb];
         int q = sq0[nb] + 1;
-        for (; q + 3 < sq1[nb]; q += 4) {
-          s0 += src[(size_t)q * TE3];
-          s1 += src[(size_t)(q + 1) * TE3];
-          s2 += src[(size_t)(q + 2) * TE3];
-          s3 += src[(size_t)(q + 3) * TE3];
+        for (; q + 7 < q1; q += 8) {
+#pragma unroll
+          for (int i = 0; i < 8; ++i) s[i] += src[(size_t)(q + i) * TE3];
         }
-        for (; q < sq1[nb]; ++q) s0 += src[(size_t)q * TE3];
-        sum += (s0 + s1) + (s2 + s3);
+        for (; q < q1; ++q) s[0] += src[(size_t)q * TE3];
+        sum += ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
       }
       if (sum != 0.0f) rho[g] = r0 + sum;
     }
@@ -485,7 +491,7 @@ hipError_t deposit_pieces(const KernelGeom& kg, const SortBufs& sb, const PieceB
                          sb.perm, sb.offsets, pb.pc_off, pb.ptile, sb.ntiles, kPiece, pb.counter, pos, mass, pb.stage,
                          pb.cap, rho);
       if ((e = hipGetLastError()) != hipSuccess) return e;
-      hipLaunchKernelGGL((k_deposit_reduce<3>), dim3(kPersistBlocks), dim3(kNT), 0, st, pb.list,
+      hipLaunchKernelGGL((k_deposit_reduce<3>), dim3(kPersistBlocks), dim3(kRedNT), 0, st, pb.list,
                          pb.list_off + sb.ntiles, pb.pc_off, nt, kg.N, pb.stage, pb.cap, rho);
       break;
     case 5:
@@ -493,7 +499,7 @@ hipError_t deposit_pieces(const KernelGeom& kg, const SortBufs& sb, const PieceB
                          sb.perm, sb.offsets, pb.pc_off, pb.ptile, sb.ntiles, kPiece, pb.counter, pos, mass, pb.stage,
                          pb.cap, rho);
       if ((e = hipGetLastError()) != hipSuccess) return e;
-      hipLaunchKernelGGL((k_deposit_reduce<5>), dim3(kPersistBlocks), dim3(kNT), 0, st, pb.list,
+      hipLaunchKernelGGL((k_deposit_reduce<5>), dim3(kPersistBlocks), dim3(kRedNT), 0, st, pb.list,
                          pb.list_off + sb.ntiles, pb.pc_off, nt, kg.N, pb.stage, pb.cap, rho);
       break;
     default:
