@@ -204,7 +204,7 @@ static void derive_sizes(pm_ctx* c, const pm_params* p, int64_t max_particles) {
     const int64_t mp = max_particles > 0 ? max_particles : 1;
     const int64_t most = max_pieces(ntiles, mp);
     const int64_t te = 8 + 2 * c->piece_ext;
-    const int64_t by_bytes = ((int64_t)512 << 20) / (te * te * te * 4);    // 512 MB of staging
+    const int64_t by_bytes = ((int64_t)1 << 30) / (te * te * te * 8);      // 1 GB of staging
     c->pb.cap = (int)(most < by_bytes ? most : by_bytes);
   }
 }
@@ -238,7 +238,8 @@ static size_t carve(pm_ctx* c, Carver& cv) {
     c->pb.list = cv.take<int>(ntiles);
     c->pb.ptile = cv.take<int>((size_t)max_pieces((int64_t)ntiles, (int64_t)mp));
     c->pb.counter = cv.take<int>(16);
-    c->pb.stage = cv.take<float>(piece_stage_floats(c->piece_ext, c->pb.cap));
+    c->pb.tmax = cv.take<unsigned>(ntiles);
+    c->pb.stage = cv.take<long long>(piece_stage_cells(c->piece_ext, c->pb.cap));
   }
   return (cv.off + 255) & ~(size_t)255;
 }

@@ -160,13 +160,15 @@ struct PieceBufs {
   int* list;        // [ntiles] tiles that receive staged cells
   int* ptile;       // [pieces] tile of each piece
   int* counter;     // [2] work counters of the deposit and the gather
-  float* stage;     // [cap][TE^3] staged halo boxes
+  unsigned* tmax;   // [ntiles] largest |m| of each tile's particles (float bits)
+  long long* stage; // [cap][TE^3] staged halo boxes: 64-bit fixed point at the tile's scale for tiles
+                    // of several pieces, else FP32 in the slot's first half
   int cap;
 };
 // most pieces a sort of n particles into ntiles tiles can make
 inline int64_t max_pieces(int64_t ntiles, int64_t n) { return (ntiles < n ? ntiles : n) + n / kPiece + 1; }
-// staging floats for cap pieces of a ball with the given extent
-size_t piece_stage_floats(int ext, int cap);
+// staging cells (64-bit) for cap pieces of a ball with the given extent
+size_t piece_stage_cells(int ext, int cap);
 hipError_t piece_plan(const PieceBufs& pb, const SortBufs& sb, int N, hipStream_t st);
 hipError_t deposit_pieces(const KernelGeom& kg, const SortBufs& sb, const PieceBufs& pb, const float* pos,
                           const float* mass, int64_t n, float* rho, hipStream_t st);

@@ -14,14 +14,17 @@
 // Work split.  After the tile sort (8^3-cell tiles), each tile's particles are
 // cut into pieces of at most kPiece; blocks take pieces from a work counter.
 //  - Deposit: a piece accumulates its balls in an LDS copy of the tile plus a
-//    halo of EXT cells, as exact 64-bit fixed-point sums (below), and stores
-//    the piece's halo box to a staging slot.  A
-//    second kernel gives every tile near matter one owner block, which adds
-//    the staged boxes of the 27 neighbouring tiles in a fixed order into rho,
-//    so no cell is written with global atomics and every staged sum is exact:
-//    the density does not depend on the order in which the particles arrive.
-//    Pieces beyond the staging capacity add their cells with FP32 global
-//    atomics.
+//    halo of EXT cells, as exact 64-bit fixed-point sums at its tile's scale
+//    (below), and stores the piece's halo box to a staging slot: as integers
+//    if the tile has several pieces, else as FP32 (one rounding of the exact
+//    sum).  A second kernel gives every tile near matter one owner block,
+//    which sums each of the 27 neighbouring tiles' staged boxes exactly
+//    (integers, at that neighbour's scale), converts the 27 sums and adds
+//    them in a fixed order into rho.  No cell is written with global atomics and no rounding
+//    depends on how a tile's particles fall into pieces, so the density does
+//    not depend on the order in which the particles arrive (the sort ranks
+//    them within a tile with atomics).  Pieces beyond the staging capacity
+//    add their cells with FP32 global atomics.
 //  - Gather: a piece loads its tile plus a halo of EXT + 1 cells of phi into
 //    LDS once; each lane then sums its particle's ball with the central
 //    difference folded into the weights, g = -(1/(2 s S)) sum_e phi(c + e) W(e)
@@ -39,7 +42,6 @@ namespace {
 constexpr int kTile = 8;
 constexpr int kNT = 256;
 constexpr int kWaves = kNT / 64;
-constexpr int kPieceBits = 32 - __builtin_clz((unsigned)kPiece - 1u);   // ceil(log2 kPiece)
 
 __device__ __forceinline__ int wrapi(int i, int N) { return i & (N - 1); }
 
@@ -122,12 +124,43 @@ __device__ __forceinline__ int next_piece(int* counter, int* slot) {
 // order of magnitude faster than LDS adds of FP32 on this chip (those take a
 // slow path), and integer sums are exact, so a piece accumulates its balls as
 // integers: each contribution c (FP32) becomes round(c 2^k) with one
-// power-of-two scale per piece chosen so that no cell sum can overflow, and
-// the cell's FP32 value is its integer sum times 2^-k.  The product of the
-// three normalised 1D weights is at most 1, so every contribution of
-// particle i is at most A_i = |m_i| / (S_i s^3) <= |m_i| / (w0 s^3), w0 being
-// the smallest possible central-cell weight; a cell sums at most kPiece
-// contributions per ball cell.
+// power-of-two scale per tile, shared by the tile's pieces, chosen so that
+// no cell sum over all the tile's particles can overflow; the cell's FP32
+// value is the integer sum times 2^-k.  The product of the three normalised
+// 1D weights is at most 1, so every contribution of particle i is at most
+// A_i = |m_i| / (S_i s^3) <= |m_i| / (w0 s^3), w0 being the smallest possible
+// central-cell weight; a tile of n_t particles adds at most n_t contributions
+// to a cell.  With A < 2^e for the tile's largest |m|, k = 61 - ceil(log2 n_t)
+// - e keeps every sum below 2^61.
+__device__ __forceinline__ int tile_scale_exp(const KernelGeom& kg, unsigned mbits, int count) {
+  const double s3 = (double)kg.s * kg.s * kg.s;
+  // the normalisation is at least the central cell's weight, whose offset is
+  // at most 1/2 cell per axis (or the analytic prefactor)
+  const double norm_lo = kg.analytic ? kg.analytic_norm : (double)expf(-0.75f * kg.inv2sig2);
+  const double A = (double)__uint_as_float(mbits) / (norm_lo * s3);
+  int e = 0;
+  frexp(A > 0.0 ? A : 1.0, &e);                   // A < 2^e
+  const int cb = count > 1 ? 32 - __clz(count - 1) : 0;      // ceil(log2 count)
+  return 61 - cb - e;
+}
+
+// Largest |m| of each tile's particles, tmax[t] (float bits; zeroed before),
+// from the pieces: a block reduces a piece and adds one atomic max per wave.
+__global__ __launch_bounds__(kNT) void k_tile_mass_max(const int* __restrict__ perm, const int* __restrict__ offsets,
+                                                      const int* __restrict__ pc_off, const int* __restrict__ ptile,
+                                                      int ntiles, int piece, const float* __restrict__ mass,
+                                                      unsigned* tmax) {
+  const int total = pc_off[ntiles];
+  for (int p = blockIdx.x; p < total; p += gridDim.x) {
+    const int t = ptile[p];
+    const int a = offsets[t] + (p - pc_off[t]) * piece;
+    const int b = min(a + piece, offsets[t + 1]);
+    float m = 0.0f;
+    for (int j = a + (int)threadIdx.x; j < b; j += kNT) m = fmaxf(m, fabsf(mass[perm[j]]));
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0 && m > 0.0f) atomicMax(&tmax[t], __float_as_uint(m));   // non-negative floats order as their bits
+  }
+}
 __device__ __forceinline__ unsigned long long to_fixed(float c, int k) {
   const float t = ldexpf(fabsf(c), k);                  // < 2^61 by the choice of k
   const unsigned hi = (unsigned)(t * 2.3283064365386963e-10f);   // t / 2^32, truncated
@@ -142,12 +175,12 @@ __global__ __launch_bounds__(kNT) void k_deposit_pieces(KernelGeom kg, const int
                                                         const int* __restrict__ pc_off,
                                                         const int* __restrict__ ptile, int ntiles, int piece,
                                                         int* counter, const float* __restrict__ pos,
-                                                        const float* __restrict__ mass, float* stage, int cap,
+                                                        const float* __restrict__ mass,
+                                                        const unsigned* __restrict__ tmax, long long* stage, int cap,
                                                         float* rho) {
   constexpr int TE = kTile + 2 * EXT;
   constexpr int TE3 = TE * TE * TE;
   extern __shared__ unsigned long long tile64[];   // TE^3 fixed-point cell sums
-  __shared__ unsigned mbits;                       // largest |m| of the piece (float bits)
   const int N = kg.N, nt = N / kTile;
   const double s3 = (double)kg.s * kg.s * kg.s;
   const int total = pc_off[ntiles];
@@ -162,21 +195,8 @@ __global__ __launch_bounds__(kNT) void k_deposit_pieces(KernelGeom kg, const int
     int k = 0;
     if (staged) {
       for (int j = threadIdx.x; j < TE3; j += kNT) tile64[j] = 0ull;
-      if (threadIdx.x == 0) mbits = 0u;
       __syncthreads();
-      float mloc = 0.0f;
-      for (int j = a + (int)threadIdx.x; j < b; j += kNT) mloc = fmaxf(mloc, fabsf(mass[perm[j]]));
-      atomicMax(&mbits, __float_as_uint(mloc));     // non-negative floats order as their bits
-      __syncthreads();
-      // A = max |m| / (w0 s^3) bounds every contribution; with 2^k A below
-      // 2^(61 - log2 kPiece), the kPiece contributions to a cell stay below 2^61
-      // the normalisation is at least the central cell's weight, whose offset
-      // is at most 1/2 cell per axis (or the analytic prefactor)
-      const double norm_lo = kg.analytic ? kg.analytic_norm : (double)expf(-0.75f * kg.inv2sig2);
-      const double A = (double)__uint_as_float(mbits) / (norm_lo * s3);
-      int e = 0;
-      frexp(A > 0.0 ? A : 1.0, &e);                 // A < 2^e
-      k = 61 - kPieceBits - e;
+      k = tile_scale_exp(kg, tmax[t], offsets[t + 1] - offsets[t]);
     }
     for (int j = a + (int)threadIdx.x; j < b; j += kNT) {
       const int64_t i = perm[j];
@@ -224,10 +244,15 @@ __global__ __launch_bounds__(kNT) void k_deposit_pieces(KernelGeom kg, const int
     }
     if (staged) {
       __syncthreads();
-      float* dst = stage + (size_t)p * TE3;
-      for (int j = threadIdx.x; j < TE3; j += kNT) {
-        const long long v = (long long)tile64[j];
-        dst[j] = (float)ldexp((double)v, -k);
+      // a tile of several pieces stages integers, summed exactly by the
+      // reduction; a lone piece's box is already its tile's exact sum and is
+      // staged as FP32 (the slot's first half), half the bytes
+      if (pc_off[t + 1] - pc_off[t] > 1) {
+        long long* dst = stage + (size_t)p * TE3;
+        for (int j = threadIdx.x; j < TE3; j += kNT) dst[j] = (long long)tile64[j];
+      } else {
+        float* dst = reinterpret_cast<float*>(stage + (size_t)p * TE3);
+        for (int j = threadIdx.x; j < TE3; j += kNT) dst[j] = (float)ldexp((double)(long long)tile64[j], -k);
       }
       __syncthreads();
     }
@@ -258,24 +283,29 @@ __global__ __launch_bounds__(256) void k_compact(const int* __restrict__ flag, c
 }
 
 // Each listed tile: rho += the staged halo boxes of the pieces of its 27
-// neighbouring tiles, one cell per thread.  The first piece of every
-// neighbour is read at once (27 independent loads, those outside a
-// neighbour's box predicated off); further pieces of a neighbour (dense tiles
-// only) follow, eight loads in flight.  The order of the additions is fixed.
-// The owners of the densest tiles set the kernel's length, so a block keeps
-// as many of their loads in flight as it can.
+// neighbouring tiles, one cell per thread.  A neighbour's pieces are summed
+// exactly as integers (a lone piece read with the others' at once, 27
+// independent loads with those outside a neighbour's box predicated off; the
+// pieces of a dense neighbour eight loads at a time), each neighbour's sum is
+// converted at its tile's scale, and the 27 values are added in a fixed
+// order.  The
+// owners of the densest tiles set the kernel's length, so a block keeps as
+// many of their loads in flight as it can.
 #ifndef PM_RED_NT
 #define PM_RED_NT 512
 #endif
 constexpr int kRedNT = PM_RED_NT;
 static_assert(512 % kRedNT == 0, "a reduce block covers the 512 cells of a tile");
 template <int EXT>
-__global__ __launch_bounds__(kRedNT) void k_deposit_reduce(const int* __restrict__ list, const int* __restrict__ nlist,
-                                                        const int* __restrict__ pc_off, int nt, int N,
-                                                        const float* __restrict__ stage, int cap, float* rho) {
+__global__ __launch_bounds__(kRedNT) void k_deposit_reduce(KernelGeom kg, const int* __restrict__ list,
+                                                           const int* __restrict__ nlist,
+                                                           const int* __restrict__ offsets,
+                                                           const int* __restrict__ pc_off,
+                                                           const unsigned* __restrict__ tmax, int nt, int N,
+                                                           const long long* __restrict__ stage, int cap, float* rho) {
   constexpr int TE = kTile + 2 * EXT;
   constexpr int TE3 = TE * TE * TE;
-  __shared__ int sq0[27], sq1[27];
+  __shared__ int sq0[27], sq1[27], sk[27], smulti[27];
   const int n = *nlist;
   for (int li = blockIdx.x; li < n; li += gridDim.x) {
     const int t = list[li];
@@ -287,6 +317,8 @@ __global__ __launch_bounds__(kRedNT) void k_deposit_reduce(const int* __restrict
       const int u = ((((tz + dz) + nt) % nt) * nt + ((ty + dy) + nt) % nt) * nt + ((tx + dx) + nt) % nt;
       sq0[nb] = pc_off[u];
       sq1[nb] = min(pc_off[u + 1], cap);
+      sk[nb] = tile_scale_exp(kg, tmax[u], offsets[u + 1] - offsets[u]);
+      smulti[nb] = pc_off[u + 1] - pc_off[u] > 1;   // staged as integers
     }
     __syncthreads();
 #pragma unroll
@@ -299,30 +331,36 @@ __global__ __launch_bounds__(kRedNT) void k_deposit_reduce(const int* __restrict
         constexpr int dx = nb % 3 - 1, dy = (nb / 3) % 3 - 1, dz = nb / 9 - 1;
         // this cell in the halo box of neighbour nb (origin at its corner minus EXT)
         const int lx = cx - dx * kTile + EXT, ly = cy - dy * kTile + EXT, lz = cz - dz * kTile + EXT;
-        const bool in = lx >= 0 && lx < TE && ly >= 0 && ly < TE && lz >= 0 && lz < TE && sq0[nb] < sq1[nb];
-        v[nb] = in ? stage[(size_t)sq0[nb] * TE3 + (lz * TE + ly) * TE + lx] : 0.0f;
+        const bool in = lx >= 0 && lx < TE && ly >= 0 && ly < TE && lz >= 0 && lz < TE && sq0[nb] < sq1[nb] &&
+                        !smulti[nb];
+        v[nb] = in ? reinterpret_cast<const float*>(stage + (size_t)sq0[nb] * TE3)[(lz * TE + ly) * TE + lx] : 0.0f;
       });
       const long long g = ((long long)(tz * kTile + cz) * N + (ty * kTile + cy)) * N + (tx * kTile + cx);
       const float r0 = rho[g];
+      // neighbours of one piece, from the loads above, in order; then those of
+      // several pieces, whose integer boxes are summed here.  Which neighbours
+      // have several pieces depends only on the tiles' particle counts, so the
+      // order of the additions is fixed.
       float sum = 0.0f;
 #pragma unroll
       for (int nb = 0; nb < 27; ++nb) sum += v[nb];
       for (int nb = 0; nb < 27; ++nb) {
-        if (sq0[nb] + 1 >= sq1[nb]) continue;        // at most one piece: added above
+        const int q1 = sq1[nb];
+        int q = sq0[nb];
+        if (!smulti[nb] || q >= q1) continue;
         const int dx = nb % 3 - 1, dy = (nb / 3) % 3 - 1, dz = nb / 9 - 1;
         const int lx = cx - dx * kTile + EXT, ly = cy - dy * kTile + EXT, lz = cz - dz * kTile + EXT;
         if (lx < 0 || lx >= TE || ly < 0 || ly >= TE || lz < 0 || lz >= TE) continue;
-        // eight independent loads in flight, summed in a fixed order
-        const float* src = stage + (lz * TE + ly) * TE + lx;
-        float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        const int q1 = sq1[nb];
-        int q = sq0[nb] + 1;
+        // eight independent loads in flight; integer sums are exact in any order
+        const long long* src = stage + (lz * TE + ly) * TE + lx;
+        long long a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         for (; q + 7 < q1; q += 8) {
 #pragma unroll
-          for (int i = 0; i < 8; ++i) s[i] += src[(size_t)(q + i) * TE3];
+          for (int i = 0; i < 8; ++i) a[i] += src[(size_t)(q + i) * TE3];
         }
-        for (; q < q1; ++q) s[0] += src[(size_t)q * TE3];
-        sum += ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+        for (; q < q1; ++q) a[0] += src[(size_t)q * TE3];
+        const long long tot = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+        sum += (float)ldexp((double)tot, -sk[nb]);
       }
       if (sum != 0.0f) rho[g] = r0 + sum;
     }
@@ -458,7 +496,7 @@ static constexpr size_t gather_lds() {
   return sizeof(float) * (size_t)TE * ((TE + 1) * TE + 1);
 }
 
-size_t piece_stage_floats(int ext, int cap) {
+size_t piece_stage_cells(int ext, int cap) {
   const size_t te = kTile + 2 * (size_t)ext;
   return (size_t)cap * te * te * te;
 }
@@ -485,22 +523,29 @@ hipError_t deposit_pieces(const KernelGeom& kg, const SortBufs& sb, const PieceB
   hipError_t e = fill_zero(reinterpret_cast<float*>(pb.counter), 1, st);
   if (e != hipSuccess) return e;
   const int nt = kg.N / kTile;
+  // the tiles' fixed-point scales: their largest |m|
+  if ((e = fill_zero(reinterpret_cast<float*>(pb.tmax), sb.ntiles, st)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_tile_mass_max, dim3(kPersistBlocks), dim3(kNT), 0, st, sb.perm, sb.offsets, pb.pc_off, pb.ptile,
+                     sb.ntiles, kPiece, mass, pb.tmax);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   switch (kg.piece_ext) {
     case 3:
       hipLaunchKernelGGL((k_deposit_pieces<3, 16>), dim3(kPersistBlocks), dim3(kNT), deposit_lds<3>(), st, kg,
-                         sb.perm, sb.offsets, pb.pc_off, pb.ptile, sb.ntiles, kPiece, pb.counter, pos, mass, pb.stage,
-                         pb.cap, rho);
+                         sb.perm, sb.offsets, pb.pc_off, pb.ptile, sb.ntiles, kPiece, pb.counter, pos, mass, pb.tmax,
+                         pb.stage, pb.cap, rho);
       if ((e = hipGetLastError()) != hipSuccess) return e;
-      hipLaunchKernelGGL((k_deposit_reduce<3>), dim3(kPersistBlocks), dim3(kRedNT), 0, st, pb.list,
-                         pb.list_off + sb.ntiles, pb.pc_off, nt, kg.N, pb.stage, pb.cap, rho);
+      hipLaunchKernelGGL((k_deposit_reduce<3>), dim3(kPersistBlocks), dim3(kRedNT), 0, st, kg, pb.list,
+                         pb.list_off + sb.ntiles, sb.offsets, pb.pc_off, pb.tmax, nt, kg.N, pb.stage, pb.cap,
+                         rho);
       break;
     case 5:
       hipLaunchKernelGGL((k_deposit_pieces<5, 36>), dim3(kPersistBlocks), dim3(kNT), deposit_lds<5>(), st, kg,
-                         sb.perm, sb.offsets, pb.pc_off, pb.ptile, sb.ntiles, kPiece, pb.counter, pos, mass, pb.stage,
-                         pb.cap, rho);
+                         sb.perm, sb.offsets, pb.pc_off, pb.ptile, sb.ntiles, kPiece, pb.counter, pos, mass, pb.tmax,
+                         pb.stage, pb.cap, rho);
       if ((e = hipGetLastError()) != hipSuccess) return e;
-      hipLaunchKernelGGL((k_deposit_reduce<5>), dim3(kPersistBlocks), dim3(kRedNT), 0, st, pb.list,
-                         pb.list_off + sb.ntiles, pb.pc_off, nt, kg.N, pb.stage, pb.cap, rho);
+      hipLaunchKernelGGL((k_deposit_reduce<5>), dim3(kPersistBlocks), dim3(kRedNT), 0, st, kg, pb.list,
+                         pb.list_off + sb.ntiles, sb.offsets, pb.pc_off, pb.tmax, nt, kg.N, pb.stage, pb.cap,
+                         rho);
       break;
     default:
       return hipErrorInvalidValue;

@@ -142,9 +142,10 @@ def test_deposit_512_sampled(M, iso):
     ref = _oracle_rho_at(oparams(p), iso["pos"].astype(np.float64), iso["mass"].astype(np.float64), cells)
     val = got[cells[:, 0], cells[:, 1], cells[:, 2]]
     scale = got.max()
-    # the central cells sum about 8000 FP32 contributions added in no fixed
-    # order (eps * sqrt(n) ~ 5e-6 of their value); measured up to 8.9e-7 of
-    # the maximum over the 200 densest cells in repeated runs
+    # the central cells sum about 8000 contributions, each computed in FP32
+    # (weights, normalisation and mass factor), then added exactly in fixed
+    # point and rounded to FP32 once per neighbouring tile; the bound is the
+    # one the earlier FP32 sums needed (eps * sqrt(n) ~ 5e-6 of the value)
     assert np.max(np.abs(val - ref)) < 3e-6 * scale
     ctx.close()
 

@@ -87,6 +87,8 @@ DEPOSIT_CASES = [
     ("cloud16", lambda: W.random_cloud(1, 16, 37, radius_frac=0.3)),
     ("cloud32_s1.5", lambda: W.random_cloud(2, 32, 1000, sigma=1.5, radius_frac=0.25)),
     ("dense32", lambda: W.random_cloud(3, 32, 5000, radius_frac=0.08)),     # LDS tile path
+    # tiles of about 7500 particles: several pieces per tile
+    ("pieces32", lambda: W.random_cloud(4, 32, 60000, radius_frac=0.12)),
     ("two_body", lambda: W.two_body()),
     ("ring_small", lambda: W.ring(seed=0, n_ring=300, radius=10.0, n=32, sigma=1.5)),
 ]
@@ -105,6 +107,29 @@ def test_deposit_parity(M, name, make):
     got = host(rho).reshape(N, N, N)
     assert rel_max(got, ref) < 1e-6
     assert abs(got.sum() - ref.sum()) <= 1e-6 * ref.sum()
+    ctx.close()
+
+
+@pytest.mark.parametrize("sigma", [1.0, 1.5])
+def test_deposit_independent_of_particle_order(M, sigma):
+    # Dense tiles are cut into several pieces, and which particles share a
+    # piece follows the sort's ranks, which are taken with atomics.  The
+    # density must not depend on it: the same input twice and a permuted
+    # input give the same bits.
+    _log("deposit order independence, sigma", sigma)
+    w = W.random_cloud(6, 32, 60000, radius_frac=0.12, sigma=sigma, mass_range=(0.1, 3.0))
+    p = w["params"]
+    N = p["n_pad"]
+    ctx = M.pm_create(p, len(w["mass"]))
+    rho = [grid(N) for _ in range(3)]
+    M.pm_deposit(ctx, dev(w["pos"]), dev(w["mass"]), rho[0])
+    M.pm_deposit(ctx, dev(w["pos"]), dev(w["mass"]), rho[1])
+    perm = np.random.default_rng(11).permutation(len(w["mass"]))
+    M.pm_deposit(ctx, dev(w["pos"][perm]), dev(w["mass"][perm]), rho[2])
+    torch.cuda.synchronize()
+    assert float(rho[0].max()) > 0.0
+    assert torch.equal(rho[0], rho[1])
+    assert torch.equal(rho[0], rho[2])
     ctx.close()
 
 
