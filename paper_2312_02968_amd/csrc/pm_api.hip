@@ -204,7 +204,7 @@ static void derive_sizes(pm_ctx* c, const pm_params* p, int64_t max_particles) {
     const int64_t mp = max_particles > 0 ? max_particles : 1;
     const int64_t most = max_pieces(ntiles, mp);
     const int64_t te = 8 + 2 * c->piece_ext;
-    const int64_t by_bytes = ((int64_t)1 << 30) / (te * te * te * 8);      // 1 GB of staging
+    const int64_t by_bytes = ((int64_t)2 << 30) / (te * te * te * 8);      // 2 GB of staging
     c->pb.cap = (int)(most < by_bytes ? most : by_bytes);
   }
 }

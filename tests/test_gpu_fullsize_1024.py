@@ -168,10 +168,10 @@ def test_deposit_1024_sampled(M, mix):
     assert abs(total - mix["mass"].astype(np.float64).sum()) < 1e-5 * mix["mass"].sum()
     ref = _oracle_rho_at(oparams(p), mix["pos"].astype(np.float64), mix["mass"].astype(np.float64), cells)
     # A dense cell here sums 1e4-1e5 contributions (particle mass 2^-24,
-    # central weight <= 0.063), each computed in FP32; pieces beyond the
-    # staging capacity add theirs with FP32 atomics in no fixed order, whose
-    # rounding error is about eps * sqrt(n) ~ 6e-8 * 150 ~ 1e-5 of the value
-    # (measured: up to 1.2e-6 of the maximum).
+    # central weight <= 0.063), each computed in FP32, added exactly in fixed
+    # point and rounded to FP32 once per neighbouring tile.  The bound is the
+    # one FP32 sums in no fixed order would need, eps * sqrt(n) ~ 6e-8 * 150
+    # ~ 1e-5 of the value (such sums measured up to 1.2e-6 of the maximum).
     assert np.max(np.abs(val - ref)) < 1e-5 * scale
 
 
