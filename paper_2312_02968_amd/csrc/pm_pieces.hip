@@ -41,7 +41,19 @@ namespace pm {
 namespace {
 constexpr int kTile = 8;
 constexpr int kNT = 256;
-constexpr int kWaves = kNT / 64;
+// Block sizes of the deposit's tile kernel and of the gather (a piece per
+// block).  Pieces average about 70 particles on the isothermal sphere, so
+// most of a block's lanes wait while the few with particles sum their balls;
+// 128-thread gather blocks keep twice as many pieces in flight per CU (the
+// gather 361 -> 320 us there), while the deposit's tile kernel, whose LDS
+// tile bounds its blocks per CU, is faster with 256 (266 against 295 us).
+#ifndef PM_DEPOSIT_NT
+#define PM_DEPOSIT_NT 256
+#endif
+#ifndef PM_GATHER_NT
+#define PM_GATHER_NT 128
+#endif
+constexpr int kDepNT = PM_DEPOSIT_NT, kGatNT = PM_GATHER_NT;
 
 __device__ __forceinline__ int wrapi(int i, int N) { return i & (N - 1); }
 
@@ -170,7 +182,7 @@ __device__ __forceinline__ unsigned long long to_fixed(float c, int k) {
 }
 
 template <int EXT, int R2>
-__global__ __launch_bounds__(kNT) void k_deposit_pieces(KernelGeom kg, const int* __restrict__ perm,
+__global__ __launch_bounds__(kDepNT) void k_deposit_pieces(KernelGeom kg, const int* __restrict__ perm,
                                                         const int* __restrict__ offsets,
                                                         const int* __restrict__ pc_off,
                                                         const int* __restrict__ ptile, int ntiles, int piece,
@@ -194,11 +206,11 @@ __global__ __launch_bounds__(kNT) void k_deposit_pieces(KernelGeom kg, const int
     const bool staged = p < cap;
     int k = 0;
     if (staged) {
-      for (int j = threadIdx.x; j < TE3; j += kNT) tile64[j] = 0ull;
+      for (int j = threadIdx.x; j < TE3; j += kDepNT) tile64[j] = 0ull;
       __syncthreads();
       k = tile_scale_exp(kg, tmax[t], offsets[t + 1] - offsets[t]);
     }
-    for (int j = a + (int)threadIdx.x; j < b; j += kNT) {
+    for (int j = a + (int)threadIdx.x; j < b; j += kDepNT) {
       const int64_t i = perm[j];
       Lane<EXT> L;
       lane_setup<EXT, R2>(L, kg, pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], !kg.analytic);
@@ -249,10 +261,10 @@ __global__ __launch_bounds__(kNT) void k_deposit_pieces(KernelGeom kg, const int
       // staged as FP32 (the slot's first half), half the bytes
       if (pc_off[t + 1] - pc_off[t] > 1) {
         long long* dst = stage + (size_t)p * TE3;
-        for (int j = threadIdx.x; j < TE3; j += kNT) dst[j] = (long long)tile64[j];
+        for (int j = threadIdx.x; j < TE3; j += kDepNT) dst[j] = (long long)tile64[j];
       } else {
         float* dst = reinterpret_cast<float*>(stage + (size_t)p * TE3);
-        for (int j = threadIdx.x; j < TE3; j += kNT) dst[j] = (float)ldexp((double)(long long)tile64[j], -k);
+        for (int j = threadIdx.x; j < TE3; j += kDepNT) dst[j] = (float)ldexp((double)(long long)tile64[j], -k);
       }
       __syncthreads();
     }
@@ -371,7 +383,7 @@ __global__ __launch_bounds__(kRedNT) void k_deposit_reduce(KernelGeom kg, const 
 // gather + push
 // ---------------------------------------------------------------------------
 template <int EXT, int R2>
-__global__ __launch_bounds__(kNT) void k_gather_pieces(KernelGeom kg, const int* __restrict__ perm,
+__global__ __launch_bounds__(kGatNT) void k_gather_pieces(KernelGeom kg, const int* __restrict__ perm,
                                                        const int* __restrict__ offsets,
                                                        const int* __restrict__ pc_off,
                                                        const int* __restrict__ ptile, int ntiles, int piece,
@@ -391,13 +403,13 @@ __global__ __launch_bounds__(kNT) void k_gather_pieces(KernelGeom kg, const int*
     const int b = min(a + piece, offsets[t + 1]);
     const int tx = t % nt, ty = (t / nt) % nt, tz = t / (nt * nt);
     const int ox = tx * kTile - HE, oy = ty * kTile - HE, oz = tz * kTile - HE;
-    for (int j = threadIdx.x; j < TE * TE * TE; j += kNT) {
+    for (int j = threadIdx.x; j < TE * TE * TE; j += kGatNT) {
       const int lx = j % TE, ly = (j / TE) % TE, lz = j / (TE * TE);
       tile[lz * PP + ly * RP + lx] =
           phi[((long long)wrapi(oz + lz, N) * N + wrapi(oy + ly, N)) * N + wrapi(ox + lx, N)];
     }
     __syncthreads();
-    for (int j = a + (int)threadIdx.x; j < b; j += kNT) {
+    for (int j = a + (int)threadIdx.x; j < b; j += kGatNT) {
       const int64_t i = perm[j];
       const float x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
       Lane<EXT> L;
@@ -530,7 +542,7 @@ hipError_t deposit_pieces(const KernelGeom& kg, const SortBufs& sb, const PieceB
   if ((e = hipGetLastError()) != hipSuccess) return e;
   switch (kg.piece_ext) {
     case 3:
-      hipLaunchKernelGGL((k_deposit_pieces<3, 16>), dim3(kPersistBlocks), dim3(kNT), deposit_lds<3>(), st, kg,
+      hipLaunchKernelGGL((k_deposit_pieces<3, 16>), dim3(kPersistBlocks), dim3(kDepNT), deposit_lds<3>(), st, kg,
                          sb.perm, sb.offsets, pb.pc_off, pb.ptile, sb.ntiles, kPiece, pb.counter, pos, mass, pb.tmax,
                          pb.stage, pb.cap, rho);
       if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -539,7 +551,7 @@ hipError_t deposit_pieces(const KernelGeom& kg, const SortBufs& sb, const PieceB
                          rho);
       break;
     case 5:
-      hipLaunchKernelGGL((k_deposit_pieces<5, 36>), dim3(kPersistBlocks), dim3(kNT), deposit_lds<5>(), st, kg,
+      hipLaunchKernelGGL((k_deposit_pieces<5, 36>), dim3(kPersistBlocks), dim3(kDepNT), deposit_lds<5>(), st, kg,
                          sb.perm, sb.offsets, pb.pc_off, pb.ptile, sb.ntiles, kPiece, pb.counter, pos, mass, pb.tmax,
                          pb.stage, pb.cap, rho);
       if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -561,12 +573,12 @@ hipError_t gather_pieces(const KernelGeom& kg, const SortBufs& sb, const PieceBu
   if (e != hipSuccess) return e;
   switch (kg.piece_ext) {
     case 3:
-      hipLaunchKernelGGL((k_gather_pieces<3, 16>), dim3(kPersistBlocks), dim3(kNT), gather_lds<3>(), st, kg,
+      hipLaunchKernelGGL((k_gather_pieces<3, 16>), dim3(kPersistBlocks), dim3(kGatNT), gather_lds<3>(), st, kg,
                          sb.perm, sb.offsets, pb.pc_off, pb.ptile, sb.ntiles, kPiece, pb.counter + 1, phi, pos, vel, acc,
                          dt_kick, dt_drift, mode);
       break;
     case 5:
-      hipLaunchKernelGGL((k_gather_pieces<5, 36>), dim3(kPersistBlocks), dim3(kNT), gather_lds<5>(), st, kg,
+      hipLaunchKernelGGL((k_gather_pieces<5, 36>), dim3(kPersistBlocks), dim3(kGatNT), gather_lds<5>(), st, kg,
                          sb.perm, sb.offsets, pb.pc_off, pb.ptile, sb.ntiles, kPiece, pb.counter + 1, phi, pos, vel, acc,
                          dt_kick, dt_drift, mode);
       break;
