@@ -140,8 +140,13 @@ pm_status pm_destroy(pm_ctx* ctx);
  * overwritten.  Each particle adds m_i w_id / s^3 to the cells c_i + d of its
  * ball (central pixel c_i = floor(x_i/s + 1/2) per axis), with w the Gaussian
  * weights normalised by their FP64 sum over the ball (or the literal prefactor
- * with PM_F_ANALYTIC_NORM).  Cell sums use atomic adds, so the rounding
- * order (and the last bits) vary from run to run.  N <= max_particles. */
+ * with PM_F_ANALYTIC_NORM).  For the balls of radius 4 sigma with sigma = 1
+ * or 1.5 cells, every cell is an exact fixed-point sum per 8^3 tile of
+ * particles, rounded to FP32 once per tile and added in a fixed order, so
+ * rho is the same bits for any order of the particles (as long as the tiles'
+ * pieces of at most 1024 particles fit the context's 2 GB of staging; pieces
+ * beyond it, and other balls, add their cells with FP32 atomics, whose last
+ * bits vary from run to run).  N <= max_particles. */
 pm_status pm_deposit(pm_ctx* ctx, const float* pos, const float* mass, int64_t N, float* rho);
 
 /* MOND potential phi from rho by the fixed-point iteration of Sect. 2.1:
@@ -160,9 +165,10 @@ pm_status aqual_solve(pm_ctx* ctx, const float* rho, const float* H0, float* phi
 
 /* pm_deposit for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
- * no context, no workspace, and no allocation of any kind.  Same result as
- * pm_deposit on a context with parameters p (rho: device float [n_pad^3],
- * overwritten; pos, mass as there), enqueued on stream (a hipStream_t, NULL
+ * no context, no workspace, and no allocation of any kind.  The density of
+ * pm_deposit on a context with parameters p up to FP32 rounding (its cell
+ * sums use atomic adds, whose last bits vary from run to run; rho: device
+ * float [n_pad^3], overwritten; pos, mass as there), enqueued on stream (a hipStream_t, NULL
  * = the default stream) without waiting.  Its scratch (the ball table and the
  * sort buffers, about 18 MB) is one fixed array per GPU that the library
  * holds until the process ends; every call on a GPU uses it, so calls that
