@@ -307,6 +307,10 @@ __global__ __launch_bounds__(256) void k_compact(const int* __restrict__ flag, c
 #define PM_RED_NT 512
 #endif
 constexpr int kRedNT = PM_RED_NT;
+#ifndef PM_RED_LOADS
+#define PM_RED_LOADS 8
+#endif
+constexpr int kRedLoads = PM_RED_LOADS;       // loads in flight per dense neighbour
 static_assert(512 % kRedNT == 0, "a reduce block covers the 512 cells of a tile");
 template <int EXT>
 __global__ __launch_bounds__(kRedNT) void k_deposit_reduce(KernelGeom kg, const int* __restrict__ list,
@@ -363,15 +367,19 @@ __global__ __launch_bounds__(kRedNT) void k_deposit_reduce(KernelGeom kg, const 
         const int dx = nb % 3 - 1, dy = (nb / 3) % 3 - 1, dz = nb / 9 - 1;
         const int lx = cx - dx * kTile + EXT, ly = cy - dy * kTile + EXT, lz = cz - dz * kTile + EXT;
         if (lx < 0 || lx >= TE || ly < 0 || ly >= TE || lz < 0 || lz >= TE) continue;
-        // eight independent loads in flight; integer sums are exact in any order
+        // kRedLoads independent loads in flight; integer sums are exact in any order
         const long long* src = stage + (lz * TE + ly) * TE + lx;
-        long long a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        for (; q + 7 < q1; q += 8) {
+        long long a[kRedLoads];
 #pragma unroll
-          for (int i = 0; i < 8; ++i) a[i] += src[(size_t)(q + i) * TE3];
+        for (int i = 0; i < kRedLoads; ++i) a[i] = 0;
+        for (; q + kRedLoads - 1 < q1; q += kRedLoads) {
+#pragma unroll
+          for (int i = 0; i < kRedLoads; ++i) a[i] += src[(size_t)(q + i) * TE3];
         }
         for (; q < q1; ++q) a[0] += src[(size_t)q * TE3];
-        const long long tot = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+        long long tot = 0;
+#pragma unroll
+        for (int i = 0; i < kRedLoads; ++i) tot += a[i];
         sum += (float)ldexp((double)tot, -sk[nb]);
       }
       if (sum != 0.0f) rho[g] = r0 + sum;
