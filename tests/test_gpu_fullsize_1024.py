@@ -175,6 +175,40 @@ def test_deposit_1024_sampled(M, mix):
     assert np.max(np.abs(val - ref)) < 1e-6 * scale
 
 
+@pytest.mark.timeout(600)
+def test_deposit_1024_beyond_staging(M):
+    # 2^20 particles spread over the whole 512^3 region make more tile pieces
+    # than the context's 2 GB of staging holds (97 826 halo boxes of 14^3
+    # 64-bit cells); the pieces beyond it add their cells with FP32 atomics
+    # while the others go through the exact reduction.  Both must give the
+    # Eq. smooth density.
+    _log("deposit 1024 beyond the staging capacity")
+    w = W.random_cloud(12, 512, 1 << 20, radius_frac=0.49)
+    p = w["params"]
+    assert p["n_pad"] == N
+    c = np.floor(w["pos"].astype(np.float64) / (p["box"] / p["n"]) + 0.5).astype(np.int64) + N // 2
+    t = c // 8
+    counts = np.bincount((t[:, 2] * (N // 8) + t[:, 1]) * (N // 8) + t[:, 0])
+    assert int(((counts + 1023) // 1024).sum()) > 97826
+    ctx = M.pm_create(p, len(w["mass"]))
+    rho = torch.zeros(N ** 3, dtype=torch.float32, device="cuda")
+    M.pm_deposit(ctx, _dev(w["pos"]), _dev(w["mass"]), rho)
+    total = float(rho.sum(dtype=torch.float64).item())
+    rng = np.random.default_rng(13)
+    # occupied cells all over the region (the staged and the atomic pieces
+    # lie in different parts of it), and random cells
+    occ = rng.choice(len(w["mass"]), 128, replace=False)
+    cells = np.concatenate([c[occ][:, ::-1], rng.integers(H - 250, H + 250, (32, 3))])
+    flat = torch.from_numpy((cells[:, 0] * N + cells[:, 1]) * N + cells[:, 2]).cuda()
+    val = rho[flat].double().cpu().numpy()
+    scale = float(rho.max().item())
+    ctx.close()
+    del rho
+    assert abs(total - w["mass"].astype(np.float64).sum()) < 1e-5 * w["mass"].sum()
+    ref = _oracle_rho_at(oparams(p), w["pos"].astype(np.float64), w["mass"].astype(np.float64), cells)
+    assert np.max(np.abs(val - ref)) < 1e-6 * scale
+
+
 @pytest.mark.timeout(300)
 def test_step_1024_runs_in_region(M, mix):
     _log("pm_step 1024, 2^24 particles")
