@@ -631,7 +631,10 @@ __device__ __forceinline__ void coarse_xyz(int64_t v, int n, int& X, int& Y, int
 }
 
 template <int FB>
-__global__ __launch_bounds__(NT) void k_feat_sumsq(const float* __restrict__ phi, int n, float inv_2s, double* part) {
+__global__ __launch_bounds__(NT) void k_feat_g(const float* __restrict__ phi, int n, float inv_2s, float* __restrict__ g3,
+                                               double* part) {
+  // the block means g_c of every voxel, kept as g3[c][v] for k_feat_write,
+  // and the FP64 partial sums of |g_c|^2 for the scale
   double acc[1] = {0.0};
   const int N = FB * n;
   const int64_t nvox = (int64_t)n * n * n;
@@ -640,26 +643,23 @@ __global__ __launch_bounds__(NT) void k_feat_sumsq(const float* __restrict__ phi
     coarse_xyz(v, n, X, Y, Z);
     float g[3];
     coarse_gN<FB>(phi, X, Y, Z, N, inv_2s, g);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) g3[c * nvox + v] = g[c];
     acc[0] += (double)g[0] * g[0] + (double)g[1] * g[1] + (double)g[2] * g[2];
   }
   block_reduce_store<1>(acc, part);
 }
 
-// x[v] = [g_c / rms, log10(|g_c| / a0 + 1e-30), 0 ...]
-template <int FB>
-__global__ __launch_bounds__(NT) void k_feat_write(const float* __restrict__ phi, int n, float inv_2s, float inv_a0,
+// x[v] = [g_c / rms, log10(|g_c| / a0 + 1e-30), 0 ...] from the block means
+// k_feat_g kept, so the full-resolution potential is read once
+__global__ __launch_bounds__(NT) void k_feat_write(const float* __restrict__ g3, int64_t nvox, float inv_a0,
                                                    const double* __restrict__ sumsq, double* rms_out,
                                                    bf16* __restrict__ x) {
-  const int N = FB * n;
-  const int64_t nvox = (int64_t)n * n * n;
   const double rms = sqrt(*sumsq / (double)nvox);
   const float scale = rms > 0.0 ? (float)(1.0 / rms) : 0.0f;
   if (blockIdx.x == 0 && threadIdx.x == 0) *rms_out = rms;
   for (int64_t v = blockIdx.x * (int64_t)NT + threadIdx.x; v < nvox; v += (int64_t)gridDim.x * NT) {
-    int X, Y, Z;
-    coarse_xyz(v, n, X, Y, Z);
-    float g[3];
-    coarse_gN<FB>(phi, X, Y, Z, N, inv_2s, g);
+    const float g[3] = {g3[v], g3[nvox + v], g3[2 * nvox + v]};
     const float mag = sqrtf(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
     uint4 o0 = make_uint4(0u, 0u, 0u, 0u), o1 = make_uint4(0u, 0u, 0u, 0u);
     bf16* e = reinterpret_cast<bf16*>(&o0);
@@ -955,19 +955,18 @@ hipError_t features(const Buffers& b, int slot, const float* phiN, double inv_2s
   const int64_t nvox = level_voxels(n, 0);
   const int nb = grid_for(nvox);
   if (nb > b.dpartial_count || (fb != 2 && fb != 4)) return hipErrorInvalidValue;
+  // the slot's block means wait in its part of a gradient scratch buffer
+  // (32 bytes per voxel, used only inside a backward pass)
+  float* g3 = reinterpret_cast<float*>(b.g16a + (int64_t)slot * nvox * 16);
   if (fb == 2)
-    hipLaunchKernelGGL(k_feat_sumsq<2>, dim3(nb), dim3(NT), 0, st, phiN, n, (float)inv_2s, b.dpartial);
+    hipLaunchKernelGGL(k_feat_g<2>, dim3(nb), dim3(NT), 0, st, phiN, n, (float)inv_2s, g3, b.dpartial);
   else
-    hipLaunchKernelGGL(k_feat_sumsq<4>, dim3(nb), dim3(NT), 0, st, phiN, n, (float)inv_2s, b.dpartial);
-  NETCHK(launched("k_feat_sumsq"));
+    hipLaunchKernelGGL(k_feat_g<4>, dim3(nb), dim3(NT), 0, st, phiN, n, (float)inv_2s, g3, b.dpartial);
+  NETCHK(launched("k_feat_g"));
   hipLaunchKernelGGL(k_reduce_d, dim3(1), dim3(NT), 0, st, b.dpartial, nb, 1, b.sums + slot);
   NETCHK(launched("k_reduce_d"));
-  if (fb == 2)
-    hipLaunchKernelGGL(k_feat_write<2>, dim3(nb), dim3(NT), 0, st, phiN, n, (float)inv_2s, (float)(1.0 / a0),
-                       b.sums + slot, b.rms + slot, b.x + (int64_t)slot * nvox * 16);
-  else
-    hipLaunchKernelGGL(k_feat_write<4>, dim3(nb), dim3(NT), 0, st, phiN, n, (float)inv_2s, (float)(1.0 / a0),
-                       b.sums + slot, b.rms + slot, b.x + (int64_t)slot * nvox * 16);
+  hipLaunchKernelGGL(k_feat_write, dim3(nb), dim3(NT), 0, st, g3, nvox, (float)(1.0 / a0), b.sums + slot,
+                     b.rms + slot, b.x + (int64_t)slot * nvox * 16);
   return launched("k_feat_write");
 }
 
