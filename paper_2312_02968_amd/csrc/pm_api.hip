@@ -461,8 +461,12 @@ static pm_status run_solve(pm_ctx* c, const float* rho, const float* H0, float* 
   }
   // learned start: the Newton potential for the network's features from the
   // spectrum just formed (a Poisson z pass into the work buffer, phiN kept),
-  // the network, and its coarse output expanded in the forward x pass in
-  // place of a full-resolution H0
+  // the network, and its coarse output in Fourier space: the coarse DFT
+  // (in the phi buffer, free once the features are formed) that the Newton z
+  // pass multiplies by the block sums, or (network sizes without the coarse
+  // transform) the output expanded in the forward x pass
+  bool coarse = false;
+  float2* cspec = reinterpret_cast<float2*>(c->phi);
   if (learned) {
     PassDesc z = pdesc(PASS_Z_POISSON, c->phiN);
     z.z = zargs(c);
@@ -477,10 +481,15 @@ static pm_status run_solve(pm_ctx* c, const float* rho, const float* H0, float* 
     const int fb = N / learned->n;
     HIPCHK(net::features(*learned, 0, c->phi, 0.5 / s_px, c->p.a0, fb, c->st));
     HIPCHK(net::forward(*learned, 1, c->st));
-    PassDesc d = pdesc(PASS_X_FWD_COARSE3, c->spec);
-    d.co = Coarse{learned->yhat, learned->rms, learned->n, fb};
-    HIPCHK(pass(c, d));
-    HIPCHK(pass(c, pdesc(PASS_Y_FWD, c->spec, 3)));
+    coarse = coarse_spectrum_supported(learned->n, N);
+    if (coarse) {
+      HIPCHK(coarse_spectrum(c->fg, learned->yhat, learned->rms, learned->n, cspec, c->st));
+    } else {
+      PassDesc d = pdesc(PASS_X_FWD_COARSE3, c->spec);
+      d.co = Coarse{learned->yhat, learned->rms, learned->n, fb};
+      HIPCHK(pass(c, d));
+      HIPCHK(pass(c, pdesc(PASS_Y_FWD, c->spec, 3)));
+    }
   }
   // warm start: F0 = P_L g_N + P_T F_prev from the last F of the previous solve
   const bool keep_F = !inc && (p.flags & PM_F_WARM_START) != 0;
@@ -510,7 +519,12 @@ static pm_status run_solve(pm_ctx* c, const float* rho, const float* H0, float* 
   {
     PassDesc d = pdesc(PASS_Z_NEWTON, c->spec);
     d.z = zargs(c);
-    d.z.with_h0 = warm ? 2 : ((start || learned) ? 1 : 0);
+    d.z.with_h0 = warm ? 2 : (coarse ? 3 : ((start || learned) ? 1 : 0));
+    if (coarse) {
+      d.z.cspec = cspec;
+      d.z.cn = learned->n;
+      d.z.cfb = N / learned->n;
+    }
     d.io = io ? 2 : 0;
     HIPCHK(pass(c, d));
     HIPCHK(reduce_partials(c->partials, z_blocks_io(N, d.io), c->dacc, c->st));

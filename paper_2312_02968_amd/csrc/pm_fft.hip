@@ -1083,8 +1083,16 @@ __global__ __launch_bounds__(256) void k_ypass_mfma(float2* spec, long long comp
   }
 }
 
+// B(k) = sum_{j < fb} w_L^(k j): the DFT along one axis of a block of fb
+// ones, from the transform's twiddle table (w_L^t at tw[t]).
+__device__ __forceinline__ float2 block_sum(const float2* tw, int k, int fb, int L) {
+  float2 b = make_float2(1.0f, 0.0f);
+  for (int j = 1; j < fb; ++j) b = cadd(b, tw[(k * j) & (L - 1)]);
+  return b;
+}
+
 enum { Z_FWD = 0, Z_INV = 1, Z_NEWTON = 2, Z_CURL = 3, Z_CURL_FINAL = 4, Z_DIV = 5, Z_NEWTON_H0 = 6, Z_POISSON = 7,
-       Z_NEWTON_WARM = 8, Z_APPARENT = 9, Z_GRAD = 10 };
+       Z_NEWTON_WARM = 8, Z_APPARENT = 9, Z_GRAD = 10, Z_NEWTON_COARSE = 11 };
 
 template <int ZOP> struct ZComp;
 template <> struct ZComp<Z_FWD>        { static constexpr int IN = 1, OUT = 1; };
@@ -1092,6 +1100,7 @@ template <> struct ZComp<Z_INV>        { static constexpr int IN = 1, OUT = 1; }
 template <> struct ZComp<Z_NEWTON>     { static constexpr int IN = 1, OUT = 3; };
 template <> struct ZComp<Z_NEWTON_H0>  { static constexpr int IN = 4, OUT = 3; };
 template <> struct ZComp<Z_NEWTON_WARM> { static constexpr int IN = 4, OUT = 3; };
+template <> struct ZComp<Z_NEWTON_COARSE> { static constexpr int IN = 1, OUT = 3; };
 template <> struct ZComp<Z_CURL>       { static constexpr int IN = 3, OUT = 3; };
 template <> struct ZComp<Z_CURL_FINAL> { static constexpr int IN = 3, OUT = 1; };
 template <> struct ZComp<Z_DIV>        { static constexpr int IN = 3, OUT = 3; };
@@ -1121,6 +1130,10 @@ template <> struct ZComp<Z_GRAD>       { static constexpr int IN = 1, OUT = 3; }
 //                 F = P_L g_N + P_T F_prev
 //   Z_GRAD      : g = -i kt phi_hat / N^3 (three output components), the field
 //                 of a potential as the curl-free projection forms it
+//   Z_NEWTON_COARSE: as Z_NEWTON_H0 with H0 constant on blocks of cfb^3 cells,
+//                 H0 = rms y(parent): its DFT is Y(kx mod cn, ky mod cn,
+//                 kz mod cn) B(kx) B(ky) B(kz), Y the coarse DFT (cspec) and
+//                 B(k) = sum_{j < cfb} w_N^(k j), so no full-resolution H0
 // IO as PassDesc::io; the half-precision forms read the forward y pass's
 // scales and write one scale per component of the block's 8 kx columns.
 template <int L, int T, int NT, int HZ, int ZOP, int IO = 0>
@@ -1175,7 +1188,7 @@ __global__ __launch_bounds__(NT) void k_zpass(ZArgs a, const float2* __restrict_
     for (int h = 0; h < HZ; ++h) nvs[HZ * c + h] = nvh[h];
 #pragma unroll
   for (int c = 0; c < NIN; ++c) {
-    const float2* p = (ZOP == Z_NEWTON || ZOP == Z_NEWTON_H0 || ZOP == Z_NEWTON_WARM)
+    const float2* p = (ZOP == Z_NEWTON || ZOP == Z_NEWTON_H0 || ZOP == Z_NEWTON_WARM || ZOP == Z_NEWTON_COARSE)
                           ? (c == 0 ? a.phiN + off : a.spec + (c - 1) * a.comp_stride + off)
                           : a.spec + c * a.comp_stride + off;
 #pragma unroll
@@ -1258,6 +1271,9 @@ __global__ __launch_bounds__(NT) void k_zpass(ZArgs a, const float2* __restrict_
       const float kx = a.kv[kxi < L ? kxi : 0];
       const float tx = (kxi < L / 2) ? a.kt[kxi] : 0.0f;
       const float kpx = (kxi < L / 2) ? a.kap[kxi] : 0.0f;
+      float2 bxy = make_float2(1.0f, 0.0f);          // coarse start: B(kx) B(ky)
+      if constexpr (ZOP == Z_NEWTON_COARSE)
+        bxy = cmul(block_sum(tw_s, kxi, a.cfb, L), block_sum(tw_s, y, a.cfb, L));
 #pragma unroll
       for (int r = 0; r < RL; ++r) {
         const int kz = j + r * (L / RL);
@@ -1285,7 +1301,7 @@ __global__ __launch_bounds__(NT) void k_zpass(ZArgs a, const float2* __restrict_
         float2* v0 = v + (0 * HZ + h) * E + e;
         float2* v1 = v + (1 * HZ + h) * E + e;
         float2* v2 = v + (2 * HZ + h) * E + e;
-        if (ZOP == Z_NEWTON || ZOP == Z_NEWTON_H0 || ZOP == Z_NEWTON_WARM) {
+        if (ZOP == Z_NEWTON || ZOP == Z_NEWTON_H0 || ZOP == Z_NEWTON_WARM || ZOP == Z_NEWTON_COARSE) {
           const float kzz = a.kv[kz];
           const float k2 = kx * kx + ky * ky + kzz * kzz;
           const float A = (k2 > 0.0f) ? hw_rcp(k2) : 0.0f;
@@ -1294,14 +1310,28 @@ __global__ __launch_bounds__(NT) void k_zpass(ZArgs a, const float2* __restrict_
           const float kpz = a.kap[kz];
           const float2 g = cscale(mul_mi<false>(ph), a.scale);
           float2 o0 = cscale(g, kpx), o1 = cscale(g, kapy), o2 = cscale(g, kpz);
-          if (ZOP == Z_NEWTON_H0 || ZOP == Z_NEWTON_WARM) {
+          if (ZOP == Z_NEWTON_H0 || ZOP == Z_NEWTON_WARM || ZOP == Z_NEWTON_COARSE) {
             // H0 (or F_prev) components arrived in input slots 1..3 (component c
-            // at slot HZ c + h); H starts at the divergence-free part of H0, or
-            // of F_prev - g_N: h - kt At (kt . h)
+            // at slot HZ c + h), or H0 comes from the coarse spectrum; H starts
+            // at the divergence-free part of H0, or of F_prev - g_N:
+            // h - kt At (kt . h)
             const float tz = a.kt[kz];
             const float t2 = tx * tx + ty * ty + tz * tz;
             const float At = (t2 > 0.0f) ? hw_rcp(t2) : 0.0f;
-            float2 h0 = v[(1 * HZ + h) * E + e], h1 = v[(2 * HZ + h) * E + e], h2 = v[(3 * HZ + h) * E + e];
+            float2 h0, h1, h2;
+            if constexpr (ZOP == Z_NEWTON_COARSE) {
+              const int m = a.cn - 1;
+              const long long cn3 = (long long)a.cn * a.cn * a.cn;
+              const long long ci = ((long long)(kz & m) * a.cn + (y & m)) * a.cn + (kxi & m);
+              const float2 bb = cmul(bxy, block_sum(tw_s, kz, a.cfb, L));
+              h0 = cmul(a.cspec[ci], bb);
+              h1 = cmul(a.cspec[cn3 + ci], bb);
+              h2 = cmul(a.cspec[2 * cn3 + ci], bb);
+            } else {
+              h0 = v[(1 * HZ + h) * E + e];
+              h1 = v[(2 * HZ + h) * E + e];
+              h2 = v[(3 * HZ + h) * E + e];
+            }
             if (ZOP == Z_NEWTON_WARM) {
               // o_c = g_N hat (already divided by N^3); bring F_prev to the same units
               const float rs = 1.0f / a.scale;
@@ -1352,7 +1382,7 @@ __global__ __launch_bounds__(NT) void k_zpass(ZArgs a, const float2* __restrict_
       }
     }
   }
-  if (ZOP == Z_NEWTON || ZOP == Z_NEWTON_H0 || ZOP == Z_NEWTON_WARM) {
+  if (ZOP == Z_NEWTON || ZOP == Z_NEWTON_H0 || ZOP == Z_NEWTON_WARM || ZOP == Z_NEWTON_COARSE) {
     __shared__ double red[NT / 64];
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
@@ -1542,6 +1572,14 @@ hipError_t run_pass(const FftGeom& g, const PassDesc& d, hipStream_t st) {
     case PASS_Z_NEWTON:
       if (d.io == 2) return launch_z<N, Z_NEWTON, 2>(g, d.z, st);
       if (d.z.with_h0 == 2) return launch_z<N, Z_NEWTON_WARM>(g, d.z, st);
+      if (d.z.with_h0 == 3) {
+        if constexpr (N <= 512) {
+          if (!d.z.cspec || d.z.cfb < 2 || d.z.cn * d.z.cfb != N) return hipErrorInvalidValue;
+          return launch_z<N, Z_NEWTON_COARSE>(g, d.z, st);
+        } else {
+          return hipErrorInvalidValue;
+        }
+      }
       return d.z.with_h0 ? launch_z<N, Z_NEWTON_H0>(g, d.z, st) : launch_z<N, Z_NEWTON>(g, d.z, st);
     case PASS_Z_CURL: return d.io == 1 ? launch_z<N, Z_CURL, 1>(g, d.z, st) : launch_z<N, Z_CURL>(g, d.z, st);
     case PASS_Z_CURL_FINAL:
@@ -1583,6 +1621,77 @@ hipError_t fft_pass(const FftGeom& g0, const PassDesc& d, hipStream_t st) {
     case 256: return run_pass<256>(g, d, st);
     case 512: return run_pass<512>(g, d, st);
     case 1024: return run_pass<1024>(g, d, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+// ----------------------------------------------------------------------------
+// The learned start's coarse field in Fourier space.  Pass AXIS transforms the
+// n-point sequences along that axis of every component in place: a block
+// holds S = 16 of them in LDS (X sequences as rows, Y and Z sequences as
+// columns of 16 consecutive X) and runs the block FFT with the box's twiddle
+// table (n divides N).  The X pass reads the real field y and scales it by
+// rms; the Y and Z passes work on the complex result.
+// ----------------------------------------------------------------------------
+namespace {
+constexpr int kCsS = 16;
+template <int L, int AXIS>
+__global__ __launch_bounds__(256) void k_coarse_spec(const float* __restrict__ y, const double* __restrict__ rms,
+                                                      float2* cs, const float2* __restrict__ tw, int twmul) {
+  extern __shared__ float2 lds[];
+  constexpr int S = kCsS, NT = 256;
+  constexpr int QS = AXIS == 0 ? L + 1 : 1, IS = AXIS == 0 ? 1 : S + 1;
+  constexpr int lines = L * (L / S);               // blocks per component
+  const int c = blockIdx.x / lines, rem = blockIdx.x % lines;
+  const int a = rem / (L / S), b0 = (rem % (L / S)) * S;
+  const long long n3 = (long long)L * L * L;
+  // element i of sequence q: X pass (Z = a, Y = b0 + q, X = i); Y pass
+  // (Z = a, Y = i, X = b0 + q); Z pass (Z = i, Y = a, X = b0 + q)
+  auto gidx = [&](int q, int i) -> long long {
+    if (AXIS == 0) return ((long long)a * L + b0 + q) * L + i;
+    if (AXIS == 1) return ((long long)a * L + i) * L + b0 + q;
+    return ((long long)i * L + a) * L + b0 + q;
+  };
+  const float r = (float)*rms;
+  for (int t = threadIdx.x; t < S * L; t += NT) {
+    const int q = AXIS == 0 ? t / L : t % S, i = AXIS == 0 ? t % L : t / S;
+    const long long gi = c * n3 + gidx(q, i);
+    lds[q * QS + i * IS] = AXIS == 0 ? make_float2(r * y[gi], 0.0f) : cs[gi];
+  }
+  __syncthreads();
+  block_fft<L, S, NT, AXIS != 0, false>(lds, QS, IS, tw, twmul);
+  for (int t = threadIdx.x; t < S * L; t += NT) {
+    const int q = AXIS == 0 ? t / L : t % S, i = AXIS == 0 ? t % L : t / S;
+    cs[c * n3 + gidx(q, i)] = lds[q * QS + i * IS];
+  }
+}
+
+template <int L>
+hipError_t coarse_spec_passes(const float2* tw, int N, const float* y, const double* rms, float2* cs,
+                              hipStream_t st) {
+  const dim3 grid(3 * L * (L / kCsS));
+  const size_t sh = sizeof(float2) * (size_t)(kCsS + 1) * (L + 1);
+  hipLaunchKernelGGL((k_coarse_spec<L, 0>), grid, dim3(256), sh, st, y, rms, cs, tw, N / L);
+  hipLaunchKernelGGL((k_coarse_spec<L, 1>), grid, dim3(256), sh, st, y, rms, cs, tw, N / L);
+  hipLaunchKernelGGL((k_coarse_spec<L, 2>), grid, dim3(256), sh, st, y, rms, cs, tw, N / L);
+  return hipGetLastError();
+}
+}  // namespace
+
+bool coarse_spectrum_supported(int n, int N) {
+  // (the coarse-start z pass is compiled for boxes up to 512^3; at 1024^3 its
+  // registers would spill, and the start is expanded in the x pass instead)
+  return n >= 16 && n <= 256 && (n & (n - 1)) == 0 && N <= 512 && N % n == 0 && N / n >= 2;
+}
+
+hipError_t coarse_spectrum(const FftGeom& g, const float* y, const double* rms, int n, float2* cs, hipStream_t st) {
+  if (!coarse_spectrum_supported(n, g.N)) return hipErrorInvalidValue;
+  switch (n) {
+    case 16: return coarse_spec_passes<16>(g.tw, g.N, y, rms, cs, st);
+    case 32: return coarse_spec_passes<32>(g.tw, g.N, y, rms, cs, st);
+    case 64: return coarse_spec_passes<64>(g.tw, g.N, y, rms, cs, st);
+    case 128: return coarse_spec_passes<128>(g.tw, g.N, y, rms, cs, st);
+    case 256: return coarse_spec_passes<256>(g.tw, g.N, y, rms, cs, st);
   }
   return hipErrorInvalidValue;
 }

@@ -49,9 +49,11 @@ struct ZArgs {
   const float* kap;
   float newton_coef;
   float scale;
-  int with_h0;     // 0: H = 0; 1: H0 given; 2: warm start from the previous F
+  int with_h0;     // 0: H = 0; 1: H0 given; 2: warm start from the previous F; 3: coarse start spectrum
   double* partials;
   int nc;
+  const float2* cspec = nullptr;   // with_h0 3: DFT of the coarse start [3][cn^3], cn = N / cfb
+  int cn = 0, cfb = 0;
 };
 
 enum PassKind {
@@ -102,6 +104,11 @@ struct PassDesc {
 };
 
 hipError_t fft_pass(const FftGeom& g, const PassDesc& d, hipStream_t st);
+// The learned start's coarse field in Fourier space: cs[c] = the unnormalised
+// DFT over the n^3 grid of rms * y[c] (y: [3][n^3], X fastest; cs complex, the
+// same layout), for n in 16..256 and boxes up to 512^3 (coarse_spectrum_supported).
+bool coarse_spectrum_supported(int n, int N);
+hipError_t coarse_spectrum(const FftGeom& g, const float* y, const double* rms, int n, float2* cs, hipStream_t st);
 hipError_t reduce_partials(const double* partials, int n, double* out, hipStream_t st, Gate gate = Gate{});
 // Tolerance mode on the device.  ctl[0]: 0 iterating, 1 converged in this
 // iteration (the final projection runs), 2 finished; ctl[1]: iterations done;

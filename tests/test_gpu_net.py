@@ -347,15 +347,21 @@ def test_learned_start_falls_back_to_the_zero_start(weights):
     ctx.close()
 
 
-@pytest.mark.parametrize("fb", [2, 4])
-def test_one_call_learned_solve_equals_the_separate_calls(fb):
+@pytest.mark.parametrize("n,fb", [(32, 2), (32, 4), (16, 4)])
+def test_one_call_learned_solve_equals_the_separate_calls(n, fb):
     # aqual_solve_learned forms the features from the solve's own Newton
-    # spectrum and expands the network's coarse output inside the first
-    # transform; pm_newton_potential, pm_net_forward and aqual_solve with the
-    # full-resolution H0 run the same arithmetic step by step
-    w = W.random_cloud(6, 32, 500, mu=W.MU_STANDARD)
+    # spectrum and brings the network's coarse output into Fourier space
+    # directly: the DFT of a start constant on fb^3 blocks is the coarse DFT
+    # times the blocks' own DFT, applied in the Newton z pass (network grids
+    # of 16 to 256 voxels per axis), or the coarse output is expanded inside
+    # the first transform (other sizes).  pm_newton_potential, pm_net_forward
+    # and aqual_solve with the full-resolution H0 run the same arithmetic
+    # step by step: bit for bit on the expanded path, to FP32 rounding on the
+    # spectral one (the two routes round the start's spectrum differently).
+    w = W.random_cloud(6, n, 500, mu=W.MU_STANDARD)
     p = dict(w["params"], iters=3, flags=M.PM_F_RESIDUAL)
     N = p["n_pad"]
+    spectral = N // fb >= 16
     v32, _ = gpu_params(7)
     ctx = M.pm_create(p, 500)
     rho = grid(N)
@@ -368,7 +374,11 @@ def test_one_call_learned_solve_equals_the_separate_calls(fb):
     M.pm_net_forward(ctx, net, phiN, H0)
     info_sep = M.aqual_solve(ctx, rho, phi_sep, H0=H0)
     info_one = M.aqual_solve_learned(ctx, net, rho, phi_one)
-    assert torch.equal(phi_one, phi_sep)
-    assert info_one["residuals"] == info_sep["residuals"]
+    if spectral:
+        assert rel_l2(host(phi_one), host(phi_sep)) < 1e-6
+        np.testing.assert_allclose(info_one["residuals"], info_sep["residuals"], rtol=1e-4)
+    else:
+        assert torch.equal(phi_one, phi_sep)
+        assert info_one["residuals"] == info_sep["residuals"]
     net.close()
     ctx.close()
