@@ -398,10 +398,14 @@ pm_status pm_net_forward(pm_ctx* ctx, pm_net* net, const float* phiN, float* H0)
 
 /* aqual_solve from the learned start in one call: the solve's own Newton
  * spectrum gives phi_N for the network's features (no second Newton solve),
- * the network runs on slot 0, and its coarse output enters the forward x
- * transform directly, each value expanded over its block (no
- * full-resolution H0 is written or read).  The same result as
- * pm_newton_potential, pm_net_forward and aqual_solve with that H0.  rho,
+ * the network runs on slot 0, and its coarse output enters in Fourier
+ * space: its own DFT times the DFT of a block of cells is the DFT of the
+ * start that repeats each value over its block, applied in the Newton pass
+ * (for networks of 16 to 256 voxels per axis in boxes up to 512^3; other
+ * sizes expand the output in the forward x transform).  No full-resolution
+ * H0 is written or read.  The result of pm_newton_potential, pm_net_forward
+ * and aqual_solve with that H0, to FP32 rounding (bit for bit on the
+ * expanded route).  rho,
  * phi: device float [n_pad^3] (phi is written and may not be the context's
  * internal grid); info and tol as in aqual_solve.  The network's slot 0 and
  * the context's internal potential grid are overwritten. */

@@ -205,8 +205,8 @@ def rejected(info):
 def learned_solve_tol(ctx, net, rho, phi):
     """The learned path in tolerance mode, with the plain iteration as the
     fallback: the solve from the learned start (aqual_solve_learned: features
-    from the solve's own Newton spectrum, network, coarse start expanded in the
-    first transform); if that solve is rejected, solve again from H = 0.
+    from the solve's own Newton spectrum, network, coarse start entering in
+    Fourier space); if that solve is rejected, solve again from H = 0.
     Returns (info, fell_back); the time of both solves counts against the
     learned start."""
     info = M.aqual_solve_learned(ctx, net, rho, phi)
