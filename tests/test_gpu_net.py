@@ -347,7 +347,7 @@ def test_learned_start_falls_back_to_the_zero_start(weights):
     ctx.close()
 
 
-@pytest.mark.parametrize("n,fb", [(32, 2), (32, 4), (16, 4)])
+@pytest.mark.parametrize("n,fb", [(32, 2), (32, 4), (16, 4), (128, 2), (256, 4)])
 def test_one_call_learned_solve_equals_the_separate_calls(n, fb):
     # aqual_solve_learned forms the features from the solve's own Newton
     # spectrum and brings the network's coarse output into Fourier space
