@@ -224,3 +224,25 @@ def test_net_input_and_start_field_at_quarter_resolution():
     assert H0.shape == (3, 16, 16, 16)
     assert np.allclose(H0[:, 5, 9, 14], rms * y[:, 1, 2, 3])
     assert np.allclose(ol.target(p, H0, rms, f=4), y)
+
+
+@pytest.mark.parametrize("f", [2, 4])
+def test_start_field_spectrum_is_coarse_spectrum_times_block_sums(f):
+    # The learned solve never forms the full-resolution start: it multiplies
+    # the coarse output's n^3-point DFT by the DFT of one block of f cells
+    # per axis.  For the start the oracle builds (each coarse value repeated
+    # over its f^3 block), DFT_N(H0)(k) = Y(k mod n) B(kx) B(ky) B(kz) with
+    # Y = DFT_n(rms y) and B(k) = sum_{j < f} exp(-2 pi i k j / N).
+    n = 4
+    N = f * n
+    rng = np.random.default_rng(21)
+    y = rng.standard_normal((3, n, n, n))
+    H0 = ol.start_field(None, y, 1.7, f)
+    assert H0.shape == (3, N, N, N)
+    Y = np.fft.fftn(1.7 * y, axes=(1, 2, 3))
+    k = np.arange(N)
+    B = np.exp(-2j * np.pi * np.outer(k, np.arange(f)) / N).sum(axis=1)
+    kz, ky, kx = np.meshgrid(k, k, k, indexing="ij")
+    want = Y[:, kz % n, ky % n, kx % n] * (B[kz] * B[ky] * B[kx])[None]
+    got = np.fft.fftn(H0, axes=(1, 2, 3))
+    assert np.max(np.abs(got - want)) < 1e-12 * np.max(np.abs(got))
