@@ -67,7 +67,7 @@ def measured_traffic(kernel, workload):
 _X_MODES = {0: "x_fwd_real", 1: "x_inv_real", 2: "x_nu", 3: "x_mu", 4: "x_nu_keep", 5: "x_lin_nu", 6: "x_lin_nu_keep",
             7: "x_lin_mu", 8: "x_fwd_coarse3"}
 _Z_OPS = {0: "z_fwd", 1: "z_inv", 2: "z_newton", 3: "z_curl", 4: "z_curl_final", 5: "z_div", 6: "z_newton",
-          7: "z_poisson", 8: "z_newton", 9: "z_apparent", 10: "z_grad", 11: "z_newton"}
+          7: "z_poisson", 8: "z_newton", 9: "z_apparent", 10: "z_grad", 11: "z_newton", 12: "z_poisson"}
 
 
 def timer_name(kernel):

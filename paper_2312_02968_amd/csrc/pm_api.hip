@@ -118,6 +118,7 @@ static int timer_of(PassKind k) {
     case PASS_Z_CURL_FINAL: return PM_T_Z_CURL_FINAL;
     case PASS_Z_DIV: return PM_T_Z_DIV;
     case PASS_Z_POISSON: return PM_T_Z_NEWTON;
+    case PASS_Z_POISSON_SPEC: return PM_T_Z_NEWTON;
     case PASS_Z_APPARENT: return PM_T_Z_FWD;
   }
   return PM_T_REDUCE;
@@ -459,29 +460,37 @@ static pm_status run_solve(pm_ctx* c, const float* rho, const float* H0, float* 
     HIPCHK(pass(c, d));
     HIPCHK(pass(c, pdesc(PASS_Y_FWD, c->phiN, 1)));
   }
-  // learned start: the Newton potential for the network's features from the
-  // spectrum just formed (a Poisson z pass into the work buffer, phiN kept),
-  // the network, and its coarse output in Fourier space: the coarse DFT
-  // (in the phi buffer, free once the features are formed) that the Newton z
-  // pass multiplies by the block sums, or (network sizes without the coarse
-  // transform) the output expanded in the forward x pass
+  // learned start: the network's features from the spectrum just formed, its
+  // forward pass, and its coarse output brought into the Newton z pass.  For
+  // the network sizes with coarse transforms, both ends stay in Fourier
+  // space: a Poisson z pass gives the Newton potential's full spectrum, whose
+  // aliases onto the network's grid are the block means of g_N (in the phi
+  // buffer as scratch), and the coarse output's own DFT, times the DFT of a
+  // block, is the start's spectrum that the Newton z pass takes.  Otherwise
+  // the potential goes to real space for the features (phiN kept) and the
+  // output is expanded in the forward x pass.
   bool coarse = false;
   float2* cspec = reinterpret_cast<float2*>(c->phi);
   if (learned) {
-    PassDesc z = pdesc(PASS_Z_POISSON, c->phiN);
+    const double s_px = c->p.box / c->p.n;
+    const int fb = N / learned->n;
+    coarse = coarse_spectrum_supported(learned->n, N);
+    PassDesc z = pdesc(coarse ? PASS_Z_POISSON_SPEC : PASS_Z_POISSON, c->phiN);
     z.z = zargs(c);
     z.z.spec = c->phiN;
     z.z.out = c->spec;
     HIPCHK(pass(c, z));
-    HIPCHK(pass(c, pdesc(PASS_Y_INV, c->spec, 1)));
-    PassDesc x = pdesc(PASS_X_INV_REAL, c->spec);
-    x.real = c->phi;
-    HIPCHK(pass(c, x));
-    const double s_px = c->p.box / c->p.n;
-    const int fb = N / learned->n;
-    HIPCHK(net::features(*learned, 0, c->phi, 0.5 / s_px, c->p.a0, fb, c->st));
+    if (coarse) {
+      HIPCHK(coarse_features(c->fg, c->spec, c->kap, learned->n, cspec, net::feature_means(*learned, 0), c->st));
+      HIPCHK(net::features_from_means(*learned, 0, c->p.a0, c->st));
+    } else {
+      HIPCHK(pass(c, pdesc(PASS_Y_INV, c->spec, 1)));
+      PassDesc x = pdesc(PASS_X_INV_REAL, c->spec);
+      x.real = c->phi;
+      HIPCHK(pass(c, x));
+      HIPCHK(net::features(*learned, 0, c->phi, 0.5 / s_px, c->p.a0, fb, c->st));
+    }
     HIPCHK(net::forward(*learned, 1, c->st));
-    coarse = coarse_spectrum_supported(learned->n, N);
     if (coarse) {
       HIPCHK(coarse_spectrum(c->fg, learned->yhat, learned->rms, learned->n, cspec, c->st));
     } else {

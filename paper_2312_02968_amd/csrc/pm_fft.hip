@@ -1092,7 +1092,7 @@ __device__ __forceinline__ float2 block_sum(const float2* tw, int k, int fb, int
 }
 
 enum { Z_FWD = 0, Z_INV = 1, Z_NEWTON = 2, Z_CURL = 3, Z_CURL_FINAL = 4, Z_DIV = 5, Z_NEWTON_H0 = 6, Z_POISSON = 7,
-       Z_NEWTON_WARM = 8, Z_APPARENT = 9, Z_GRAD = 10, Z_NEWTON_COARSE = 11 };
+       Z_NEWTON_WARM = 8, Z_APPARENT = 9, Z_GRAD = 10, Z_NEWTON_COARSE = 11, Z_POISSON_SPEC = 12 };
 
 template <int ZOP> struct ZComp;
 template <> struct ZComp<Z_FWD>        { static constexpr int IN = 1, OUT = 1; };
@@ -1101,6 +1101,7 @@ template <> struct ZComp<Z_NEWTON>     { static constexpr int IN = 1, OUT = 3; }
 template <> struct ZComp<Z_NEWTON_H0>  { static constexpr int IN = 4, OUT = 3; };
 template <> struct ZComp<Z_NEWTON_WARM> { static constexpr int IN = 4, OUT = 3; };
 template <> struct ZComp<Z_NEWTON_COARSE> { static constexpr int IN = 1, OUT = 3; };
+template <> struct ZComp<Z_POISSON_SPEC> { static constexpr int IN = 1, OUT = 1; };
 template <> struct ZComp<Z_CURL>       { static constexpr int IN = 3, OUT = 3; };
 template <> struct ZComp<Z_CURL_FINAL> { static constexpr int IN = 3, OUT = 1; };
 template <> struct ZComp<Z_DIV>        { static constexpr int IN = 3, OUT = 3; };
@@ -1130,6 +1131,8 @@ template <> struct ZComp<Z_GRAD>       { static constexpr int IN = 1, OUT = 3; }
 //                 F = P_L g_N + P_T F_prev
 //   Z_GRAD      : g = -i kt phi_hat / N^3 (three output components), the field
 //                 of a potential as the curl-free projection forms it
+//   Z_POISSON_SPEC: Z_POISSON without the inverse z transform: the Newton
+//                 potential's full spectrum (kx, ky, kz), normalised, to out
 //   Z_NEWTON_COARSE: as Z_NEWTON_H0 with H0 constant on blocks of cfb^3 cells,
 //                 H0 = rms y(parent): its DFT is Y(kx mod cn, ky mod cn,
 //                 kz mod cn) B(kx) B(ky) B(kz), Y the coarse DFT (cspec) and
@@ -1278,7 +1281,7 @@ __global__ __launch_bounds__(NT) void k_zpass(ZArgs a, const float2* __restrict_
       for (int r = 0; r < RL; ++r) {
         const int kz = j + r * (L / RL);
         const int e = u * RL + r;
-        if constexpr (ZOP == Z_POISSON) {
+        if constexpr (ZOP == Z_POISSON || ZOP == Z_POISSON_SPEC) {
           const float kzz = a.kv[kz];
           const float k2 = kx * kx + ky * ky + kzz * kzz;
           const float A = (k2 > 0.0f) ? hw_rcp(k2) : 0.0f;
@@ -1381,6 +1384,14 @@ __global__ __launch_bounds__(NT) void k_zpass(ZArgs a, const float2* __restrict_
         }
       }
     }
+  }
+  if constexpr (ZOP == Z_POISSON_SPEC) {
+    float2* ob = (a.out ? a.out : a.spec) + off;
+    float2* dsp[HZ];
+#pragma unroll
+    for (int h = 0; h < HZ; ++h) dsp[h] = ob + hoff(h);
+    store_cols<L, T, NT, Last::R, HZ>(v, E, dsp, nvs, row);
+    return;
   }
   if (ZOP == Z_NEWTON || ZOP == Z_NEWTON_H0 || ZOP == Z_NEWTON_WARM || ZOP == Z_NEWTON_COARSE) {
     __shared__ double red[NT / 64];
@@ -1586,6 +1597,7 @@ hipError_t run_pass(const FftGeom& g, const PassDesc& d, hipStream_t st) {
       return d.io == 3 ? launch_z<N, Z_CURL_FINAL, 3>(g, d.z, st) : launch_z<N, Z_CURL_FINAL>(g, d.z, st);
     case PASS_Z_DIV: return d.io == 1 ? launch_z<N, Z_DIV, 1>(g, d.z, st) : launch_z<N, Z_DIV>(g, d.z, st);
     case PASS_Z_POISSON: return launch_z<N, Z_POISSON>(g, d.z, st);
+    case PASS_Z_POISSON_SPEC: return launch_z<N, Z_POISSON_SPEC>(g, d.z, st);
     case PASS_Z_APPARENT: return launch_z<N, Z_APPARENT>(g, d.z, st);
     case PASS_Z_GRAD: return launch_z<N, Z_GRAD>(g, d.z, st);
   }
@@ -1635,9 +1647,12 @@ hipError_t fft_pass(const FftGeom& g0, const PassDesc& d, hipStream_t st) {
 // ----------------------------------------------------------------------------
 namespace {
 constexpr int kCsS = 16;
-template <int L, int AXIS>
+// INV: the inverse transform, whose last pass (AXIS 2) writes the real parts
+// to y instead (the block means of the features, real by construction).
+template <int L, int AXIS, bool INV = false>
 __global__ __launch_bounds__(256) void k_coarse_spec(const float* __restrict__ y, const double* __restrict__ rms,
-                                                      float2* cs, const float2* __restrict__ tw, int twmul) {
+                                                      float2* cs, const float2* __restrict__ tw, int twmul,
+                                                      float* yout = nullptr) {
   extern __shared__ float2 lds[];
   constexpr int S = kCsS, NT = 256;
   constexpr int QS = AXIS == 0 ? L + 1 : 1, IS = AXIS == 0 ? 1 : S + 1;
@@ -1652,18 +1667,85 @@ __global__ __launch_bounds__(256) void k_coarse_spec(const float* __restrict__ y
     if (AXIS == 1) return ((long long)a * L + i) * L + b0 + q;
     return ((long long)i * L + a) * L + b0 + q;
   };
-  const float r = (float)*rms;
+  const float r = INV ? 1.0f : (float)*rms;
   for (int t = threadIdx.x; t < S * L; t += NT) {
     const int q = AXIS == 0 ? t / L : t % S, i = AXIS == 0 ? t % L : t / S;
     const long long gi = c * n3 + gidx(q, i);
-    lds[q * QS + i * IS] = AXIS == 0 ? make_float2(r * y[gi], 0.0f) : cs[gi];
+    lds[q * QS + i * IS] = (AXIS == 0 && !INV) ? make_float2(r * y[gi], 0.0f) : cs[gi];
   }
   __syncthreads();
-  block_fft<L, S, NT, AXIS != 0, false>(lds, QS, IS, tw, twmul);
+  block_fft<L, S, NT, AXIS != 0, INV>(lds, QS, IS, tw, twmul);
   for (int t = threadIdx.x; t < S * L; t += NT) {
     const int q = AXIS == 0 ? t / L : t % S, i = AXIS == 0 ? t % L : t / S;
-    cs[c * n3 + gidx(q, i)] = lds[q * QS + i * IS];
+    if (INV && AXIS == 2) yout[c * n3 + gidx(q, i)] = lds[q * QS + i * IS].x;
+    else cs[c * n3 + gidx(q, i)] = lds[q * QS + i * IS];
   }
+}
+
+// Block means of g_N = -D phi_N over fb^3 blocks, in Fourier space: the mean
+// over the blocks of a field sampled on the n^3 grid has the DFT
+// Ghat(K) = (1/fb^3) sum over the fb^3 modes k = K mod n of
+// -i kappa(k) phi_hat(k) conj(B(kx) B(ky) B(kz)), with kappa the central-
+// difference symbol, phi_hat the normalised Newton spectrum in the kx half
+// layout [kx/16][kz][ky][kx mod 16] (modes with kx > N/2 from their
+// conjugates) and B(k) = sum_{j < fb} w_N^(k j).  One thread per coarse mode
+// with Kx <= n/2 (the field is real); for 0 < Kx < n/2 it also writes the
+// conjugate at -K, which no other thread writes.
+template <int FB>
+__global__ __launch_bounds__(256) void k_feat_spec(const float2* __restrict__ ph, const float* __restrict__ kap,
+                                                    const float2* __restrict__ tw, int N, int n, float2* cs) {
+  const int hx = n / 2 + 1;
+  const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (long long)hx * n * n) return;
+  const int Kx = (int)(t % hx), Ky = (int)((t / hx) % n), Kz = (int)(t / ((long long)hx * n));
+  const long long n3 = (long long)n * n * n;
+  float2 acc[3] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+#pragma unroll
+  for (int mz = 0; mz < FB; ++mz) {
+    const int kz = Kz + n * mz;
+    const float2 bz = block_sum(tw, kz, FB, N);
+#pragma unroll
+    for (int my = 0; my < FB; ++my) {
+      const int ky = Ky + n * my;
+      const float2 byz = cmul(block_sum(tw, ky, FB, N), bz);
+#pragma unroll
+      for (int mx = 0; mx < FB; ++mx) {
+        const int kx = Kx + n * mx;
+        float2 v;
+        if (kx <= N / 2) {
+          v = ph[((long long)((kx >> 4) * N + kz) * N + ky) * 16 + (kx & 15)];
+        } else {
+          const int cx = N - kx, cy = (N - ky) & (N - 1), cz = (N - kz) & (N - 1);
+          v = cconj(ph[((long long)((cx >> 4) * N + cz) * N + cy) * 16 + (cx & 15)]);
+        }
+        const float2 w = cmul(v, cconj(cmul(block_sum(tw, kx, FB, N), byz)));   // phi_hat conj(B)
+        const float2 mw = mul_mi<false>(w);                                      // -i phi_hat conj(B)
+        acc[0] = cadd(acc[0], cscale(mw, kap[kx]));
+        acc[1] = cadd(acc[1], cscale(mw, kap[ky]));
+        acc[2] = cadd(acc[2], cscale(mw, kap[kz]));
+      }
+    }
+  }
+  constexpr float inv = 1.0f / (FB * FB * FB);
+  const long long v0 = ((long long)Kz * n + Ky) * n + Kx;
+  const bool mirror = Kx > 0 && 2 * Kx < n;
+  const long long v1 = ((long long)((n - Kz) & (n - 1)) * n + ((n - Ky) & (n - 1))) * n + (n - Kx);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float2 r = cscale(acc[c], inv);
+    cs[c * n3 + v0] = r;
+    if (mirror) cs[c * n3 + v1] = cconj(r);
+  }
+}
+
+template <int L>
+hipError_t coarse_feat_passes(const float2* tw, int N, float2* cs, float* g3, hipStream_t st) {
+  const dim3 grid(3 * L * (L / kCsS));
+  const size_t sh = sizeof(float2) * (size_t)(kCsS + 1) * (L + 1);
+  hipLaunchKernelGGL((k_coarse_spec<L, 0, true>), grid, dim3(256), sh, st, nullptr, nullptr, cs, tw, N / L, nullptr);
+  hipLaunchKernelGGL((k_coarse_spec<L, 1, true>), grid, dim3(256), sh, st, nullptr, nullptr, cs, tw, N / L, nullptr);
+  hipLaunchKernelGGL((k_coarse_spec<L, 2, true>), grid, dim3(256), sh, st, nullptr, nullptr, cs, tw, N / L, g3);
+  return hipGetLastError();
 }
 
 template <int L>
@@ -1682,6 +1764,27 @@ bool coarse_spectrum_supported(int n, int N) {
   // (the coarse-start z pass is compiled for boxes up to 512^3; at 1024^3 its
   // registers would spill, and the start is expanded in the x pass instead)
   return n >= 16 && n <= 256 && (n & (n - 1)) == 0 && N <= 512 && N % n == 0 && N / n >= 2;
+}
+
+hipError_t coarse_features(const FftGeom& g, const float2* phihat, const float* kap, int n, float2* cs, float* g3,
+                           hipStream_t st) {
+  if (!coarse_spectrum_supported(n, g.N)) return hipErrorInvalidValue;
+  const int fb = g.N / n;
+  const long long modes = (long long)(n / 2 + 1) * n * n;
+  const dim3 grid((unsigned)((modes + 255) / 256));
+  if (fb == 2) hipLaunchKernelGGL((k_feat_spec<2>), grid, dim3(256), 0, st, phihat, kap, g.tw, g.N, n, cs);
+  else if (fb == 4) hipLaunchKernelGGL((k_feat_spec<4>), grid, dim3(256), 0, st, phihat, kap, g.tw, g.N, n, cs);
+  else return hipErrorInvalidValue;
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  switch (n) {
+    case 16: return coarse_feat_passes<16>(g.tw, g.N, cs, g3, st);
+    case 32: return coarse_feat_passes<32>(g.tw, g.N, cs, g3, st);
+    case 64: return coarse_feat_passes<64>(g.tw, g.N, cs, g3, st);
+    case 128: return coarse_feat_passes<128>(g.tw, g.N, cs, g3, st);
+    case 256: return coarse_feat_passes<256>(g.tw, g.N, cs, g3, st);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t coarse_spectrum(const FftGeom& g, const float* y, const double* rms, int n, float2* cs, hipStream_t st) {

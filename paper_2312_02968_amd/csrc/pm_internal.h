@@ -60,7 +60,7 @@ enum PassKind {
   PASS_X_FWD_REAL, PASS_X_FWD_REAL3, PASS_X_FWD_COARSE3, PASS_X_INV_REAL, PASS_X_INV_REAL3, PASS_X_NU, PASS_X_MU,
   PASS_X_LIN_NU, PASS_X_LIN_MU, PASS_Z_GRAD,
   PASS_Y_FWD, PASS_Y_INV,
-  PASS_Z_FWD, PASS_Z_INV, PASS_Z_NEWTON, PASS_Z_CURL, PASS_Z_CURL_FINAL, PASS_Z_DIV, PASS_Z_POISSON, PASS_Z_APPARENT
+  PASS_Z_FWD, PASS_Z_INV, PASS_Z_NEWTON, PASS_Z_CURL, PASS_Z_CURL_FINAL, PASS_Z_DIV, PASS_Z_POISSON, PASS_Z_APPARENT, PASS_Z_POISSON_SPEC
 };
 
 // Density of the external-field sheets per axis (Sect. 5: a pixel layer of
@@ -109,6 +109,12 @@ hipError_t fft_pass(const FftGeom& g, const PassDesc& d, hipStream_t st);
 // same layout), for n in 16..256 and boxes up to 512^3 (coarse_spectrum_supported).
 bool coarse_spectrum_supported(int n, int N);
 hipError_t coarse_spectrum(const FftGeom& g, const float* y, const double* rms, int n, float2* cs, hipStream_t st);
+// The network's features before normalisation, g3[c] = block means over
+// (N/n)^3 cells of g_N = -D phi_N, from the Newton potential's full spectrum
+// phihat (PASS_Z_POISSON_SPEC, normalised) and the central-difference symbol
+// kap; cs ([3][n^3] complex) is scratch.  Same sizes as coarse_spectrum.
+hipError_t coarse_features(const FftGeom& g, const float2* phihat, const float* kap, int n, float2* cs, float* g3,
+                           hipStream_t st);
 hipError_t reduce_partials(const double* partials, int n, double* out, hipStream_t st, Gate gate = Gate{});
 // Tolerance mode on the device.  ctl[0]: 0 iterating, 1 converged in this
 // iteration (the final projection runs), 2 finished; ctl[1]: iterations done;

@@ -71,6 +71,11 @@ hipError_t adam(const Buffers& b, float lr, float beta1, float beta2, float eps,
 // the channels [g_c / rms, log10(|g_c| / a0 + 1e-30)].
 // fb: box cells per network voxel along an axis (n_pad / n), 2 or 4
 hipError_t features(const Buffers& b, int slot, const float* phiN, double inv_2s, double a0, int fb, hipStream_t st);
+// The slot's block means g_c ([3][n^3] floats, kept in its part of a gradient
+// scratch buffer), and the slot's input from block means already written
+// there (the scale rms and the channels, as features forms them).
+float* feature_means(const Buffers& b, int slot);
+hipError_t features_from_means(const Buffers& b, int slot, double a0, hipStream_t st);
 // Training target of one slot: block mean of (F - g_N) / rms (F: [3][N^3]).
 hipError_t target_from_field(const Buffers& b, int slot, const float* phiN, const float* F, double inv_2s, int fb,
                              hipStream_t st);

@@ -672,6 +672,16 @@ __global__ __launch_bounds__(NT) void k_feat_write(const float* __restrict__ g3,
   }
 }
 
+// FP64 partial sums of |g_c|^2 over the block means g3[c][v]
+__global__ __launch_bounds__(NT) void k_sumsq3(const float* __restrict__ g3, int64_t nvox, double* part) {
+  double acc[1] = {0.0};
+  for (int64_t v = blockIdx.x * (int64_t)NT + threadIdx.x; v < nvox; v += (int64_t)gridDim.x * NT) {
+    const float g0 = g3[v], g1 = g3[nvox + v], g2 = g3[2 * nvox + v];
+    acc[0] += (double)g0 * g0 + (double)g1 * g1 + (double)g2 * g2;
+  }
+  block_reduce_store<1>(acc, part);
+}
+
 // target[c][v] = block mean of (F[c] - g_N[c]) = (F[c] + D_c phi_N), over rms
 template <int FB>
 __global__ __launch_bounds__(NT) void k_target(const float* __restrict__ phi, const float* __restrict__ F, int n,
@@ -950,14 +960,32 @@ hipError_t adam(const Buffers& b, float lr, float beta1, float beta2, float eps,
   return pack_weights(b, st);
 }
 
+// The slot's block means wait in its part of a gradient scratch buffer (32
+// bytes per voxel, used only inside a backward pass).
+float* feature_means(const Buffers& b, int slot) {
+  return reinterpret_cast<float*>(b.g16a + (int64_t)slot * level_voxels(b.n, 0) * 16);
+}
+
+hipError_t features_from_means(const Buffers& b, int slot, double a0, hipStream_t st) {
+  const int64_t nvox = level_voxels(b.n, 0);
+  const int nb = grid_for(nvox);
+  if (nb > b.dpartial_count) return hipErrorInvalidValue;
+  const float* g3 = feature_means(b, slot);
+  hipLaunchKernelGGL(k_sumsq3, dim3(nb), dim3(NT), 0, st, g3, nvox, b.dpartial);
+  NETCHK(launched("k_sumsq3"));
+  hipLaunchKernelGGL(k_reduce_d, dim3(1), dim3(NT), 0, st, b.dpartial, nb, 1, b.sums + slot);
+  NETCHK(launched("k_reduce_d"));
+  hipLaunchKernelGGL(k_feat_write, dim3(nb), dim3(NT), 0, st, g3, nvox, (float)(1.0 / a0), b.sums + slot,
+                     b.rms + slot, b.x + (int64_t)slot * nvox * 16);
+  return launched("k_feat_write");
+}
+
 hipError_t features(const Buffers& b, int slot, const float* phiN, double inv_2s, double a0, int fb, hipStream_t st) {
   const int n = b.n;
   const int64_t nvox = level_voxels(n, 0);
   const int nb = grid_for(nvox);
   if (nb > b.dpartial_count || (fb != 2 && fb != 4)) return hipErrorInvalidValue;
-  // the slot's block means wait in its part of a gradient scratch buffer
-  // (32 bytes per voxel, used only inside a backward pass)
-  float* g3 = reinterpret_cast<float*>(b.g16a + (int64_t)slot * nvox * 16);
+  float* g3 = feature_means(b, slot);
   if (fb == 2)
     hipLaunchKernelGGL(k_feat_g<2>, dim3(nb), dim3(NT), 0, st, phiN, n, (float)inv_2s, g3, b.dpartial);
   else
