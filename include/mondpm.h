@@ -397,15 +397,18 @@ pm_status pm_net_train_step(pm_net* net, int32_t batch, float lr, double* loss);
 pm_status pm_net_forward(pm_ctx* ctx, pm_net* net, const float* phiN, float* H0);
 
 /* aqual_solve from the learned start in one call: the solve's own Newton
- * spectrum gives phi_N for the network's features (no second Newton solve),
- * the network runs on slot 0, and its coarse output enters in Fourier
- * space: its own DFT times the DFT of a block of cells is the DFT of the
- * start that repeats each value over its block, applied in the Newton pass
- * (for networks of 16 to 256 voxels per axis in boxes up to 512^3; other
- * sizes expand the output in the forward x transform).  No full-resolution
- * H0 is written or read.  The result of pm_newton_potential, pm_net_forward
- * and aqual_solve with that H0, to FP32 rounding (bit for bit on the
- * expanded route).  rho,
+ * spectrum gives the network's features (no second Newton solve), the
+ * network runs on slot 0, and its coarse output enters the Newton pass.
+ * For networks of 16 to 256 voxels per axis in boxes up to 512^3 both stay
+ * in Fourier space: the features' block means are the Newton spectrum's
+ * aliases onto the network's grid, and the start's spectrum is the coarse
+ * output's DFT times the DFT of one block (no real phi_N, no
+ * full-resolution H0).  Other sizes form the features from the real
+ * potential and expand the output in the forward x transform.  The result
+ * of pm_newton_potential, pm_net_forward and aqual_solve with that H0: bit
+ * for bit on the real-space route; on the spectral one the network's input
+ * to one BF16 step where the FP32 rounding of the block means crosses a
+ * BF16 boundary.  rho,
  * phi: device float [n_pad^3] (phi is written and may not be the context's
  * internal grid); info and tol as in aqual_solve.  The network's slot 0 and
  * the context's internal potential grid are overwritten. */
