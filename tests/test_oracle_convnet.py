@@ -246,3 +246,31 @@ def test_start_field_spectrum_is_coarse_spectrum_times_block_sums(f):
     want = Y[:, kz % n, ky % n, kx % n] * (B[kz] * B[ky] * B[kx])[None]
     got = np.fft.fftn(H0, axes=(1, 2, 3))
     assert np.max(np.abs(got - want)) < 1e-12 * np.max(np.abs(got))
+
+
+@pytest.mark.parametrize("f", [2, 4])
+def test_feature_block_means_are_aliases_of_the_newton_spectrum(f):
+    # The learned solve forms the network's block means of g_N = -D phi_N
+    # without a real phi_N: their n^3-point DFT is
+    # (1/f^3) sum_{k = K mod n} -i kappa(k) phi_hat(k) conj(B(kx) B(ky) B(kz)),
+    # kappa the central-difference symbol sin(2 pi k / N) / s, phi_hat the
+    # normalised spectrum (phi = sum phi_hat e^{+ikx}) and B as for the start.
+    # Checked on the oracle's own Newton potential and block means.
+    p = pm.Params(n=8, n_pad=16, box=5.0)
+    N, n = p.n_pad, p.n_pad // f
+    rng = np.random.default_rng(31)
+    rho = np.zeros((N, N, N))
+    rho[4:12, 4:12, 4:12] = rng.uniform(0.0, 1.0, (8, 8, 8))
+    phiN, gN = pm.newton_potential(p, rho)
+    want = ol.coarse(gN, f)
+    ph = np.fft.fftn(phiN) / N ** 3
+    k = np.arange(N)
+    kap = np.sin(2 * np.pi * k / N) / p.s
+    B = np.exp(-2j * np.pi * np.outer(k, np.arange(f)) / N).sum(axis=1)
+    kz, ky, kx = np.meshgrid(k, k, k, indexing="ij")
+    w = ph * np.conj(B[kz] * B[ky] * B[kx]) / f ** 3
+    Y = np.zeros((3, n, n, n), complex)
+    for c, kc in enumerate((kx, ky, kz)):
+        np.add.at(Y[c], (kz % n, ky % n, kx % n), -1j * kap[kc] * w)
+    got = np.fft.ifftn(Y, axes=(1, 2, 3)).real * n ** 3
+    assert np.max(np.abs(got - want)) < 1e-12 * np.max(np.abs(want))
